@@ -1,0 +1,171 @@
+"""Benchmark of the lens-gradient hot path on one MI355X.
+
+Primary metric: pixel x potential grad+Hessian evaluations per second of the
+fused map kernel on the 2048^2-grid, 502-potential workload (FP64, five output
+planes), inputs resident in HBM, each step one lens_hessian_map call (the
+parameter prologue and the map kernel).  Secondary metrics in the same JSON
+line: FP32-evaluation maps, batched source-plane chi^2 samples/s (4096
+samples), the per-sample path on the same batch, the captured (HIP graph)
+batch, and image-plane chi^2 samples/s.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-chi2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic FP64 operations per (pixel, potential) evaluation of an
+# elliptical two-core dPIE with deflection and second derivatives, counted
+# from the closed forms (each +, -, *, /, sqrt, atan, atanh = 1)
+FLOPS_PER_EVAL = 103
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        fn()
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = [s.elapsed_time(e) * 1e-3 for s, e in zip(starts, ends)]
+    return wall, float(np.mean(ev))
+
+
+def cpu_baseline_map(c, budget_s=12.0):
+    """The oracle on a strip of rows of the same map (all potentials)."""
+    from oracle import oracle as O
+    pots = O.phys_to_pots(c["pots"])
+    f = O.dlsds(c["zl"], c["zs"])
+    nx, ny, x0, y0, dx, dy = c["grid"]
+    npot = len(pots["x0"])
+    rows = 2
+    while True:
+        g = (nx, rows, x0, y0, dx, dy)
+        t0 = time.perf_counter()
+        O.lens_map(pots, g, f, want_mag=False)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or rows >= ny:
+            break
+        rows = min(ny, max(rows * 2, int(rows * budget_s / max(dt, 1e-3) * 1.1)))
+    evals = nx * rows * npot
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=evals / dt, unit="pixel*potential evals/s", cores=threads, kind="oracle",
+                sample=f"{rows} of {ny} rows of the {nx}x{ny} grid, all {npot} potentials, "
+                       f"5 channels, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-chi2", action="store_true")
+    ap.add_argument("--only-map", action="store_true", help="primary map metric only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout "
+              "is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2004_06352_amd import binding as B
+    from paper_2004_06352_amd import inputs
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0, check=False)
+    c2 = inputs.config2()
+    f = B.dlsds(c2["zl"], c2["zs"])
+    phys = B.to_device(c2["pots"], B.PHYS_KEYS)
+    table = B.table_from_physical(phys, 0, ctx)
+    grid = c2["grid"]
+    nx, ny, npot = grid[0], grid[1], int(c2["pots"]["x0"].size)
+    out = {k: torch.empty((ny, nx), dtype=torch.float64, device="cuda")
+           for k in ("hxx", "hxy", "hyy", "ax", "ay")}
+
+    def step():
+        B.hessian_map(table, grid, f, B.FP64, ctx=ctx, out=out)
+
+    log(f"map {nx}x{ny} x {npot} potentials, FP64, steps={args.steps}")
+    wall, ev = timed_steps(step, args.steps, args.warmup, torch)
+    evals = nx * ny * npot
+    value = evals * args.steps / wall
+    ms = wall / args.steps * 1e3
+    achieved = FLOPS_PER_EVAL * evals / ev / 1e12
+    rec = {
+        "metric": "pixel*potential grad+Hessian evals/s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": c2["name"], "grid": [nx, ny], "potentials": npot,
+                   "channels": 5, "precision": "fp64"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "map_kernel<fp64, grad+hess>", "flops_per_eval": FLOPS_PER_EVAL,
+                     "avg_launch_ms": ev * 1e3},
+    }
+    secondary = {}
+    # FP32 evaluation with FP64 accumulation and compensated FP32
+    for name, prec in (("fp32_acc64", B.FP32_ACC64), ("fp32_comp32", B.FP32_COMP32)):
+        o32 = {k: torch.empty((ny, nx), dtype=torch.float32, device="cuda") for k in out}
+        w32, e32 = timed_steps(lambda: B.hessian_map(table, grid, f, prec, ctx=ctx, out=o32),
+                               max(3, args.steps // 2), 1, torch)
+        n = max(3, args.steps // 2)
+        secondary[f"map_{name}_evals_per_s"] = evals * n / w32
+        secondary[f"map_{name}_avg_launch_ms"] = e32 * 1e3
+        del o32
+    if not args.no_chi2 and not args.only_map:
+        c3 = inputs.config3()
+        cat = B.catalog_to_device(B.catalog_with_dlsds(c3["catalog"], c3["zl"]))
+        fixed = B.table_from_physical(B.to_device(c3["fixed"], B.PHYS_KEYS), 0, ctx)
+        free = B.table_from_physical(B.to_device(c3["free"], B.PHYS_KEYS), 0, ctx)
+        off = torch.as_tensor(c3["free_off"], dtype=torch.int32, device="cuda")
+        S = int(off.numel()) - 1
+        for name, path in (("batched", B.PATH_BATCHED), ("per_sample", B.PATH_PER_SAMPLE)):
+            n = 10 if path == B.PATH_BATCHED else 3
+            w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=path, ctx=ctx),
+                               n, 1, torch)
+            secondary[f"chi2_source_{name}_samples_per_s"] = S * n / w
+        plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx)
+        w, e = timed_steps(plan.launch, 20, 2, torch)
+        secondary["chi2_source_graph_samples_per_s"] = S * 20 / w
+        secondary["chi2_source_workload"] = c3["name"]
+        plan.close()
+    rec["secondary"] = secondary
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        rec["cpu_baseline"] = cpu_baseline_map(c2)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

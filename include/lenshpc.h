@@ -1,0 +1,285 @@
+/*
+ * lenshpc.h -- C ABI of the MI355X (gfx950) lens-gradient library.
+ *
+ * The library computes the data-parallel hot path of Lenstool-HPC
+ * (Schaefer, Fourestey & Kneib, arXiv:2004.06352):
+ *   - the deflection map alpha = grad psi, summed over every parametric
+ *     potential at every grid point (Sec. 4.1, Eq. (10));
+ *   - the second derivatives psi_xx, psi_xy, psi_yy at every grid point, the
+ *     input of the kappa, gamma and mu maps (Sec. 2.4, Eqs. (7)-(9));
+ *   - the chi^2 of many model samples, in the source plane (unlens, take the
+ *     barycentre, Sec. 2.2, Fig. 3, Eq. (6)) or in the image plane by
+ *     brute-force inversion of a triangulated grid (Sec. 2.3, Fig. 4;
+ *     Sec. 4.2, Fig. 7).
+ *
+ * Mass model.  Every potential is a dPIE (Eliasdottir et al. 2007, the
+ * reference the paper gives for its sub-halo parameters, Sec. 2.2): the
+ * difference of two cored isothermal ellipsoids with core radius rcore and cut
+ * radius rcut, convergence
+ *     kappa = (b0/2) F [1/sqrt(rcore^2 + rho^2) - 1/sqrt(rcut^2 + rho^2)],
+ *     F = rcut/(rcut - rcore),  rho^2 = x'^2/(1+eps)^2 + y'^2/(1-eps)^2,
+ * in the frame (x', y') rotated by the position angle phi.  rcut = +inf gives
+ * the cored isothermal ellipsoid; eps = 0, rcore = 0, rcut = +inf gives the
+ * singular isothermal sphere, whose deflection has modulus b0 everywhere.
+ * A potential with rcore = 0 contributes exactly zero at its own centre.
+ *
+ * Units: positions and radii in arcsec, angles in radians (counter-clockwise
+ * from +x), b0 in arcsec at Dls/Ds = 1.  Deflections come out in arcsec,
+ * second derivatives dimensionless; every map is multiplied by the Dls/Ds
+ * (`dlsds`) passed with it.
+ *
+ * Layout.  Tables are structures of arrays: one array per parameter, entry k
+ * of each array describes potential k.  Maps are row-major planes [ny][nx],
+ * one plane per channel; grid point (i, j) is (x0 + i dx, y0 + j dy) and sits
+ * at index j*nx + i.
+ *
+ * Memory.  Unless stated otherwise every array pointer is a DEVICE pointer on
+ * the context's device, owned by the caller, and must stay valid until the
+ * stream has passed the call.  The library owns only its context scratch
+ * (derived tables, cached deflections, image slots, work queues), allocated on
+ * demand up to the context's scratch limit and freed by lens_ctx_destroy.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Compute calls
+ * are asynchronous on it, except that a context created with
+ * LENS_CTX_CHECK_TABLES validates device-resident table contents before
+ * launching and therefore synchronises `stream` once per call.
+ *
+ * Errors.  Functions return LENS_OK (0) or a negative status; a thread-local
+ * message is available from lens_last_error().  An argument error is detected
+ * before anything is launched and leaves every output untouched.  Device-side
+ * content errors (a potential with eps outside [0, 1), rcore < 0,
+ * rcore >= rcut, b0 < 0 or a NaN) are reported synchronously as LENS_EINVAL in
+ * checked contexts; in unchecked contexts the affected outputs become NaN and
+ * lens_ctx_status() reports LENS_EINVAL after the stream has passed the call.
+ * Faults of the device runtime surface as LENS_EDEVICE.
+ *
+ * Threads.  A context may be used by one host thread at a time; several
+ * contexts may share a device.  A context's scratch is reused by every call
+ * on it, so calls on one context must not overlap on the device: give each
+ * concurrently used stream its own context.
+ *
+ * Bounds.  Before launching, every device array argument is checked against
+ * the allocation it lies in (hipMemGetAddressRange): an array that does not
+ * fit is LENS_EINVAL.  Offsets read by kernels are clamped to the declared
+ * sizes, so inconsistent offset contents cannot address outside the arrays.
+ */
+#ifndef LENSHPC_H
+#define LENSHPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LENSHPC_ABI_VERSION 1
+
+typedef int32_t lens_status_t;
+#define LENS_OK 0
+#define LENS_EINVAL (-1)       /* invalid argument or table content */
+#define LENS_ENOMEM (-2)       /* device memory or the scratch limit exhausted */
+#define LENS_EDEVICE (-3)      /* HIP runtime error or device fault */
+#define LENS_EOVERFLOW (-4)    /* image slots overflowed (counts stay exact) */
+#define LENS_EUNSUPPORTED (-5) /* valid request this build does not provide */
+
+/* Evaluation precision of the map and chi^2 kernels.
+ *   LENS_FP64        every step in FP64; FP64 outputs.
+ *   LENS_FP32_ACC64  pixel offsets and rotation in FP64, each potential's
+ *                    terms in FP32, the sum over potentials in FP64; maps are
+ *                    stored as FP32, chi^2 as FP64.
+ *   LENS_FP32_COMP32 as LENS_FP32_ACC64 but the sum over potentials is a
+ *                    compensated (Neumaier) FP32 sum. */
+typedef int32_t lens_precision_t;
+#define LENS_FP64 0
+#define LENS_FP32_ACC64 1
+#define LENS_FP32_COMP32 2
+
+typedef int32_t lens_chi2_mode_t;
+#define LENS_CHI2_SOURCE 0 /* source-plane: scatter of unlensed images (Sec. 2.2) */
+#define LENS_CHI2_IMAGE 1  /* image-plane: grid inversion + assignment (Sec. 2.3, 4.2) */
+
+/* How lens_chi2_batch issues its work (the result does not depend on it).
+ *   LENS_CHI2_PATH_PER_SAMPLE  one kernel launch per sample (reference path)
+ *   LENS_CHI2_PATH_BATCHED     persistent kernels pulling samples from a
+ *                              device work queue, a few launches per batch */
+typedef int32_t lens_chi2_path_t;
+#define LENS_CHI2_PATH_BATCHED 0
+#define LENS_CHI2_PATH_PER_SAMPLE 1
+
+/* Context flags */
+#define LENS_CTX_CHECK_TABLES 1u /* validate table contents before each launch */
+
+typedef struct lens_ctx lens_ctx_t;        /* opaque */
+typedef struct lens_chi2_plan lens_chi2_plan_t; /* opaque */
+
+/* Potential table in amplitude form; n entries; device arrays. */
+typedef struct {
+    int32_t n;
+    const double *x0, *y0; /* centre [arcsec] */
+    const double *b0;      /* amplitude at Dls/Ds = 1 [arcsec], >= 0 */
+    const double *eps;     /* Kassiola-Kovner ellipticity (a-b)/(a+b), 0 <= eps < 1 */
+    const double *phi;     /* position angle [rad] */
+    const double *rcore;   /* core radius [arcsec], >= 0 */
+    const double *rcut;    /* cut radius [arcsec], > rcore, may be +inf */
+} lens_pot_table_t;
+
+/* Potential table in physical form (Sec. 2.2: centre, velocity dispersion,
+ * ellipticity, orientation, profile radii); n entries; device arrays. */
+typedef struct {
+    int32_t n;
+    const double *x0, *y0; /* centre [arcsec] */
+    const double *sigma;   /* velocity dispersion [km/s], >= 0 */
+    const double *e;       /* ellipticity (a^2-b^2)/(a^2+b^2), 0 <= e < 1 */
+    const double *phi;     /* position angle [rad] */
+    const double *rcore, *rcut; /* [arcsec] */
+} lens_phys_table_t;
+
+/* Rectangular image-plane grid (Sec. 2.4: one point per image pixel). */
+typedef struct {
+    int32_t nx, ny;   /* >= 1 each */
+    double x0, y0;    /* coordinates of point (0, 0) [arcsec] */
+    double dx, dy;    /* spacing [arcsec], > 0 */
+} lens_grid_t;
+
+/* A batch of model samples for chi^2 (one MCMC proposal per sample).  Model
+ * m is the fixed table followed by free entries free_offset[m] ..
+ * free_offset[m+1]-1, summed in that order.  Samples may differ in size. */
+typedef struct {
+    int32_t n_samples;          /* >= 0 */
+    const int32_t *free_offset; /* device [n_samples+1], non-decreasing, [0] = 0 */
+    lens_pot_table_t free;      /* concatenated free potentials of all samples */
+    lens_pot_table_t fixed;     /* shared by every sample (n may be 0) */
+} lens_model_batch_t;
+
+/* Constraint catalogue (Eq. (6)): n_sys multiple-image systems; images of
+ * system i are img_offset[i] .. img_offset[i+1]-1. */
+typedef struct {
+    int32_t n_sys;             /* >= 1 */
+    int32_t n_img;             /* total images = img_offset[n_sys], 1..4096 */
+    const int32_t *img_offset; /* device [n_sys+1], non-decreasing, [0] = 0 */
+    const double *x, *y;       /* observed positions c_ij [arcsec] */
+    const double *sigma;       /* position error sigma_ij [arcsec], > 0 */
+    const double *dlsds;       /* Dls/Ds of each system's source, (0, 1] */
+} lens_catalog_t;
+
+typedef struct {
+    lens_chi2_mode_t mode;
+    lens_precision_t prec;     /* evaluation precision of the deflections */
+    lens_chi2_path_t path;
+    lens_grid_t grid;          /* image mode: the triangulated grid */
+    int32_t max_img_per_sys;   /* image mode: stored images per (sample, system), 1..64 */
+    double missing_penalty;    /* image mode: added per constraint left without an image */
+} lens_chi2_opts_t;
+
+/* Launch configuration of the map kernel (chosen by the autotuner).
+ * block_x * block_y threads per block (block_x a multiple of 64, product
+ * <= 1024), each thread evaluating pix_per_thread points along x;
+ * stage = 1 stages the derived potential constants in LDS in chunks of
+ * lds_chunk potentials, stage = 0 reads them with wave-uniform loads. */
+typedef struct {
+    int32_t block_x, block_y, pix_per_thread, stage, lds_chunk;
+} lens_map_tuning_t;
+
+/* ---- context ---------------------------------------------------------- */
+lens_status_t lens_ctx_create(int32_t device, uint64_t scratch_bytes_max, uint32_t flags,
+                              lens_ctx_t **out);
+lens_status_t lens_ctx_destroy(lens_ctx_t *ctx);
+/* Sticky device-side status of unchecked contexts; synchronises the device. */
+lens_status_t lens_ctx_status(lens_ctx_t *ctx);
+/* Set (tuning != NULL) or reset to the built-in default (NULL) the map
+ * kernel's launch configuration for one precision. */
+lens_status_t lens_set_map_tuning(lens_ctx_t *ctx, lens_precision_t prec,
+                                  const lens_map_tuning_t *tuning);
+lens_status_t lens_get_map_tuning(lens_ctx_t *ctx, lens_precision_t prec,
+                                  lens_map_tuning_t *out);
+
+/* ---- parameter prologue ------------------------------------------------- */
+/* Physical -> amplitude form on the device (Sec. 2.2 parameters):
+ *   b0  = K pi (sigma/c)^2 rad in arcsec, K = 6 (convention 0, the Lenstool
+ *         dPIE convention) or 4 (convention 1, singular isothermal sphere);
+ *   eps = (1 - sqrt(1 - e^2))/e (eps = 0 at e = 0).
+ * out_b0 and out_eps are device arrays of phys->n doubles; the other fields of
+ * the amplitude table are the physical table's own arrays. */
+lens_status_t lens_table_from_physical(lens_ctx_t *ctx, const lens_phys_table_t *phys,
+                                       int32_t convention, double *out_b0, double *out_eps,
+                                       void *stream);
+
+/* ---- maps (Sec. 4.1 Eq. (10); Sec. 2.4 Eqs. (7)-(9)) ---------------------- */
+/* Deflection map: ax, ay = dlsds * sum_k grad psi_k at every grid point.
+ * Outputs: nx*ny doubles each for LENS_FP64, floats otherwise. */
+lens_status_t lens_grad_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                            const lens_grid_t *grid, double dlsds, lens_precision_t prec,
+                            void *ax, void *ay, void *stream);
+
+/* Second-derivative map: hxx, hxy, hyy = dlsds * sum_k d^2 psi_k, computed in
+ * one pass with the deflection, which is stored too when ax and ay are both
+ * non-NULL.  Element type as for lens_grad_map. */
+lens_status_t lens_hessian_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                               const lens_grid_t *grid, double dlsds, lens_precision_t prec,
+                               void *hxx, void *hxy, void *hyy, void *ax, void *ay,
+                               void *stream);
+
+/* ---- chi^2 of a batch of samples (Sec. 2.2 Eq. (6); Sec. 2.3; Sec. 4.2) --- */
+/* chi2[m] for every sample m (device, n_samples doubles).
+ * Source mode: chi2 = sum_i sum_j |beta_ij - mean_j beta_ij|^2 / sigma_ij^2,
+ *   beta_ij = theta_ij - dlsds_i alpha(theta_ij).
+ * Image mode: per sample, sources = those barycentres; every grid cell (i, j)
+ *   is split into T0 = (v[i,j], v[i+1,j], v[i,j+1]) and
+ *   T1 = (v[i+1,j+1], v[i,j+1], v[i+1,j]) (ids 2(j(nx-1)+i) and +1); each
+ *   vertex is unlensed as u = v - dlsds_i alpha(v); a source found inside a
+ *   triangle (exact orientation tests, ties broken by the perturbation
+ *   p + (d, d^2)) gives an image at the barycentric interpolation of the
+ *   triangle's image-plane vertices.  Each image is assigned to its nearest
+ *   constraint (ties: lower index); each constraint keeps its nearest assigned
+ *   image (ties: lower triangle id) and adds |c - x|^2/sigma^2, or
+ *   missing_penalty when it has none.
+ *   nimg (device [n_samples*n_sys] int32, or NULL): exact number of images;
+ *   nmissing (device [n_samples] int32, or NULL): constraints without image;
+ *   img_xy (device [n_samples*n_sys*max_img_per_sys*2] doubles, or NULL):
+ *   stored image positions in increasing triangle id, unused slots NaN.
+ *   Returns LENS_EOVERFLOW (after completing the stream, counts exact) when a
+ *   (sample, system) had more images than max_img_per_sys.
+ *   Image mode synchronises `stream` once at the end to report overflow. */
+lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *batch,
+                              const lens_catalog_t *cat, const lens_chi2_opts_t *opts,
+                              double *chi2, int32_t *nimg, int32_t *nmissing, double *img_xy,
+                              void *stream);
+
+/* Image search alone (stage 3 of Sec. 4.2) for a given deflection grid:
+ * ax, ay (device, nx*ny doubles, Dls/Ds = 1) are the total deflection at the
+ * grid vertices; source s sits at (src_x[s], src_y[s]) with Dls/Ds f[s]
+ * (device arrays of n_src).  Outputs per source, images in increasing
+ * triangle id: nimg[s] (exact count), img_tri/img_x/img_y[s*kmax + k]
+ * (k < min(nimg[s], kmax); unused slots -1 / NaN).  Returns LENS_EOVERFLOW
+ * when a count exceeded kmax (synchronises `stream`). */
+lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *ay,
+                               const lens_grid_t *grid, int32_t n_src, const double *src_x,
+                               const double *src_y, const double *f, int32_t kmax,
+                               int32_t *nimg, int64_t *img_tri, double *img_x, double *img_y,
+                               void *stream);
+
+/* ---- captured batches (batching form) ------------------------------------ */
+/* Record the whole of one lens_chi2_batch call (batched path) into a HIP
+ * graph bound to these exact buffers and shapes; replaying it re-evaluates
+ * the batch with whatever the buffers then hold.  Source mode only. */
+lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *batch,
+                                    const lens_catalog_t *cat, const lens_chi2_opts_t *opts,
+                                    double *chi2, void *stream, lens_chi2_plan_t **out);
+lens_status_t lens_chi2_plan_launch(lens_chi2_plan_t *plan, void *stream);
+lens_status_t lens_chi2_plan_destroy(lens_chi2_plan_t *plan);
+
+/* ---- host helpers (synchronous, no device) -------------------------------- */
+/* Dls/Ds for a flat cosmology (om + ol = 1; the paper's Eq. (3) distances):
+ * 1 - chi(zl)/chi(zs), chi the comoving distance.  0 <= zl < zs. */
+lens_status_t lens_dlsds(double zl, double zs, double om, double ol, double *out);
+lens_status_t lens_b0_from_sigma(double sigma_kms, int32_t convention, double *out);
+lens_status_t lens_eps_from_e(double e, double *out);
+
+const char *lens_last_error(void); /* thread-local; valid until the next call */
+int32_t lens_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LENSHPC_H */

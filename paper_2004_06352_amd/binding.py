@@ -1,0 +1,396 @@
+"""Python binding of the C ABI in ``include/lenshpc.h`` (ctypes).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch provides device memory and the current stream.  The library
+must have been built (``python -m paper_2004_06352_amd.build``); nothing here
+falls back to any other implementation.
+
+Containers
+  table    dict of float64 device tensors x0, y0, b0, eps, phi, rcore, rcut
+  phys     dict of float64 device tensors x0, y0, sigma, e, phi, rcore, rcut
+  grid     (nx, ny, x0, y0, dx, dy)
+  catalog  dict: off (int32), x, y, sig (float64 per image), f (float64 Dls/Ds per system)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # load torch's HIP runtime before the library (one runtime per process)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_native", "liblenshpc.so")
+
+FP64, FP32_ACC64, FP32_COMP32 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32_acc64": FP32_ACC64, "fp32_comp32": FP32_COMP32}
+CHI2_SOURCE, CHI2_IMAGE = 0, 1
+PATH_BATCHED, PATH_PER_SAMPLE = 0, 1
+CTX_CHECK_TABLES = 1
+
+STATUS = {0: "LENS_OK", -1: "LENS_EINVAL", -2: "LENS_ENOMEM", -3: "LENS_EDEVICE",
+          -4: "LENS_EOVERFLOW", -5: "LENS_EUNSUPPORTED"}
+
+POT_KEYS = ("x0", "y0", "b0", "eps", "phi", "rcore", "rcut")
+PHYS_KEYS = ("x0", "y0", "sigma", "e", "phi", "rcore", "rcut")
+
+EXPORTS = ("lens_ctx_create", "lens_ctx_destroy", "lens_ctx_status", "lens_set_map_tuning",
+           "lens_get_map_tuning", "lens_table_from_physical", "lens_grad_map",
+           "lens_hessian_map", "lens_chi2_batch", "lens_find_images", "lens_chi2_plan_create",
+           "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_dlsds",
+           "lens_b0_from_sigma", "lens_eps_from_e", "lens_last_error", "lens_abi_version")
+
+
+class LensError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Pot(C.Structure):
+    _fields_ = [("n", C.c_int32)] + [(k, C.c_void_p) for k in POT_KEYS]
+
+
+class _Phys(C.Structure):
+    _fields_ = [("n", C.c_int32)] + [(k, C.c_void_p) for k in PHYS_KEYS]
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x0", C.c_double), ("y0", C.c_double),
+                ("dx", C.c_double), ("dy", C.c_double)]
+
+
+class _Batch(C.Structure):
+    _fields_ = [("n_samples", C.c_int32), ("free_offset", C.c_void_p), ("free", _Pot),
+                ("fixed", _Pot)]
+
+
+class _Cat(C.Structure):
+    _fields_ = [("n_sys", C.c_int32), ("n_img", C.c_int32), ("img_offset", C.c_void_p),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("sigma", C.c_void_p),
+                ("dlsds", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("prec", C.c_int32), ("path", C.c_int32), ("grid", _Grid),
+                ("max_img_per_sys", C.c_int32), ("missing_penalty", C.c_double)]
+
+
+class MapTuning(C.Structure):
+    _fields_ = [("block_x", C.c_int32), ("block_y", C.c_int32), ("pix_per_thread", C.c_int32),
+                ("stage", C.c_int32), ("lds_chunk", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.block_x, self.block_y, self.pix_per_thread, self.stage, self.lds_chunk)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(python -m paper_2004_06352_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+        L.lens_ctx_create.argtypes = [i32, C.c_uint64, C.c_uint32, C.POINTER(vp)]
+        L.lens_ctx_destroy.argtypes = [vp]
+        L.lens_ctx_status.argtypes = [vp]
+        L.lens_set_map_tuning.argtypes = [vp, i32, C.POINTER(MapTuning)]
+        L.lens_get_map_tuning.argtypes = [vp, i32, C.POINTER(MapTuning)]
+        L.lens_table_from_physical.argtypes = [vp, C.POINTER(_Phys), i32, vp, vp, vp]
+        L.lens_grad_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp, vp]
+        L.lens_hessian_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp,
+                                       vp, vp, vp, vp]
+        L.lens_chi2_batch.argtypes = [vp, C.POINTER(_Batch), C.POINTER(_Cat), C.POINTER(_Opts),
+                                      vp, vp, vp, vp, vp]
+        L.lens_find_images.argtypes = [vp, vp, vp, C.POINTER(_Grid), i32, vp, vp, vp, i32, vp,
+                                       vp, vp, vp, vp]
+        L.lens_chi2_plan_create.argtypes = [vp, C.POINTER(_Batch), C.POINTER(_Cat),
+                                            C.POINTER(_Opts), vp, vp, C.POINTER(vp)]
+        L.lens_chi2_plan_launch.argtypes = [vp, vp]
+        L.lens_chi2_plan_destroy.argtypes = [vp]
+        L.lens_dlsds.argtypes = [dbl, dbl, dbl, dbl, C.POINTER(dbl)]
+        L.lens_b0_from_sigma.argtypes = [dbl, i32, C.POINTER(dbl)]
+        L.lens_eps_from_e.argtypes = [dbl, C.POINTER(dbl)]
+        L.lens_last_error.restype = C.c_char_p
+        L.lens_abi_version.restype = i32
+        for name in EXPORTS:
+            if name not in ("lens_last_error", "lens_abi_version"):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise LensError(status, lib().lens_last_error().decode())
+
+
+def _stream(device=None):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """A library context on one device (scratch + flags).  check=True
+    validates table contents before each launch (synchronising once)."""
+
+    def __init__(self, device: int = 0, scratch_max: int = 16 << 30, check: bool = True):
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().lens_ctx_create(device, scratch_max, CTX_CHECK_TABLES if check else 0,
+                                     C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lens_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def status(self):
+        _check(lib().lens_ctx_status(self.handle))
+
+    def set_map_tuning(self, prec, tuning=None):
+        if tuning is not None and not isinstance(tuning, MapTuning):
+            tuning = MapTuning(*tuning)
+        _check(lib().lens_set_map_tuning(self.handle, prec,
+                                         C.byref(tuning) if tuning is not None else None))
+
+    def get_map_tuning(self, prec):
+        t = MapTuning()
+        _check(lib().lens_get_map_tuning(self.handle, prec, C.byref(t)))
+        return t.as_tuple()
+
+
+_contexts = {}
+
+
+def default_context(device=None, check=True) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    key = (device, check)
+    if key not in _contexts:
+        _contexts[key] = Context(device, check=check)
+    return _contexts[key]
+
+
+def _dev(t, device, dtype=torch.float64):
+    t = torch.as_tensor(t, dtype=dtype)
+    return t.to(device=device).contiguous()
+
+
+def to_device(d: dict, keys, device="cuda"):
+    """dict of array-likes -> dict of contiguous float64 device tensors."""
+    return {k: _dev(d[k], device) for k in keys}
+
+
+def _pot(t):
+    n = int(t["x0"].numel())
+    for k in POT_KEYS:
+        assert t[k].dtype == torch.float64 and t[k].is_cuda and t[k].is_contiguous(), k
+        assert t[k].numel() == n, k
+    return _Pot(n, *[t[k].data_ptr() if n else None for k in POT_KEYS])
+
+
+def _grid(g):
+    nx, ny, x0, y0, dx, dy = g
+    return _Grid(int(nx), int(ny), float(x0), float(y0), float(dx), float(dy))
+
+
+def _ctx(ctx):
+    return ctx if ctx is not None else default_context()
+
+
+def table_from_physical(phys, convention=0, ctx=None):
+    """Physical table -> amplitude table on the device (library prologue)."""
+    ctx = _ctx(ctx)
+    n = int(phys["x0"].numel())
+    dev = phys["x0"].device
+    b0 = torch.empty(n, dtype=torch.float64, device=dev)
+    eps = torch.empty(n, dtype=torch.float64, device=dev)
+    P = _Phys(n, *[phys[k].data_ptr() if n else None for k in PHYS_KEYS])
+    _check(lib().lens_table_from_physical(ctx.handle, C.byref(P), convention,
+                                          _ptr(b0) if n else None, _ptr(eps) if n else None,
+                                          _stream(dev)))
+    return dict(x0=phys["x0"], y0=phys["y0"], b0=b0, eps=eps, phi=phys["phi"],
+                rcore=phys["rcore"], rcut=phys["rcut"])
+
+
+def _out_dtype(prec):
+    return torch.float64 if prec == FP64 else torch.float32
+
+
+def grad_map(table, grid, dlsds=1.0, prec=FP64, ctx=None):
+    """(ax, ay), each (ny, nx): dlsds times the summed deflection."""
+    ctx = _ctx(ctx)
+    nx, ny = int(grid[0]), int(grid[1])
+    dev = table["x0"].device
+    ax = torch.empty((ny, nx), dtype=_out_dtype(prec), device=dev)
+    ay = torch.empty_like(ax)
+    T, G = _pot(table), _grid(grid)
+    _check(lib().lens_grad_map(ctx.handle, C.byref(T), C.byref(G), float(dlsds), prec,
+                               _ptr(ax), _ptr(ay), _stream(dev)))
+    return ax, ay
+
+
+def hessian_map(table, grid, dlsds=1.0, prec=FP64, with_alpha=True, ctx=None, out=None):
+    """dict of (ny, nx) planes hxx, hxy, hyy (and ax, ay when with_alpha)."""
+    ctx = _ctx(ctx)
+    nx, ny = int(grid[0]), int(grid[1])
+    dev = table["x0"].device
+    if out is None:
+        names = ("hxx", "hxy", "hyy") + (("ax", "ay") if with_alpha else ())
+        out = {k: torch.empty((ny, nx), dtype=_out_dtype(prec), device=dev) for k in names}
+    T, G = _pot(table), _grid(grid)
+    _check(lib().lens_hessian_map(ctx.handle, C.byref(T), C.byref(G), float(dlsds), prec,
+                                  _ptr(out["hxx"]), _ptr(out["hxy"]), _ptr(out["hyy"]),
+                                  _ptr(out.get("ax")), _ptr(out.get("ay")), _stream(dev)))
+    return out
+
+
+def _batch(fixed, free, free_off):
+    return _Batch(int(free_off.numel()) - 1, free_off.data_ptr(), _pot(free), _pot(fixed))
+
+
+def _catalog(cat):
+    off = cat["off"]
+    assert off.dtype == torch.int32 and off.is_cuda
+    return _Cat(int(off.numel()) - 1, int(cat["x"].numel()), off.data_ptr(), cat["x"].data_ptr(),
+                cat["y"].data_ptr(), cat["sig"].data_ptr(), cat["f"].data_ptr())
+
+
+def catalog_to_device(cat, device="cuda"):
+    return dict(off=torch.as_tensor(cat["off"], dtype=torch.int32).to(device).contiguous(),
+                x=_dev(cat["x"], device), y=_dev(cat["y"], device), sig=_dev(cat["sig"], device),
+                f=_dev(cat["f"], device))
+
+
+def _opts(mode, prec, path, grid, kmax, penalty):
+    g = _grid(grid) if grid is not None else _Grid(0, 0, 0, 0, 0, 0)
+    return _Opts(mode, prec, path, g, int(kmax), float(penalty))
+
+
+def chi2_batch(fixed, free, free_off, cat, mode=CHI2_SOURCE, prec=FP64, path=PATH_BATCHED,
+               grid=None, kmax=16, penalty=0.0, want_images=False, ctx=None):
+    """chi^2 of every sample; image mode also returns nimg, nmissing (and
+    img_xy (S, nsys, kmax, 2) when want_images)."""
+    ctx = _ctx(ctx)
+    dev = free_off.device
+    S = int(free_off.numel()) - 1
+    nsys = int(cat["off"].numel()) - 1
+    chi2 = torch.empty(S, dtype=torch.float64, device=dev)
+    res = dict(chi2=chi2)
+    nimg = nmiss = img = None
+    if mode == CHI2_IMAGE:
+        nimg = torch.empty((S, nsys), dtype=torch.int32, device=dev)
+        nmiss = torch.empty(S, dtype=torch.int32, device=dev)
+        res.update(nimg=nimg, nmissing=nmiss)
+        if want_images:
+            img = torch.empty((S, nsys, kmax, 2), dtype=torch.float64, device=dev)
+            res["img_xy"] = img
+    B, K = _batch(fixed, free, free_off), _catalog(cat)
+    O = _opts(mode, prec, path, grid, kmax, penalty)
+    st = lib().lens_chi2_batch(ctx.handle, C.byref(B), C.byref(K), C.byref(O), _ptr(chi2),
+                               _ptr(nimg), _ptr(nmiss), _ptr(img), _stream(dev))
+    if st == -4:
+        res["overflow"] = True
+        return res
+    _check(st)
+    res["overflow"] = False
+    return res
+
+
+def find_images(alpha, grid, src_x, src_y, f, kmax=16, ctx=None):
+    """alpha: (2, ny, nx) float64 device tensor (Dls/Ds = 1).  Returns
+    (nimg, tri, x, y) with per-source slot arrays (n_src, kmax)."""
+    ctx = _ctx(ctx)
+    dev = alpha.device
+    assert alpha.dtype == torch.float64 and alpha.is_contiguous() and alpha.shape[0] == 2
+    n = int(src_x.numel())
+    nimg = torch.empty(n, dtype=torch.int32, device=dev)
+    tri = torch.empty((n, kmax), dtype=torch.int64, device=dev)
+    ix = torch.empty((n, kmax), dtype=torch.float64, device=dev)
+    iy = torch.empty((n, kmax), dtype=torch.float64, device=dev)
+    G = _grid(grid)
+    nv = int(grid[0]) * int(grid[1])
+    ay_ptr = alpha.data_ptr() + nv * 8
+    st = lib().lens_find_images(ctx.handle, _ptr(alpha), C.c_void_p(ay_ptr), C.byref(G), n,
+                                _ptr(src_x), _ptr(src_y), _ptr(f), int(kmax), _ptr(nimg),
+                                _ptr(tri), _ptr(ix), _ptr(iy), _stream(dev))
+    if st not in (0, -4):
+        _check(st)
+    return nimg, tri, ix, iy, st == -4
+
+
+class Chi2Plan:
+    """A source-plane lens_chi2_batch recorded into a HIP graph; launch()
+    replays it on the current stream over the same buffers."""
+
+    def __init__(self, fixed, free, free_off, cat, prec=FP64, ctx=None):
+        self.ctx = _ctx(ctx)
+        dev = free_off.device
+        S = int(free_off.numel()) - 1
+        self.chi2 = torch.empty(S, dtype=torch.float64, device=dev)
+        self._keep = (fixed, free, free_off, cat)
+        B, K = _batch(fixed, free, free_off), _catalog(cat)
+        O = _opts(CHI2_SOURCE, prec, PATH_BATCHED, None, 1, 0.0)
+        h = C.c_void_p()
+        self.stream = torch.cuda.Stream(device=dev)
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        _check(lib().lens_chi2_plan_create(self.ctx.handle, C.byref(B), C.byref(K), C.byref(O),
+                                           _ptr(self.chi2), C.c_void_p(self.stream.cuda_stream),
+                                           C.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        _check(lib().lens_chi2_plan_launch(self.handle, _stream(self.chi2.device)))
+        return self.chi2
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lens_chi2_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- host helpers -----------------------------------------------------------
+def dlsds(zl, zs, om=0.3, ol=0.7):
+    out = C.c_double()
+    _check(lib().lens_dlsds(float(zl), float(zs), float(om), float(ol), C.byref(out)))
+    return out.value
+
+
+def b0_from_sigma(sigma, convention=0):
+    out = C.c_double()
+    _check(lib().lens_b0_from_sigma(float(sigma), int(convention), C.byref(out)))
+    return out.value
+
+
+def eps_from_e(e):
+    out = C.c_double()
+    _check(lib().lens_eps_from_e(float(e), C.byref(out)))
+    return out.value
+
+
+def catalog_with_dlsds(cat, zl, om=0.3, ol=0.7):
+    """Catalogue dict (numpy) with f = Dls/Ds per system from its source redshift."""
+    out = dict(cat)
+    out["f"] = [dlsds(zl, z, om, ol) for z in cat["zs"]]
+    return out

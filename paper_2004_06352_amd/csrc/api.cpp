@@ -1,0 +1,810 @@
+// api.cpp -- the C ABI of include/lenshpc.h: argument validation, context
+// scratch, and the launch sequences of the map and chi^2 calls.
+//
+// Every argument error is found before the first launch (and leaves outputs
+// untouched); device arrays are checked against the allocation they lie in.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lens_internal.h"
+
+using namespace lens;
+
+static thread_local std::string g_err;
+
+static lens_status_t fail(lens_status_t code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(LENS_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+#define TRY(expr)                          \
+    do {                                   \
+        lens_status_t s_ = (expr);         \
+        if (s_ != LENS_OK) return s_;      \
+    } while (0)
+
+struct lens_ctx {
+    int device = 0;
+    uint64_t scratch_max = 0;
+    uint32_t flags = 0;
+    void *scratch = nullptr;
+    size_t scratch_size = 0;
+    int *small = nullptr;        // device: [0] status, [1] queue, [2..] spare
+    int *host_small = nullptr;   // pinned mirror
+    int num_cu = 256;
+    lens_map_tuning_t tune[3];
+};
+
+struct lens_chi2_plan {
+    lens_ctx_t *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+const lens_map_tuning_t kDefaultMapTuning = {64, 4, 1, 1, 64};
+
+// Keep the caller's current device.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+// The byte range [p, p + bytes) must lie inside one device allocation.
+lens_status_t check_range(const void *p, size_t bytes, const char *name) {
+    if (bytes == 0) return LENS_OK;
+    if (!p) return fail(LENS_EINVAL, "%s is NULL", name);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    hipError_t e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e != hipSuccess || base == nullptr) {
+        (void)hipGetLastError();
+        return fail(LENS_EINVAL, "%s (%p) is not a device allocation", name, p);
+    }
+    const char *b = (const char *)base, *q = (const char *)p;
+    if (q < b || (size_t)(q - b) + bytes > size)
+        return fail(LENS_EINVAL, "%s: %zu bytes at %p exceed its allocation (%zu bytes at %p)",
+                    name, bytes, p, size, (const void *)base);
+    return LENS_OK;
+}
+
+lens_status_t check_table(const lens_pot_table_t *t, const char *name) {
+    if (!t) return fail(LENS_EINVAL, "%s is NULL", name);
+    if (t->n < 0) return fail(LENS_EINVAL, "%s.n = %d < 0", name, t->n);
+    const size_t b = (size_t)t->n * sizeof(double);
+    const void *ps[7] = {t->x0, t->y0, t->b0, t->eps, t->phi, t->rcore, t->rcut};
+    const char *nm[7] = {"x0", "y0", "b0", "eps", "phi", "rcore", "rcut"};
+    for (int i = 0; i < 7; ++i) {
+        char full[96];
+        snprintf(full, sizeof full, "%s.%s", name, nm[i]);
+        TRY(check_range(ps[i], b, full));
+    }
+    return LENS_OK;
+}
+
+lens_status_t check_grid(const lens_grid_t *g) {
+    if (!g) return fail(LENS_EINVAL, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1) return fail(LENS_EINVAL, "grid %d x %d", g->nx, g->ny);
+    if ((long long)g->nx * g->ny > (1LL << 31))
+        return fail(LENS_EINVAL, "grid of %lld points exceeds 2^31", (long long)g->nx * g->ny);
+    if (!is_fin(g->x0) || !is_fin(g->y0) || !is_fin(g->dx) || !is_fin(g->dy) || !(g->dx > 0) ||
+        !(g->dy > 0))
+        return fail(LENS_EINVAL, "grid origin/spacing not finite and positive");
+    return LENS_OK;
+}
+
+lens_status_t check_prec(lens_precision_t p) {
+    if (p != LENS_FP64 && p != LENS_FP32_ACC64 && p != LENS_FP32_COMP32)
+        return fail(LENS_EINVAL, "unknown precision %d", p);
+    return LENS_OK;
+}
+
+// Bump allocator over the context scratch.
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    }
+};
+
+lens_status_t ensure_scratch(lens_ctx_t *ctx, size_t bytes) {
+    if (bytes <= ctx->scratch_size) return LENS_OK;
+    if (bytes > ctx->scratch_max)
+        return fail(LENS_ENOMEM, "needs %zu bytes of scratch, context limit is %llu", bytes,
+                    (unsigned long long)ctx->scratch_max);
+    if (ctx->scratch) {
+        HIP_TRY(hipFree(ctx->scratch));  // waits for work still using it
+        ctx->scratch = nullptr;
+        ctx->scratch_size = 0;
+    }
+    size_t sz = std::max(bytes, (size_t)1 << 20);
+    sz = std::min<size_t>(std::max(sz, bytes), std::max<size_t>(bytes, ctx->scratch_max));
+    hipError_t e = hipMalloc(&ctx->scratch, sz);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->scratch = nullptr;
+        return fail(LENS_ENOMEM, "hipMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
+    }
+    ctx->scratch_size = sz;
+    return LENS_OK;
+}
+
+char *sc(lens_ctx_t *ctx, size_t off) { return (char *)ctx->scratch + off; }
+
+PotSoA soa(const lens_pot_table_t *t) {
+    return PotSoA{t->x0, t->y0, t->b0, t->eps, t->phi, t->rcore, t->rcut};
+}
+
+Derived derived_at(lens_ctx_t *ctx, size_t off, int n) {
+    const int st = derived_stride(n);
+    double *d = (double *)sc(ctx, off);
+    float *f = (float *)(d + (size_t)NDER * st);
+    return Derived{d, f, n, st};
+}
+
+lens_status_t run_prologue(lens_ctx_t *ctx, const lens_pot_table_t *t, const Derived &D,
+                           hipStream_t st) {
+    HIP_TRY(launch_prologue(soa(t), t->n, const_cast<double *>(D.d), const_cast<float *>(D.f),
+                            D.stride, ctx->small, st));
+    return LENS_OK;
+}
+
+bool checked(const lens_ctx_t *ctx) { return (ctx->flags & LENS_CTX_CHECK_TABLES) != 0; }
+
+// In checked contexts: clear the status word before the prologues.
+lens_status_t status_reset(lens_ctx_t *ctx, hipStream_t st) {
+    if (!checked(ctx)) return LENS_OK;
+    HIP_TRY(launch_zero_i32(ctx->small, 1, st));
+    return LENS_OK;
+}
+
+// In checked contexts: wait for the prologues and report invalid content.
+lens_status_t status_check(lens_ctx_t *ctx, hipStream_t st) {
+    if (!checked(ctx)) return LENS_OK;
+    HIP_TRY(hipMemcpyAsync(ctx->host_small, ctx->small, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctx->host_small[0] & ST_INVALID_TABLE)
+        return fail(LENS_EINVAL, "a potential table holds invalid parameters");
+    return LENS_OK;
+}
+
+lens_status_t map_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const lens_grid_t *grid,
+                         double dlsds, lens_precision_t prec, void *out[5], bool grad, bool hess,
+                         hipStream_t st) {
+    if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
+    TRY(check_prec(prec));
+    TRY(check_table(table, "table"));
+    TRY(check_grid(grid));
+    if (!is_fin(dlsds) || dlsds < 0) return fail(LENS_EINVAL, "dlsds = %g", dlsds);
+    const size_t np = (size_t)grid->nx * grid->ny;
+    const size_t esz = prec == LENS_FP64 ? sizeof(double) : sizeof(float);
+    const char *names[5] = {"ax", "ay", "hxx", "hxy", "hyy"};
+    for (int c = 0; c < 5; ++c)
+        if (out[c]) TRY(check_range(out[c], np * esz, names[c]));
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
+    Carve cv;
+    const size_t o_tab = cv.take(derived_bytes(table->n));
+    TRY(ensure_scratch(ctx, cv.off));
+    const Derived D = derived_at(ctx, o_tab, table->n);
+    TRY(status_reset(ctx, st));
+    TRY(run_prologue(ctx, table, D, st));
+    TRY(status_check(ctx, st));
+    MapLaunch m;
+    m.tab = D;
+    m.grid = GridArgs{grid->nx, grid->ny, grid->x0, grid->y0, grid->dx, grid->dy};
+    m.dlsds = dlsds;
+    for (int c = 0; c < 5; ++c) m.out[c] = out[c];
+    m.prec = prec;
+    m.grad = grad;
+    m.hess = hess;
+    m.tune = ctx->tune[prec];
+    HIP_TRY(launch_map(m, st));
+    return LENS_OK;
+}
+
+// ------------------------- chi^2 ---------------------------------------------
+lens_status_t check_batch(const lens_model_batch_t *b) {
+    if (!b) return fail(LENS_EINVAL, "batch is NULL");
+    if (b->n_samples < 0) return fail(LENS_EINVAL, "n_samples < 0");
+    TRY(check_range(b->free_offset, ((size_t)b->n_samples + 1) * sizeof(int32_t),
+                    "batch.free_offset"));
+    TRY(check_table(&b->free, "batch.free"));
+    TRY(check_table(&b->fixed, "batch.fixed"));
+    return LENS_OK;
+}
+
+lens_status_t check_catalog(const lens_catalog_t *c) {
+    if (!c) return fail(LENS_EINVAL, "catalog is NULL");
+    if (c->n_sys < 1) return fail(LENS_EINVAL, "catalog.n_sys = %d", c->n_sys);
+    if (c->n_img < 1 || c->n_img > 4096)
+        return fail(LENS_EINVAL, "catalog.n_img = %d (1..4096)", c->n_img);
+    TRY(check_range(c->img_offset, ((size_t)c->n_sys + 1) * sizeof(int32_t),
+                    "catalog.img_offset"));
+    const size_t b = (size_t)c->n_img * sizeof(double);
+    TRY(check_range(c->x, b, "catalog.x"));
+    TRY(check_range(c->y, b, "catalog.y"));
+    TRY(check_range(c->sigma, b, "catalog.sigma"));
+    TRY(check_range(c->dlsds, (size_t)c->n_sys * sizeof(double), "catalog.dlsds"));
+    return LENS_OK;
+}
+
+// Checked contexts: the offset arrays and catalogue values, read back.
+lens_status_t check_contents(lens_ctx_t *ctx, const lens_model_batch_t *b,
+                             const lens_catalog_t *c, hipStream_t st) {
+    if (!checked(ctx)) return LENS_OK;
+    std::vector<int32_t> fo(b->n_samples + 1), io(c->n_sys + 1);
+    std::vector<double> sig(c->n_img), f(c->n_sys), x(c->n_img), y(c->n_img);
+    HIP_TRY(hipMemcpyAsync(fo.data(), b->free_offset, fo.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(io.data(), c->img_offset, io.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(sig.data(), c->sigma, sig.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(f.data(), c->dlsds, f.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(x.data(), c->x, x.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(y.data(), c->y, y.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (fo[0] != 0 || fo[b->n_samples] != b->free.n)
+        return fail(LENS_EINVAL, "free_offset must run from 0 to free.n = %d", b->free.n);
+    for (int m = 0; m < b->n_samples; ++m)
+        if (fo[m + 1] < fo[m]) return fail(LENS_EINVAL, "free_offset decreases at %d", m);
+    if (io[0] != 0 || io[c->n_sys] != c->n_img)
+        return fail(LENS_EINVAL, "img_offset must run from 0 to n_img = %d", c->n_img);
+    for (int i = 0; i < c->n_sys; ++i) {
+        if (io[i + 1] < io[i]) return fail(LENS_EINVAL, "img_offset decreases at %d", i);
+        if (!(f[i] > 0.0 && f[i] <= 1.0)) return fail(LENS_EINVAL, "dlsds[%d] = %g", i, f[i]);
+    }
+    for (int t = 0; t < c->n_img; ++t)
+        if (!(sig[t] > 0.0) || !is_fin(sig[t]) || !is_fin(x[t]) || !is_fin(y[t]))
+            return fail(LENS_EINVAL, "catalog image %d: bad position or sigma", t);
+    return LENS_OK;
+}
+
+struct SrcPlan {
+    size_t o_fix, o_free, o_afix, o_src;
+    int nchunk, nimg_pad;
+};
+
+SrcPlan plan_src(Carve &cv, const lens_model_batch_t *b, const lens_catalog_t *c, bool sources) {
+    SrcPlan p;
+    p.nchunk = (b->fixed.n + 31) / 32;
+    p.nimg_pad = (c->n_img + 63) / 64 * 64;
+    p.o_fix = cv.take(derived_bytes(b->fixed.n));
+    p.o_free = cv.take(derived_bytes(b->free.n));
+    p.o_afix = cv.take((size_t)std::max(p.nchunk, 1) * 2 * p.nimg_pad * sizeof(double));
+    p.o_src = sources ? cv.take((size_t)std::max(b->n_samples, 1) * c->n_sys * 2 * sizeof(double))
+                      : 0;
+    return p;
+}
+
+int batched_blocks(const lens_ctx_t *ctx, int S) { return std::max(1, std::min(S, ctx->num_cu * 8)); }
+
+// Prologues, fixed deflection at the constraints, then the per-sample kernel.
+lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
+                           lens_precision_t prec, lens_chi2_path_t path, const SrcPlan &p,
+                           double *chi2, bool sources, hipStream_t st, bool with_check) {
+    const Derived DF = derived_at(ctx, p.o_fix, b->fixed.n);
+    const Derived DV = derived_at(ctx, p.o_free, b->free.n);
+    if (with_check) TRY(status_reset(ctx, st));
+    TRY(run_prologue(ctx, &b->fixed, DF, st));
+    TRY(run_prologue(ctx, &b->free, DV, st));
+    if (with_check) TRY(status_check(ctx, st));
+    double *afix = (double *)sc(ctx, p.o_afix);
+    HIP_TRY(launch_fixed_alpha_points(DF, c->n_img, c->x, c->y, p.nchunk, p.nimg_pad, afix, prec,
+                                      st));
+    Chi2SrcLaunch L;
+    L.freet = DV;
+    L.free_off = b->free_offset;
+    L.n_samples = b->n_samples;
+    L.sample0 = 0;
+    L.nsys = c->n_sys;
+    L.nimg = c->n_img;
+    L.img_off = c->img_offset;
+    L.x = c->x;
+    L.y = c->y;
+    L.sig = c->sigma;
+    L.f = c->dlsds;
+    L.afix = afix;
+    L.nchunk = p.nchunk;
+    L.nimg_pad = p.nimg_pad;
+    L.chi2 = chi2;
+    L.src_x = sources ? (double *)sc(ctx, p.o_src) : nullptr;
+    L.src_y = sources ? L.src_x + (size_t)b->n_samples * c->n_sys : nullptr;
+    L.queue = ctx->small + 1;
+    L.prec = prec == LENS_FP64 ? 0 : 1;
+    if (b->n_samples == 0) return LENS_OK;
+    if (path == LENS_CHI2_PATH_BATCHED) {
+        HIP_TRY(launch_zero_i32(ctx->small + 1, 1, st));
+        L.persistent = 1;
+        L.grid_blocks = batched_blocks(ctx, b->n_samples);
+        HIP_TRY(launch_chi2_src(L, st));
+    } else {
+        L.persistent = 0;
+        L.grid_blocks = 1;
+        for (int m = 0; m < b->n_samples; ++m) {
+            L.sample0 = m;
+            HIP_TRY(launch_chi2_src(L, st));
+        }
+    }
+    return LENS_OK;
+}
+
+lens_status_t check_chi2_args(lens_ctx_t *ctx, const lens_model_batch_t *b,
+                              const lens_catalog_t *c, const lens_chi2_opts_t *o) {
+    if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
+    if (!o) return fail(LENS_EINVAL, "opts is NULL");
+    TRY(check_batch(b));
+    TRY(check_catalog(c));
+    TRY(check_prec(o->prec));
+    if (o->path != LENS_CHI2_PATH_BATCHED && o->path != LENS_CHI2_PATH_PER_SAMPLE)
+        return fail(LENS_EINVAL, "unknown path %d", o->path);
+    if (o->mode != LENS_CHI2_SOURCE && o->mode != LENS_CHI2_IMAGE)
+        return fail(LENS_EINVAL, "unknown mode %d", o->mode);
+    if (o->mode == LENS_CHI2_IMAGE) {
+        TRY(check_grid(&o->grid));
+        if (o->grid.nx < 2 || o->grid.ny < 2)
+            return fail(LENS_EINVAL, "image mode needs a grid of at least 2 x 2");
+        if (o->max_img_per_sys < 1 || o->max_img_per_sys > 64)
+            return fail(LENS_EINVAL, "max_img_per_sys = %d (1..64)", o->max_img_per_sys);
+        if (!is_fin(o->missing_penalty))
+            return fail(LENS_EINVAL, "missing_penalty is not finite");
+    }
+    return LENS_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+const char *lens_last_error(void) { return g_err.c_str(); }
+int32_t lens_abi_version(void) { return LENSHPC_ABI_VERSION; }
+
+lens_status_t lens_ctx_create(int32_t device, uint64_t scratch_bytes_max, uint32_t flags,
+                              lens_ctx_t **out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(LENS_EDEVICE, "no HIP device");
+    }
+    if (device < 0 || device >= ndev) return fail(LENS_EINVAL, "device %d of %d", device, ndev);
+    if (flags & ~LENS_CTX_CHECK_TABLES) return fail(LENS_EINVAL, "unknown flags 0x%x", flags);
+    DeviceGuard dg(device);
+    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", device);
+    lens_ctx_t *c = new lens_ctx_t();
+    c->device = device;
+    c->scratch_max = scratch_bytes_max;
+    c->flags = flags;
+    for (int p = 0; p < 3; ++p) c->tune[p] = kDefaultMapTuning;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (hipMalloc(&c->small, 64 * sizeof(int)) != hipSuccess ||
+        hipHostMalloc(&c->host_small, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->small) (void)hipFree(c->small);
+        delete c;
+        return fail(LENS_ENOMEM, "context allocation failed");
+    }
+    if (hipMemset(c->small, 0, 64 * sizeof(int)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(c->small);
+        (void)hipHostFree(c->host_small);
+        delete c;
+        return fail(LENS_EDEVICE, "context initialisation failed");
+    }
+    *out = c;
+    return LENS_OK;
+}
+
+lens_status_t lens_ctx_destroy(lens_ctx_t *ctx) {
+    if (!ctx) return LENS_OK;
+    DeviceGuard dg(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->small) (void)hipFree(ctx->small);
+    if (ctx->host_small) (void)hipHostFree(ctx->host_small);
+    delete ctx;
+    return LENS_OK;
+}
+
+lens_status_t lens_ctx_status(lens_ctx_t *ctx) {
+    if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(ctx->host_small, ctx->small, sizeof(int), hipMemcpyDeviceToHost));
+    const int s = ctx->host_small[0];
+    HIP_TRY(hipMemset(ctx->small, 0, sizeof(int)));
+    if (s & ST_INVALID_TABLE) return fail(LENS_EINVAL, "a table held invalid parameters");
+    if (s & ST_OVERFLOW) return fail(LENS_EOVERFLOW, "image slots overflowed");
+    return LENS_OK;
+}
+
+lens_status_t lens_set_map_tuning(lens_ctx_t *ctx, lens_precision_t prec,
+                                  const lens_map_tuning_t *t) {
+    if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
+    TRY(check_prec(prec));
+    if (!t) {
+        ctx->tune[prec] = kDefaultMapTuning;
+        return LENS_OK;
+    }
+    if (!map_tuning_valid(*t))
+        return fail(LENS_EINVAL, "invalid map tuning {%d,%d,%d,%d,%d}", t->block_x, t->block_y,
+                    t->pix_per_thread, t->stage, t->lds_chunk);
+    ctx->tune[prec] = *t;
+    return LENS_OK;
+}
+
+lens_status_t lens_get_map_tuning(lens_ctx_t *ctx, lens_precision_t prec, lens_map_tuning_t *out) {
+    if (!ctx || !out) return fail(LENS_EINVAL, "NULL argument");
+    TRY(check_prec(prec));
+    *out = ctx->tune[prec];
+    return LENS_OK;
+}
+
+lens_status_t lens_table_from_physical(lens_ctx_t *ctx, const lens_phys_table_t *phys,
+                                       int32_t convention, double *out_b0, double *out_eps,
+                                       void *stream) {
+    if (!ctx || !phys) return fail(LENS_EINVAL, "NULL argument");
+    if (phys->n < 0) return fail(LENS_EINVAL, "n < 0");
+    if (convention != 0 && convention != 1) return fail(LENS_EINVAL, "convention %d", convention);
+    const size_t b = (size_t)phys->n * sizeof(double);
+    TRY(check_range(phys->sigma, b, "phys.sigma"));
+    TRY(check_range(phys->e, b, "phys.e"));
+    TRY(check_range(out_b0, b, "out_b0"));
+    TRY(check_range(out_eps, b, "out_eps"));
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    TRY(status_reset(ctx, st));
+    HIP_TRY(launch_phys_to_amp(phys->sigma, phys->e, phys->n, convention, out_b0, out_eps,
+                               ctx->small, st));
+    TRY(status_check(ctx, st));
+    return LENS_OK;
+}
+
+lens_status_t lens_grad_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                            const lens_grid_t *grid, double dlsds, lens_precision_t prec, void *ax,
+                            void *ay, void *stream) {
+    if (!ax || !ay) return fail(LENS_EINVAL, "ax and ay are required");
+    void *out[5] = {ax, ay, nullptr, nullptr, nullptr};
+    return map_common(ctx, table, grid, dlsds, prec, out, true, false, (hipStream_t)stream);
+}
+
+lens_status_t lens_hessian_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                               const lens_grid_t *grid, double dlsds, lens_precision_t prec,
+                               void *hxx, void *hxy, void *hyy, void *ax, void *ay, void *stream) {
+    if (!hxx || !hxy || !hyy) return fail(LENS_EINVAL, "hxx, hxy and hyy are required");
+    if ((ax == nullptr) != (ay == nullptr))
+        return fail(LENS_EINVAL, "ax and ay must both be given or both be NULL");
+    void *out[5] = {ax, ay, hxx, hxy, hyy};
+    return map_common(ctx, table, grid, dlsds, prec, out, ax != nullptr, true,
+                      (hipStream_t)stream);
+}
+
+lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
+                              const lens_catalog_t *c, const lens_chi2_opts_t *o, double *chi2,
+                              int32_t *nimg, int32_t *nmissing, double *img_xy, void *stream) {
+    TRY(check_chi2_args(ctx, b, c, o));
+    const int S = b->n_samples;
+    TRY(check_range(chi2, (size_t)S * sizeof(double), "chi2"));
+    const bool img = o->mode == LENS_CHI2_IMAGE;
+    const int kmax = img ? o->max_img_per_sys : 0;
+    if (img) {
+        if (nimg) TRY(check_range(nimg, (size_t)S * c->n_sys * sizeof(int32_t), "nimg"));
+        if (nmissing) TRY(check_range(nmissing, (size_t)S * sizeof(int32_t), "nmissing"));
+        if (img_xy)
+            TRY(check_range(img_xy, (size_t)S * c->n_sys * kmax * 2 * sizeof(double), "img_xy"));
+    }
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv;
+    SrcPlan sp = plan_src(cv, b, c, img);
+    if (!img) {
+        TRY(ensure_scratch(ctx, cv.off));
+        TRY(check_contents(ctx, b, c, st));
+        return src_sequence(ctx, b, c, o->prec, o->path, sp, chi2, false, st, true);
+    }
+    // ---- image plane ----
+    const GridArgs G{o->grid.nx, o->grid.ny, o->grid.x0, o->grid.y0, o->grid.dx, o->grid.dy};
+    const size_t nv = (size_t)G.nx * G.ny;
+    const size_t o_afix = cv.take(2 * nv * sizeof(double));
+    const size_t fixed_bytes = cv.off;
+    // per-sample working set: deflection grid + slots
+    const size_t per_sample = 2 * nv * sizeof(double) +
+                              (size_t)c->n_sys * (sizeof(int) + 2 * sizeof(double) + sizeof(int) +
+                                                  (size_t)kmax * (sizeof(long long) + 2 * sizeof(double))) +
+                              4096;
+    int chunk = o->path == LENS_CHI2_PATH_PER_SAMPLE ? 1 : 32;
+    if (ctx->scratch_max > fixed_bytes) {
+        const size_t fit = (ctx->scratch_max - fixed_bytes) / per_sample;
+        chunk = (int)std::min<size_t>(chunk, std::max<size_t>(fit, 1));
+    }
+    chunk = std::max(1, std::min(chunk, std::max(S, 1)));
+    const size_t o_alpha = cv.take((size_t)chunk * 2 * nv * sizeof(double));
+    const size_t o_count = cv.take((size_t)chunk * c->n_sys * sizeof(int));
+    const size_t o_tri = cv.take((size_t)chunk * c->n_sys * kmax * sizeof(long long));
+    const size_t o_ix = cv.take((size_t)chunk * c->n_sys * kmax * sizeof(double));
+    const size_t o_iy = cv.take((size_t)chunk * c->n_sys * kmax * sizeof(double));
+    const size_t o_part = cv.take((size_t)chunk * c->n_sys * sizeof(double));
+    const size_t o_miss = cv.take((size_t)chunk * c->n_sys * sizeof(int));
+    TRY(ensure_scratch(ctx, cv.off));
+    TRY(check_contents(ctx, b, c, st));
+    HIP_TRY(launch_zero_i32(ctx->small + 2, 1, st));  // overflow word
+    TRY(src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr, true, st, true));
+    const double *srcx = (const double *)sc(ctx, sp.o_src);
+    const double *srcy = srcx + (size_t)S * c->n_sys;
+    double *afx = (double *)sc(ctx, o_afix), *afy = afx + nv;
+    const Derived DF = derived_at(ctx, sp.o_fix, b->fixed.n);
+    const Derived DV = derived_at(ctx, sp.o_free, b->free.n);
+    if (b->fixed.n > 0) {
+        MapLaunch m;
+        m.tab = DF;
+        m.grid = G;
+        m.dlsds = 1.0;
+        m.out[0] = afx;
+        m.out[1] = afy;
+        m.out[2] = m.out[3] = m.out[4] = nullptr;
+        m.prec = 0;
+        m.grad = true;
+        m.hess = false;
+        m.tune = ctx->tune[0];
+        HIP_TRY(launch_map(m, st));
+    }
+    double *alpha = (double *)sc(ctx, o_alpha);
+    int *count = (int *)sc(ctx, o_count);
+    long long *tri = (long long *)sc(ctx, o_tri);
+    double *ix = (double *)sc(ctx, o_ix), *iy = (double *)sc(ctx, o_iy);
+    for (int m0 = 0; m0 < S; m0 += chunk) {
+        const int ns = std::min(chunk, S - m0);
+        AlphaGridLaunch A;
+        A.freet = DV;
+        A.free_off = b->free_offset;
+        A.m0 = m0;
+        A.nsamp = ns;
+        A.grid = G;
+        A.afix_x = b->fixed.n > 0 ? afx : nullptr;
+        A.afix_y = b->fixed.n > 0 ? afy : nullptr;
+        A.out = alpha;
+        A.prec = o->prec == LENS_FP64 ? 0 : 1;
+        HIP_TRY(launch_alpha_grid(A, st));
+        HIP_TRY(launch_zero_i32(count, ns * c->n_sys, st));
+        ImgLaunch I;
+        I.alpha = alpha;
+        I.grid = G;
+        I.n_grids = ns;
+        I.nq = c->n_sys;
+        I.sx = srcx + (size_t)m0 * c->n_sys;
+        I.sy = srcy + (size_t)m0 * c->n_sys;
+        I.f = c->dlsds;
+        I.kmax = kmax;
+        I.count = count;
+        I.tri = tri;
+        I.ix = ix;
+        I.iy = iy;
+        HIP_TRY(launch_find_images(I, st));
+        HIP_TRY(launch_sort_images(ns * c->n_sys, kmax, count, tri, ix, iy, st));
+        AssignLaunch Q;
+        Q.nsamp = ns;
+        Q.nsys = c->n_sys;
+        Q.kmax = kmax;
+        Q.count = count;
+        Q.ix = ix;
+        Q.iy = iy;
+        Q.img_off = c->img_offset;
+        Q.nimg_total = c->n_img;
+        Q.x = c->x;
+        Q.y = c->y;
+        Q.sig = c->sigma;
+        Q.penalty = o->missing_penalty;
+        Q.m0 = m0;
+        Q.chi2 = chi2;
+        Q.nimg = nimg;
+        Q.nmissing = nmissing;
+        Q.img_xy = img_xy;
+        Q.part = (double *)sc(ctx, o_part);
+        Q.miss = (int *)sc(ctx, o_miss);
+        Q.status = ctx->small + 2;
+        HIP_TRY(launch_assign(Q, st));
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->host_small + 2, ctx->small + 2, sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctx->host_small[2] & ST_OVERFLOW)
+        return fail(LENS_EOVERFLOW, "more images than max_img_per_sys in some (sample, system)");
+    return LENS_OK;
+}
+
+lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *ay,
+                               const lens_grid_t *grid, int32_t n_src, const double *src_x,
+                               const double *src_y, const double *f, int32_t kmax, int32_t *nimg,
+                               int64_t *img_tri, double *img_x, double *img_y, void *stream) {
+    if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
+    TRY(check_grid(grid));
+    if (grid->nx < 2 || grid->ny < 2) return fail(LENS_EINVAL, "grid must be at least 2 x 2");
+    if (n_src < 0) return fail(LENS_EINVAL, "n_src < 0");
+    if (kmax < 1 || kmax > 64) return fail(LENS_EINVAL, "kmax = %d (1..64)", kmax);
+    const size_t nv = (size_t)grid->nx * grid->ny;
+    if (ay != ax + nv)
+        return fail(LENS_EINVAL, "ay must follow ax in one buffer (ay == ax + nx*ny)");
+    TRY(check_range(ax, 2 * nv * sizeof(double), "ax/ay"));
+    TRY(check_range(src_x, (size_t)n_src * 8, "src_x"));
+    TRY(check_range(src_y, (size_t)n_src * 8, "src_y"));
+    TRY(check_range(f, (size_t)n_src * 8, "f"));
+    TRY(check_range(nimg, (size_t)n_src * 4, "nimg"));
+    TRY(check_range(img_tri, (size_t)n_src * kmax * 8, "img_tri"));
+    TRY(check_range(img_x, (size_t)n_src * kmax * 8, "img_x"));
+    TRY(check_range(img_y, (size_t)n_src * kmax * 8, "img_y"));
+    if (n_src == 0) return LENS_OK;
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_zero_i32(nimg, n_src, st));
+    HIP_TRY(launch_fill_i64((long long *)img_tri, (size_t)n_src * kmax, -1, st));
+    HIP_TRY(launch_fill_f64(img_x, (size_t)n_src * kmax, NAN, st));
+    HIP_TRY(launch_fill_f64(img_y, (size_t)n_src * kmax, NAN, st));
+    ImgLaunch I;
+    I.alpha = ax;
+    I.grid = GridArgs{grid->nx, grid->ny, grid->x0, grid->y0, grid->dx, grid->dy};
+    I.n_grids = 1;
+    I.nq = n_src;
+    I.sx = src_x;
+    I.sy = src_y;
+    I.f = f;
+    I.kmax = kmax;
+    I.count = nimg;
+    I.tri = (long long *)img_tri;
+    I.ix = img_x;
+    I.iy = img_y;
+    HIP_TRY(launch_find_images(I, st));
+    HIP_TRY(launch_sort_images(n_src, kmax, nimg, (long long *)img_tri, img_x, img_y, st));
+    std::vector<int32_t> cnt(n_src);
+    HIP_TRY(hipMemcpyAsync(cnt.data(), nimg, (size_t)n_src * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int s = 0; s < n_src; ++s)
+        if (cnt[s] > kmax) return fail(LENS_EOVERFLOW, "source %d has %d images > kmax", s, cnt[s]);
+    return LENS_OK;
+}
+
+// ---------------------------------------------------------------------------
+lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *b,
+                                    const lens_catalog_t *c, const lens_chi2_opts_t *o,
+                                    double *chi2, void *stream, lens_chi2_plan_t **out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    *out = nullptr;
+    TRY(check_chi2_args(ctx, b, c, o));
+    if (o->mode != LENS_CHI2_SOURCE)
+        return fail(LENS_EUNSUPPORTED, "captured plans cover the source-plane mode");
+    TRY(check_range(chi2, (size_t)b->n_samples * sizeof(double), "chi2"));
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv;
+    SrcPlan sp = plan_src(cv, b, c, false);
+    TRY(ensure_scratch(ctx, cv.off));
+    TRY(check_contents(ctx, b, c, st));
+    // validate table contents once, outside the capture
+    TRY(status_reset(ctx, st));
+    TRY(run_prologue(ctx, &b->fixed, derived_at(ctx, sp.o_fix, b->fixed.n), st));
+    TRY(run_prologue(ctx, &b->free, derived_at(ctx, sp.o_free, b->free.n), st));
+    TRY(status_check(ctx, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    lens_chi2_plan_t *p = new lens_chi2_plan_t();
+    p->ctx = ctx;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(LENS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    lens_status_t s =
+        src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, chi2, false, st, false);
+    e = hipStreamEndCapture(st, &p->graph);
+    if (s != LENS_OK || e != hipSuccess) {
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        delete p;
+        if (s != LENS_OK) return s;
+        return fail(LENS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(p->graph);
+        delete p;
+        return fail(LENS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return LENS_OK;
+}
+
+lens_status_t lens_chi2_plan_launch(lens_chi2_plan_t *p, void *stream) {
+    if (!p) return fail(LENS_EINVAL, "plan is NULL");
+    DeviceGuard dg(p->ctx->device);
+    HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    return LENS_OK;
+}
+
+lens_status_t lens_chi2_plan_destroy(lens_chi2_plan_t *p) {
+    if (!p) return LENS_OK;
+    DeviceGuard dg(p->ctx->device);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+    return LENS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers.
+// Dls/Ds = 1 - chi(zl)/chi(zs), chi(z) = int_0^z dz'/sqrt(om (1+z')^3 + ol),
+// by 5-point Gauss-Legendre on 512 equal panels.
+static double comoving_gl(double z, double om, double ol) {
+    static const double xg[5] = {-0.9061798459386640, -0.5384693101056831, 0.0,
+                                 0.5384693101056831, 0.9061798459386640};
+    static const double wg[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889,
+                                 0.4786286704993665, 0.2369268850561891};
+    const int panels = 512;
+    const double h = z / panels;
+    double s = 0.0;
+    for (int p = 0; p < panels; ++p) {
+        const double mid = (p + 0.5) * h;
+        for (int g = 0; g < 5; ++g) {
+            const double zz = mid + 0.5 * h * xg[g];
+            const double a = 1.0 + zz;
+            s += wg[g] / sqrt(om * a * a * a + ol);
+        }
+    }
+    return 0.5 * h * s;
+}
+
+lens_status_t lens_dlsds(double zl, double zs, double om, double ol, double *out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    if (!(zl >= 0.0) || !(zs > zl) || !is_fin(zs) || !(om >= 0.0) || !(ol >= 0.0) ||
+        fabs(om + ol - 1.0) > 1e-9)
+        return fail(LENS_EINVAL, "need 0 <= zl < zs and a flat cosmology (om + ol = 1)");
+    *out = 1.0 - comoving_gl(zl, om, ol) / comoving_gl(zs, om, ol);
+    return LENS_OK;
+}
+
+lens_status_t lens_b0_from_sigma(double sigma_kms, int32_t convention, double *out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    if (!(sigma_kms >= 0.0) || !is_fin(sigma_kms) || (convention != 0 && convention != 1))
+        return fail(LENS_EINVAL, "sigma %g, convention %d", sigma_kms, convention);
+    const double v = sigma_kms / 299792.458;
+    *out = (convention == 1 ? 4.0 : 6.0) * M_PI * v * v * (648000.0 / M_PI);
+    return LENS_OK;
+}
+
+lens_status_t lens_eps_from_e(double e, double *out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    if (!(e >= 0.0 && e < 1.0)) return fail(LENS_EINVAL, "e = %g outside [0, 1)", e);
+    *out = e / (1.0 + sqrt(1.0 - e * e));
+    return LENS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// lens_internal.h -- layouts and launch wrappers shared by the library's
+// translation units (device side and host side).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lenshpc.h"
+
+namespace lens {
+
+// ---------------------------------------------------------------------------
+// Derived per-potential constants (output of the parameter prologue).
+//
+// Each potential is a dPIE = F (P_a - P_s): two cored isothermal ellipsoids
+// with cores w = a (rcore) and w = s (rcut), F = s/(s-a).  In the frame of
+// the potential, with q = (1-eps)/(1+eps), k = sqrt(1-q^2) = 2 sqrt(eps)/(1+eps),
+// S_w = (1+eps) w and R = q^2 x'^2 + y'^2, each core has
+//   psi_w = sqrt(q^2 S_w^2 + R),  A_w = psi_w + S_w,  B_w = psi_w + q^2 S_w,
+// deflection  P b0' [atan(k x'/A_w), atanh(k y'/B_w)] (P = (1-eps^2)/(2 sqrt eps))
+// and Hessian b0 (1-eps)/(psi_w D_w) [C_w + y'^2 + S_w psi_w, -x'y',
+// S_w^2 + x'^2 + S_w psi_w], D_w = A_w^2 + k^2 x'^2.
+// The GPU path subtracts the two cores' arctangents and hyperbolic arctangents
+// in closed form (one atan2 and one log1p per potential instead of two of
+// each); psi_s - psi_a is formed as (C_s - C_a)/(psi_a + psi_s), which does not
+// cancel.
+// ---------------------------------------------------------------------------
+enum DerivedIndex : int {
+    D_X0 = 0, D_Y0, D_C, D_S,          // centre, cos(phi), sin(phi)
+    D_C2, D_S2, D_CS, D_CMS,           // c^2, s^2, c s, c^2 - s^2
+    D_Q2,                              // q^2
+    D_CA, D_CS_, D_SA, D_SS,           // C_a = q^2 S_a^2, C_s, S_a, S_s
+    D_Q2SA, D_Q2SS, D_SA2, D_SS2,      // q^2 S_a, q^2 S_s, S_a^2, S_s^2
+    D_K, D_K2,                         // k, k^2
+    D_DC, D_DS, D_Q2DS,                // C_s - C_a, S_s - S_a, q^2 (S_s - S_a)
+    D_PF, D_HF,                        // deflection and Hessian prefactors (F included)
+    D_KIND,                            // kind bits, stored as a small integer value
+    NDER
+};
+// Float copy of the constants used after the FP64 offset/rotation step.
+enum DerivedIndexF : int {
+    F_C2 = 0, F_S2, F_CS, F_CMS, F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS, F_SA2,
+    F_SS2, F_K, F_K2, F_DC, F_DS, F_Q2DS, F_PF, F_HF, NDERF
+};
+
+enum KindBits : int {
+    K_ELL = 1,      // eps > 0: elliptical closed forms
+    K_CUT = 2,      // rcut finite: two cores
+    K_SING = 4,     // rcore == 0: singular centre (zero contribution there)
+    K_INVALID = 8,  // bad parameters: contributes NaN
+};
+
+// Derived table in device memory: double block [NDER][stride], then float
+// block [NDERF][stride].
+struct Derived {
+    const double *d;
+    const float *f;
+    int n;
+    int stride;
+};
+
+inline size_t derived_bytes(int n) {
+    size_t stride = ((size_t)n + 63) / 64 * 64;
+    if (stride == 0) stride = 64;
+    return stride * (NDER * sizeof(double) + NDERF * sizeof(float));
+}
+inline int derived_stride(int n) {
+    int s = (n + 63) / 64 * 64;
+    return s == 0 ? 64 : s;
+}
+
+// Grid point coordinate o + i*d with the product and the sum rounded
+// separately (no fused multiply-add), as the grid definition states.
+__device__ __forceinline__ double grid_coord(double o, int i, double d) {
+#pragma clang fp contract(off)
+    return o + (double)i * d;
+}
+
+struct PotSoA {
+    const double *x0, *y0, *b0, *eps, *phi, *rcore, *rcut;
+};
+
+struct GridArgs {
+    int nx, ny;
+    double x0, y0, dx, dy;
+};
+
+// status word bits written by device code
+enum StatusBits : int { ST_INVALID_TABLE = 1, ST_OVERFLOW = 2 };
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip translation units).  Each returns the
+// HIP error of the launch.
+// ---------------------------------------------------------------------------
+hipError_t launch_zero_i32(int *p, int n, hipStream_t st);
+hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, int *status,
+                           hipStream_t st);
+hipError_t launch_phys_to_amp(const double *sigma, const double *e, int n, int convention,
+                              double *b0, double *eps, int *status, hipStream_t st);
+
+struct MapLaunch {
+    Derived tab;
+    GridArgs grid;
+    double dlsds;
+    void *out[5];  // ax, ay, hxx, hxy, hyy (NULL = not stored)
+    int prec;
+    bool grad, hess;
+    lens_map_tuning_t tune;
+};
+hipError_t launch_map(const MapLaunch &m, hipStream_t st);
+bool map_tuning_valid(const lens_map_tuning_t &t);
+
+// Source-plane chi^2
+struct Chi2SrcLaunch {
+    Derived freet;            // derived free potentials of all samples
+    const int *free_off;      // [S+1]
+    int n_samples;
+    int sample0;              // first sample of this launch (per-sample path)
+    int nsys, nimg;
+    const int *img_off;
+    const double *x, *y, *sig, *f;
+    const double *afix;       // [nchunk][2][nimg_pad] partial fixed deflections
+    int nchunk, nimg_pad;
+    double *chi2;             // [S] or NULL
+    double *src_x, *src_y;    // [S*nsys] barycentric sources, or NULL
+    int *queue;               // batched path: work counter (zeroed before)
+    int persistent;           // 1: pull samples from *queue until exhausted
+    int grid_blocks;
+    int prec;
+};
+hipError_t launch_fixed_alpha_points(Derived fixedt, int nimg, const double *x, const double *y,
+                                     int nchunk, int nimg_pad, double *afix, int prec,
+                                     hipStream_t st);
+hipError_t launch_chi2_src(const Chi2SrcLaunch &c, hipStream_t st);
+
+// Image plane
+// Image search: n_grids deflection grids (grid g at alpha + g*2*nv: x plane
+// then y plane, Dls/Ds = 1), nq sources per grid: source q of grid g at
+// (sx[g*nq+q], sy[g*nq+q]) with Dls/Ds f[q].  Outputs per (g, q).
+struct ImgLaunch {
+    const double *alpha;
+    GridArgs grid;
+    int n_grids, nq;
+    const double *sx, *sy, *f;
+    int kmax;
+    int *count;                // [n_grids*nq]
+    long long *tri;            // [n_grids*nq*kmax]
+    double *ix, *iy;           // [n_grids*nq*kmax]
+};
+hipError_t launch_find_images(const ImgLaunch &L, hipStream_t st);
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
+hipError_t launch_fill_i64(long long *p, size_t n, long long v, hipStream_t st);
+hipError_t launch_sort_images(int n, int kmax, const int *count, long long *tri, double *ix,
+                              double *iy, hipStream_t st);
+
+// Vertex deflection grids for a chunk of samples: out[(s)*2*nv + {0,nv} + v]
+struct AlphaGridLaunch {
+    Derived freet;
+    const int *free_off;
+    int m0, nsamp;             // samples m0 .. m0+nsamp-1
+    GridArgs grid;
+    const double *afix_x, *afix_y; // fixed-potential deflection (nv each) or NULL
+    double *out;
+    int prec;
+};
+hipError_t launch_alpha_grid(const AlphaGridLaunch &L, hipStream_t st);
+
+struct AssignLaunch {
+    int nsamp, nsys, kmax;     // samples m0 .. m0+nsamp-1 of this chunk
+    const int *count;          // [nsamp*nsys]
+    const double *ix, *iy;     // [(s*nsys+i)*kmax + k]
+    const int *img_off;
+    int nimg_total;            // catalogue images (offset clamp)
+    const double *x, *y, *sig;
+    double penalty;
+    int m0;                    // offset of these samples in the outputs
+    double *chi2;              // [S]
+    int *nimg;                 // [S*nsys] or NULL
+    int *nmissing;             // [S] or NULL
+    double *img_xy;            // [S*nsys*kmax*2] or NULL
+    double *part;              // scratch [nsamp*nsys]
+    int *miss;                 // scratch [nsamp*nsys]
+    int *status;
+};
+hipError_t launch_assign(const AssignLaunch &L, hipStream_t st);
+
+}  // namespace lens

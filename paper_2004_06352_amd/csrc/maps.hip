@@ -1,0 +1,314 @@
+// maps.hip -- parameter prologue and the fused deflection / second-derivative
+// map kernel (paper Sec. 4.1 Eq. (10): the map is, at every grid point, the
+// sum over potentials of each potential's derivatives; Sec. 2.4 Eqs. (7)-(9)
+// for the second derivatives).
+//
+// Design (gfx950): one thread per grid point (or pix_per_thread points along
+// x, strided by block_x so that each wave stores 64 consecutive pixels);
+// every lane of the block walks the potentials in index order, so each
+// potential's constants are uniform across the wave.  They are either staged
+// through LDS in chunks (stage = 1, broadcast reads) or read with wave-uniform
+// loads (stage = 0).  Accumulators stay in registers; each output channel is a
+// row-major plane written once with coalesced stores.
+#include <math.h>
+
+#include "eval.h"
+
+namespace lens {
+
+// ---------------------------------------------------------------------------
+__global__ void zero_i32_kernel(int *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_i32(int *p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+__global__ void fill_f64_kernel(double *p, size_t n, double v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void fill_i64_kernel(long long *p, size_t n, long long v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p,
+                       n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i64(long long *p, size_t n, long long v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p,
+                       n, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Physical -> amplitude form.  b0 = K pi (sigma/c)^2 rad in arcsec, K = 6
+// (Lenstool dPIE) or 4 (singular isothermal sphere); eps from e as
+// e / (1 + sqrt(1 - e^2)), the cancellation-free form of (1 - sqrt(1-e^2))/e.
+__global__ void phys_to_amp_kernel(const double *__restrict__ sigma, const double *__restrict__ e,
+                                   int n, double K, double *__restrict__ b0,
+                                   double *__restrict__ eps, int *status) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double c_kms = 299792.458;
+    const double arcsec_per_rad = 648000.0 / M_PI;
+    double v = sigma[k] / c_kms;
+    double ek = e[k];
+    bool ok = (sigma[k] >= 0.0) && isfinite(sigma[k]) && (ek >= 0.0) && (ek < 1.0);
+    b0[k] = ok ? K * M_PI * v * v * arcsec_per_rad : NAN;
+    eps[k] = ok ? ek / (1.0 + sqrt(1.0 - ek * ek)) : NAN;
+    if (!ok) atomicOr(status, ST_INVALID_TABLE);
+}
+
+hipError_t launch_phys_to_amp(const double *sigma, const double *e, int n, int convention,
+                              double *b0, double *eps, int *status, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    double K = convention == 1 ? 4.0 : 6.0;
+    hipLaunchKernelGGL(phys_to_amp_kernel, dim3((n + 255) / 256), dim3(256), 0, st, sigma, e, n, K,
+                       b0, eps, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Parameter prologue: amplitude-form table -> derived constants (FP64 block
+// and its FP32 copy).  Invalid entries get NaN prefactors (their contribution
+// is NaN) and raise ST_INVALID_TABLE.
+__global__ void prologue_kernel(PotSoA in, int n, double *__restrict__ dd, float *__restrict__ df,
+                                int stride, int *status) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double x0 = in.x0[k], y0 = in.y0[k], b0 = in.b0[k], eps = in.eps[k];
+    const double phi = in.phi[k], a = in.rcore[k], s = in.rcut[k];
+    const bool cut = isfinite(s);
+    const bool ok = isfinite(x0) && isfinite(y0) && isfinite(b0) && b0 >= 0.0 &&
+                    isfinite(eps) && eps >= 0.0 && eps < 1.0 && isfinite(phi) &&
+                    isfinite(a) && a >= 0.0 && !isnan(s) && s > a;
+    const bool ell = eps > 0.0;
+    double c = 1.0, sn = 0.0;
+    if (ell) {
+        c = cos(phi);
+        sn = sin(phi);
+    }
+    const double q = (1.0 - eps) / (1.0 + eps), q2 = q * q;
+    const double Sa = (1.0 + eps) * a;
+    const double Ss = cut ? (1.0 + eps) * s : 0.0;
+    const double k1 = ell ? 2.0 * sqrt(eps) / (1.0 + eps) : 0.0;
+    const double F = cut ? s / (s - a) : 1.0;
+    const double om = 1.0 - eps;
+    const double DC = cut ? om * om * ((s - a) * (s + a)) : 0.0;
+    const double DS = cut ? (1.0 + eps) * (s - a) : 0.0;
+    double PF = ell ? F * b0 * (1.0 - eps * eps) / (2.0 * sqrt(eps)) : F * b0;
+    double HF = F * b0 * om;
+    int kind = (ell ? K_ELL : 0) | (cut ? K_CUT : 0) | (a == 0.0 ? K_SING : 0);
+    if (!ok) {
+        PF = NAN;
+        HF = NAN;
+        kind = K_INVALID | K_CUT | K_ELL;
+        atomicOr(status, ST_INVALID_TABLE);
+    }
+    double v[NDER];
+    v[D_X0] = x0;
+    v[D_Y0] = y0;
+    v[D_C] = c;
+    v[D_S] = sn;
+    v[D_C2] = c * c;
+    v[D_S2] = sn * sn;
+    v[D_CS] = c * sn;
+    v[D_CMS] = c * c - sn * sn;
+    v[D_Q2] = q2;
+    v[D_CA] = q2 * Sa * Sa;
+    v[D_CS_] = q2 * Ss * Ss;
+    v[D_SA] = Sa;
+    v[D_SS] = Ss;
+    v[D_Q2SA] = q2 * Sa;
+    v[D_Q2SS] = q2 * Ss;
+    v[D_SA2] = Sa * Sa;
+    v[D_SS2] = Ss * Ss;
+    v[D_K] = k1;
+    v[D_K2] = k1 * k1;
+    v[D_DC] = DC;
+    v[D_DS] = DS;
+    v[D_Q2DS] = q2 * DS;
+    v[D_PF] = PF;
+    v[D_HF] = HF;
+    v[D_KIND] = (double)kind;
+    for (int i = 0; i < NDER; ++i) dd[(size_t)i * stride + k] = v[i];
+    const int map_f[NDERF] = {D_C2, D_S2, D_CS, D_CMS, D_Q2, D_CA, D_CS_, D_SA, D_SS, D_Q2SA,
+                              D_Q2SS, D_SA2, D_SS2, D_K, D_K2, D_DC, D_DS, D_Q2DS, D_PF, D_HF};
+    for (int i = 0; i < NDERF; ++i) df[(size_t)i * stride + k] = (float)v[map_f[i]];
+}
+
+hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, int *status,
+                           hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prologue_kernel, dim3((n + 255) / 256), dim3(256), 0, st, in, n, dd, df,
+                       stride, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The map kernel.
+struct MapArgs {
+    Derived tab;
+    GridArgs g;
+    double dlsds;
+    void *out[5];
+    int chunk;
+};
+
+template <int PREC, bool GRAD, bool HESS, bool STAGE, int PPT>
+__global__ void __launch_bounds__(1024) map_kernel(MapArgs a) {
+    extern __shared__ double lds[];
+    const int bx = blockDim.x, by = blockDim.y;
+    const int i_base = blockIdx.x * bx * PPT + threadIdx.x;
+    const int j = blockIdx.y * by + threadIdx.y;
+    const double y = grid_coord(a.g.y0, j, a.g.dy);
+    double x[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) x[p] = grid_coord(a.g.x0, i_base + p * bx, a.g.dx);
+
+    // accumulators: FP64 (PREC 0, 1) or compensated FP32 (PREC 2)
+    double acc[PPT][5];
+    float fs[PPT][5], fc[PPT][5];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p)
+#pragma unroll
+        for (int ch = 0; ch < 5; ++ch) {
+            acc[p][ch] = 0.0;
+            fs[p][ch] = 0.f;
+            fc[p][ch] = 0.f;
+        }
+
+    const int n = a.tab.n, st = a.tab.stride;
+    auto body = [&](const ConstD cd, const ConstF cf) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            if (PREC == 0) {
+                eval_pot_f64<GRAD, HESS>(cd, x[p], y, acc[p]);
+            } else {
+                float o[5];
+                eval_pot_f32<GRAD, HESS>(cd, cf, x[p], y, o);
+#pragma unroll
+                for (int ch = 0; ch < 5; ++ch) {
+                    const bool used = (ch < 2) ? GRAD : HESS;
+                    if (!used) continue;
+                    if (PREC == 1)
+                        acc[p][ch] += (double)o[ch];
+                    else
+                        neumaier_add(fs[p][ch], fc[p][ch], o[ch]);
+                }
+            }
+        }
+    };
+
+    if (STAGE) {
+        const int chunk = a.chunk;
+        const int nt = bx * by, tid = threadIdx.y * bx + threadIdx.x;
+        float *ldsf = reinterpret_cast<float *>(lds + (size_t)chunk * NDER);
+        for (int k0 = 0; k0 < n; k0 += chunk) {
+            const int cnt = min(chunk, n - k0);
+            __syncthreads();
+            for (int e = tid; e < cnt * NDER; e += nt) {
+                const int ci = e / cnt, kk = e - ci * cnt;
+                lds[kk * NDER + ci] = a.tab.d[(size_t)ci * st + k0 + kk];
+            }
+            if (PREC != 0) {
+                for (int e = tid; e < cnt * NDERF; e += nt) {
+                    const int ci = e / cnt, kk = e - ci * cnt;
+                    ldsf[kk * NDERF + ci] = a.tab.f[(size_t)ci * st + k0 + kk];
+                }
+            }
+            __syncthreads();
+            for (int kk = 0; kk < cnt; ++kk)
+                body(ConstD{lds + kk * NDER, 1}, ConstF{ldsf + kk * NDERF, 1});
+        }
+    } else {
+        for (int k = 0; k < n; ++k) body(ConstD{a.tab.d + k, st}, ConstF{a.tab.f + k, st});
+    }
+
+    if (j >= a.g.ny) return;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int i = i_base + p * bx;
+        if (i >= a.g.nx) continue;
+        const size_t idx = (size_t)j * a.g.nx + i;
+#pragma unroll
+        for (int ch = 0; ch < 5; ++ch) {
+            if (a.out[ch] == nullptr) continue;
+            if (PREC == 0) {
+                static_cast<double *>(a.out[ch])[idx] = a.dlsds * acc[p][ch];
+            } else if (PREC == 1) {
+                static_cast<float *>(a.out[ch])[idx] = (float)(a.dlsds * acc[p][ch]);
+            } else {
+                static_cast<float *>(a.out[ch])[idx] =
+                    (float)(a.dlsds * ((double)fs[p][ch] + (double)fc[p][ch]));
+            }
+        }
+    }
+}
+
+typedef void (*MapKernelFn)(MapArgs);
+
+template <int PREC, bool GRAD, bool HESS>
+static MapKernelFn pick_ppt(bool stage, int ppt) {
+    if (stage) {
+        if (ppt == 1) return map_kernel<PREC, GRAD, HESS, true, 1>;
+        if (ppt == 2) return map_kernel<PREC, GRAD, HESS, true, 2>;
+    } else {
+        if (ppt == 1) return map_kernel<PREC, GRAD, HESS, false, 1>;
+        if (ppt == 2) return map_kernel<PREC, GRAD, HESS, false, 2>;
+    }
+    return nullptr;
+}
+
+template <int PREC>
+static MapKernelFn pick_mode(bool grad, bool hess, bool stage, int ppt) {
+    if (grad && hess) return pick_ppt<PREC, true, true>(stage, ppt);
+    if (grad) return pick_ppt<PREC, true, false>(stage, ppt);
+    if (hess) return pick_ppt<PREC, false, true>(stage, ppt);
+    return nullptr;
+}
+
+bool map_tuning_valid(const lens_map_tuning_t &t) {
+    if (t.block_x <= 0 || t.block_x % 64 != 0 || t.block_y <= 0) return false;
+    if ((long long)t.block_x * t.block_y > 1024) return false;
+    if (t.pix_per_thread != 1 && t.pix_per_thread != 2) return false;
+    if (t.stage != 0 && t.stage != 1) return false;
+    if (t.stage == 1 && (t.lds_chunk < 1 || t.lds_chunk > 256)) return false;
+    return true;
+}
+
+hipError_t launch_map(const MapLaunch &m, hipStream_t st) {
+    const lens_map_tuning_t &t = m.tune;
+    MapKernelFn fn = nullptr;
+    const bool stage = t.stage == 1;
+    if (m.prec == 0) fn = pick_mode<0>(m.grad, m.hess, stage, t.pix_per_thread);
+    if (m.prec == 1) fn = pick_mode<1>(m.grad, m.hess, stage, t.pix_per_thread);
+    if (m.prec == 2) fn = pick_mode<2>(m.grad, m.hess, stage, t.pix_per_thread);
+    if (!fn) return hipErrorInvalidValue;
+    MapArgs a;
+    a.tab = m.tab;
+    a.g = m.grid;
+    a.dlsds = m.dlsds;
+    for (int c = 0; c < 5; ++c) a.out[c] = m.out[c];
+    a.chunk = t.lds_chunk;
+    const long long span_x = (long long)t.block_x * t.pix_per_thread;
+    dim3 grid((unsigned)((m.grid.nx + span_x - 1) / span_x),
+              (unsigned)((m.grid.ny + t.block_y - 1) / t.block_y));
+    if (grid.y > 65535u) return hipErrorInvalidConfiguration;
+    dim3 block(t.block_x, t.block_y);
+    size_t shmem = 0;
+    if (stage) shmem = (size_t)t.lds_chunk * (NDER * sizeof(double) + NDERF * sizeof(float));
+    hipLaunchKernelGGL(fn, grid, block, shmem, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace lens
