@@ -160,6 +160,17 @@ def main():
         secondary["chi2_source_graph_samples_per_s"] = S * 20 / w
         secondary["chi2_source_workload"] = c3["name"]
         plan.close()
+        # image-plane chi^2: 1000^2 grid, 512 samples of the same model
+        c4 = inputs.config4()
+        off4 = torch.as_tensor(c4["free_off"], dtype=torch.int32, device="cuda")
+        free4 = B.table_from_physical(B.to_device(c4["free"], B.PHYS_KEYS), 0, ctx)
+        S4 = int(off4.numel()) - 1
+        for name, prec in (("fp64", B.FP64), ("fp32_acc64", B.FP32_ACC64)):
+            w, e = timed_steps(lambda: B.chi2_batch(fixed, free4, off4, cat, mode=B.CHI2_IMAGE,
+                                                    prec=prec, grid=c4["grid"], kmax=64,
+                                                    penalty=100.0, ctx=ctx), 3, 1, torch)
+            secondary[f"chi2_image_{name}_samples_per_s"] = S4 * 3 / w
+        secondary["chi2_image_workload"] = c4["name"]
     rec["secondary"] = secondary
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -174,7 +174,7 @@ typedef struct {
 
 /* Launch configuration of the map kernel (chosen by the autotuner).
  * block_x * block_y threads per block (block_x a multiple of 64, product
- * <= 1024), each thread evaluating pix_per_thread points along x;
+ * <= 256), each thread evaluating pix_per_thread points along x;
  * stage = 1 stages the derived potential constants in LDS in chunks of
  * lds_chunk potentials, stage = 0 reads them with wave-uniform loads. */
 typedef struct {

@@ -10,10 +10,25 @@
 // parameters, summed per Sec. 4.1 Eq. (10) and Sec. 2.4 Eqs. (7)-(9)):
 //   two cores a < s combine as F (P_a - P_s); the arctangent and hyperbolic
 //   arctangent differences use
-//     atan(kx/A_a) - atan(kx/A_s)   = atan2(k x (A_s - A_a), A_a A_s + k^2 x^2)
+//     atan(kx/A_a) - atan(kx/A_s)   = atan(k x (A_s - A_a) / (A_a A_s + k^2 x^2))
 //     atanh(ky/B_a) - atanh(ky/B_s) = atanh(k y (B_s - B_a) / (B_a B_s - k^2 y^2))
-//   (both arguments have the same sign, so no branch correction is needed),
-//   and atanh(z) = log1p(2z/(1-z))/2.  A_s - A_a = (C_s-C_a)/(psi_a+psi_s) + (S_s-S_a).
+//   (both arguments have the same sign, so no branch correction is needed).
+//   A_s - A_a = (C_s - C_a)/(psi_a + psi_s) + (S_s - S_a), which does not cancel.
+//
+// Arithmetic (FP64 path).  The accuracy target is a few units in the last
+// place, far inside the 1e-12 relative tolerance of the map, so the path uses
+// no correctly-rounded division or square root:
+//   - 1/sqrt(x) and 1/x start from the hardware estimates (v_rsq_f64,
+//     v_rcp_f64) and take two Newton steps each;
+//   - reciprocals needed at the same time share one reciprocal of their
+//     product (1/a = b/(ab), 1/b = a/(ab));
+//   - atan(N/D) is reduced to |b| <= tan(pi/16) with atan(t) = pi/2 -
+//     atan(1/t) and a shift to the nearest of three centres, then summed as
+//     the Taylor series b - b^3/3 + ... to b^21/21 (truncation below 2e-17 b);
+//   - atanh(N/D) = ln(P/Q)/2, P = D + N, Q = D - N, is reduced by the binary
+//     exponent k of P/Q to ln(P/Q) = k ln 2 + 2 atanh(s), s = (P 2^-k - Q) /
+//     (P 2^-k + Q) (s = N/D exactly when k = 0), |s| <= 3 - 2 sqrt(2), and
+//     atanh(s) = s + s^3/3 + ... to s^19/19.
 #pragma once
 
 #include "lens_internal.h"
@@ -37,6 +52,110 @@ __device__ __forceinline__ int uniform_kind(double k) {
     return __builtin_amdgcn_readfirstlane((int)k);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 building blocks
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(e, r, r);
+    e = fma(-x, r, 1.0);
+    return fma(e, r, r);
+}
+
+__device__ __forceinline__ double rsq64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h, y * y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h, y * y, 0.5);
+    return fma(y, e, y);
+}
+
+constexpr double kPi2 = 1.5707963267948966;
+constexpr double kPi4 = 0.7853981633974483;
+constexpr double kSqrt2 = 1.4142135623730951;
+constexpr double kLn2 = 0.6931471805599453;
+
+// atan(N/D), D > 0: t = min/max of |N|, D in [0, 1] is shifted to the
+// nearest of the centres c = 0, tan(pi/8), 1 by atan(t) = atan(c) +
+// atan((t - c)/(1 + t c)) (exact for the rounded centre, whose arctangent is
+// the stored constant), leaving |b| <= tan(pi/16); then atan(|N|/D) =
+// pi/2 - atan(D/|N|) when |N| > D.  Series to b^21/21 (truncation below
+// 2e-17 b).
+constexpr double kTanPi16 = 0.198912367379658;
+constexpr double kTan3Pi16 = 0.6681786379192989;
+constexpr double kC1 = 0.41421356237309503;       // tan(pi/8), rounded
+constexpr double kAtanC1 = 0.39269908169872414;   // atan of the rounded value
+struct AtanRed {
+    double num, den, base;
+    bool big;
+    double sign;
+};
+__device__ __forceinline__ AtanRed atan_reduce(double N, double D) {
+    const double u = fabs(N);
+    const bool big = u > D;
+    const double lo = big ? D : u, hi = big ? u : D;
+    const bool m1 = lo > kTanPi16 * hi, m2 = lo > kTan3Pi16 * hi;
+    const double c = m2 ? 1.0 : (m1 ? kC1 : 0.0);
+    AtanRed r;
+    r.num = fma(-c, hi, lo);
+    r.den = fma(c, lo, hi);
+    r.base = m2 ? kPi4 : (m1 ? kAtanC1 : 0.0);
+    r.big = big;
+    r.sign = N;
+    return r;
+}
+__device__ __forceinline__ double atan_finish(const AtanRed &r, double b) {
+    const double b2 = b * b;
+    double p = 1.0 / 21.0;
+    p = fma(p, b2, -1.0 / 19.0);
+    p = fma(p, b2, 1.0 / 17.0);
+    p = fma(p, b2, -1.0 / 15.0);
+    p = fma(p, b2, 1.0 / 13.0);
+    p = fma(p, b2, -1.0 / 11.0);
+    p = fma(p, b2, 1.0 / 9.0);
+    p = fma(p, b2, -1.0 / 7.0);
+    p = fma(p, b2, 1.0 / 5.0);
+    p = fma(p, b2, -1.0 / 3.0);
+    double t = fma(b * b2, p, b) + r.base;
+    t = r.big ? kPi2 - t : t;
+    return copysign(t, r.sign);
+}
+
+// atanh(N/D) for |N| < D: reduction of ln((D+N)/(D-N)).
+struct AtanhRed {
+    double num, den;
+    int k;
+};
+__device__ __forceinline__ AtanhRed atanh_reduce(double N, double D) {
+    const double P = D + N, Q = D - N;
+    const double mp = __builtin_amdgcn_frexp_mant(P), mq = __builtin_amdgcn_frexp_mant(Q);
+    int k = __builtin_amdgcn_frexp_exp(P) - __builtin_amdgcn_frexp_exp(Q);
+    k += (mp > kSqrt2 * mq) ? 1 : 0;
+    k -= (mq > kSqrt2 * mp) ? 1 : 0;
+    const double Pk = __builtin_amdgcn_ldexp(P, -k);
+    AtanhRed r;
+    r.num = (k == 0) ? 2.0 * N : Pk - Q;
+    r.den = Pk + Q;
+    r.k = k;
+    return r;
+}
+__device__ __forceinline__ double atanh_finish(const AtanhRed &r, double s) {
+    const double s2 = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double t = fma(s * s2, p, s);
+    return fma(0.5 * kLn2, (double)r.k, t);
+}
+
+// ---------------------------------------------------------------------------
 template <bool GRAD, bool HESS>
 __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y, double acc[5]) {
     const int kind = uniform_kind(c[D_KIND]);
@@ -51,58 +170,107 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
     const double xp = dx * cp + dy * sp;
     const double yp = dy * cp - dx * sp;
     const double x2 = xp * xp, y2 = yp * yp;
-    const double R = c[D_Q2] * x2 + y2;
+    const double R = fma(c[D_Q2], x2, y2);
     double ax = 0.0, ay = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
     if (kind & K_CUT) {
-        const double pa = sqrt(c[D_CA] + R);
-        const double ps = sqrt(c[D_CS_] + R);
+        const double ta = c[D_CA] + R, ts = c[D_CS_] + R;
+        const double ra = rsq64(ta), rs = rsq64(ts);
+        const double pa = ta * ra, ps = ts * rs;
         const double A1 = pa + c[D_SA], A2 = ps + c[D_SS];
-        if (GRAD) {
-            const double g = c[D_DC] / (pa + ps);
-            if (kind & K_ELL) {
-                const double B1 = pa + c[D_Q2SA], B2 = ps + c[D_Q2SS];
-                const double k = c[D_K], k2 = c[D_K2];
-                const double Nx = k * xp * (g + c[D_DS]);
-                const double Dx = A1 * A2 + k2 * x2;
-                const double Ny = k * yp * (g + c[D_Q2DS]);
-                const double Dy = B1 * B2 - k2 * y2;
-                ax = c[D_PF] * atan2(Nx, Dx);
-                ay = 0.5 * c[D_PF] * log1p(2.0 * Ny / (Dy - Ny));
+        const double sum = pa + ps;
+        double inv_sum, iDa = 0.0, iDs = 0.0;
+        if (kind & K_ELL) {
+            const double k2x2 = c[D_K2] * x2;
+            if (HESS) {
+                const double Da = fma(A1, A1, k2x2), Ds = fma(A2, A2, k2x2);
+                const double DD = Da * Ds;
+                const double R1 = rcp64(sum * DD);
+                inv_sum = R1 * DD;
+                const double t = R1 * sum;
+                iDa = t * Ds;
+                iDs = t * Da;
             } else {
-                const double t = c[D_PF] * (g + c[D_DS]) / (A1 * A2);
+                inv_sum = rcp64(sum);
+            }
+            if (GRAD) {
+                const double g = c[D_DC] * inv_sum;
+                const double k = c[D_K];
+                const double B1 = pa + c[D_Q2SA], B2 = ps + c[D_Q2SS];
+                const double Nx = k * xp * (g + c[D_DS]);
+                const double Dx = fma(A1, A2, k2x2);
+                const double Ny = k * yp * (g + c[D_Q2DS]);
+                const double Dy = fma(B1, B2, -c[D_K2] * y2);
+                const AtanRed ra_ = atan_reduce(Nx, Dx);
+                const AtanhRed rh = atanh_reduce(Ny, Dy);
+                const double R2 = rcp64(ra_.den * rh.den);
+                const double b = ra_.num * (R2 * rh.den);
+                const double s = rh.num * (R2 * ra_.den);
+                ax = c[D_PF] * atan_finish(ra_, b);
+                ay = c[D_PF] * atanh_finish(rh, s);
+            }
+        } else {
+            // circular: k = 0, D_w = A_w^2
+            const double A12 = A1 * A2;
+            const double R1 = rcp64(sum * A12);
+            inv_sum = R1 * A12;
+            const double i12 = R1 * sum;
+            if (HESS) {
+                const double iA1 = i12 * A2, iA2 = i12 * A1;
+                iDa = iA1 * iA1;
+                iDs = iA2 * iA2;
+            }
+            if (GRAD) {
+                const double g = c[D_DC] * inv_sum;
+                const double t = c[D_PF] * (g + c[D_DS]) * i12;
                 ax = t * xp;
                 ay = t * yp;
             }
         }
         if (HESS) {
-            const double k2x2 = c[D_K2] * x2;
-            const double Da = A1 * A1 + k2x2, Ds = A2 * A2 + k2x2;
-            const double ha = c[D_HF] / (pa * Da), hs = c[D_HF] / (ps * Ds);
-            hxx = ha * (c[D_CA] + y2 + c[D_SA] * pa) - hs * (c[D_CS_] + y2 + c[D_SS] * ps);
-            hyy = ha * (c[D_SA2] + x2 + c[D_SA] * pa) - hs * (c[D_SS2] + x2 + c[D_SS] * ps);
+            const double ha = c[D_HF] * ra * iDa, hs = c[D_HF] * rs * iDs;
+            const double sa = c[D_SA] * pa, ss = c[D_SS] * ps;
+            hxx = ha * (c[D_CA] + y2 + sa) - hs * (c[D_CS_] + y2 + ss);
+            hyy = ha * (c[D_SA2] + x2 + sa) - hs * (c[D_SS2] + x2 + ss);
             hxy = -xp * yp * (ha - hs);
         }
     } else {
-        const double pa = sqrt(c[D_CA] + R);
+        const double ta = c[D_CA] + R;
+        const double ra = rsq64(ta);
+        const double pa = ta * ra;
         const double A1 = pa + c[D_SA];
-        if (GRAD) {
-            if (kind & K_ELL) {
-                const double k = c[D_K];
+        double iDa = 0.0;
+        if (kind & K_ELL) {
+            const double k = c[D_K];
+            const double Da = fma(A1, A1, c[D_K2] * x2);
+            if (GRAD) {
                 const double B1 = pa + c[D_Q2SA];
-                const double ky = k * yp;
-                ax = c[D_PF] * atan2(k * xp, A1);
-                ay = 0.5 * c[D_PF] * log1p(2.0 * ky / (B1 - ky));
-            } else {
-                const double t = c[D_PF] / A1;
+                const AtanRed ra_ = atan_reduce(k * xp, A1);
+                const AtanhRed rh = atanh_reduce(k * yp, B1);
+                const double den = ra_.den * rh.den;
+                const double R2 = rcp64(HESS ? den * Da : den);
+                const double RD = HESS ? R2 * Da : R2;
+                const double b = ra_.num * (RD * rh.den);
+                const double s = rh.num * (RD * ra_.den);
+                if (HESS) iDa = R2 * den;
+                ax = c[D_PF] * atan_finish(ra_, b);
+                ay = c[D_PF] * atanh_finish(rh, s);
+            } else if (HESS) {
+                iDa = rcp64(Da);
+            }
+        } else {
+            const double iA1 = rcp64(A1);
+            if (GRAD) {
+                const double t = c[D_PF] * iA1;
                 ax = t * xp;
                 ay = t * yp;
             }
+            iDa = iA1 * iA1;
         }
         if (HESS) {
-            const double Da = A1 * A1 + c[D_K2] * x2;
-            const double ha = c[D_HF] / (pa * Da);
-            hxx = ha * (c[D_CA] + y2 + c[D_SA] * pa);
-            hyy = ha * (c[D_SA2] + x2 + c[D_SA] * pa);
+            const double ha = c[D_HF] * ra * iDa;
+            const double sa = c[D_SA] * pa;
+            hxx = ha * (c[D_CA] + y2 + sa);
+            hyy = ha * (c[D_SA2] + x2 + sa);
             hxy = -xp * yp * ha;
         }
     }
@@ -120,7 +288,68 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 building blocks: native reciprocal and reciprocal square root (about
+// one unit in the last place), the same reductions, series to b^9/9
+// (truncation below 1e-8 b).
 __device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ float frsq(float v) { return __builtin_amdgcn_rsqf(v); }
+
+struct AtanRedF {
+    float num, den, base;
+    bool big;
+    float sign;
+};
+__device__ __forceinline__ AtanRedF atan_reduce_f(float N, float D) {
+    const float u = fabsf(N);
+    const bool big = u > D;
+    const float lo = big ? D : u, hi = big ? u : D;
+    const bool m1 = lo > 0.19891237f * hi, m2 = lo > 0.66817864f * hi;
+    const float c = m2 ? 1.0f : (m1 ? 0.41421356f : 0.0f);
+    AtanRedF r;
+    r.num = fmaf(-c, hi, lo);
+    r.den = fmaf(c, lo, hi);
+    r.base = m2 ? 0.78539816f : (m1 ? 0.39269908f : 0.0f);
+    r.big = big;
+    r.sign = N;
+    return r;
+}
+__device__ __forceinline__ float atan_finish_f(const AtanRedF &r, float b) {
+    const float b2 = b * b;
+    float p = 1.0f / 9.0f;
+    p = fmaf(p, b2, -1.0f / 7.0f);
+    p = fmaf(p, b2, 1.0f / 5.0f);
+    p = fmaf(p, b2, -1.0f / 3.0f);
+    float t = fmaf(b * b2, p, b) + r.base;
+    t = r.big ? 1.57079633f - t : t;
+    return copysignf(t, r.sign);
+}
+struct AtanhRedF {
+    float num, den;
+    int k;
+};
+__device__ __forceinline__ AtanhRedF atanh_reduce_f(float N, float D) {
+    const float P = D + N, Q = D - N;
+    const float mp = __builtin_amdgcn_frexp_mantf(P), mq = __builtin_amdgcn_frexp_mantf(Q);
+    int k = __builtin_amdgcn_frexp_expf(P) - __builtin_amdgcn_frexp_expf(Q);
+    k += (mp > 1.41421356f * mq) ? 1 : 0;
+    k -= (mq > 1.41421356f * mp) ? 1 : 0;
+    const float Pk = __builtin_amdgcn_ldexpf(P, -k);
+    AtanhRedF r;
+    r.num = (k == 0) ? 2.0f * N : Pk - Q;
+    r.den = Pk + Q;
+    r.k = k;
+    return r;
+}
+__device__ __forceinline__ float atanh_finish_f(const AtanhRedF &r, float s) {
+    const float s2 = s * s;
+    float p = 1.0f / 9.0f;
+    p = fmaf(p, s2, 1.0f / 7.0f);
+    p = fmaf(p, s2, 1.0f / 5.0f);
+    p = fmaf(p, s2, 1.0f / 3.0f);
+    const float t = fmaf(s * s2, p, s);
+    return fmaf(0.34657359f, (float)r.k, t);
+}
 
 // FP32 evaluation: offset and rotation in FP64 (|x| ~ 100" would lose
 // ~1e-5" if formed in FP32), the rest in FP32.  out[] receives this
@@ -140,58 +369,85 @@ __device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, dou
     const float xp = (float)(dx * cpd + dy * spd);
     const float yp = (float)(dy * cpd - dx * spd);
     const float x2 = xp * xp, y2 = yp * yp;
-    const float R = f[F_Q2] * x2 + y2;
+    const float R = fmaf(f[F_Q2], x2, y2);
     float ax = 0.f, ay = 0.f, hxx = 0.f, hxy = 0.f, hyy = 0.f;
     if (kind & K_CUT) {
-        const float pa = __builtin_sqrtf(f[F_CA] + R);
-        const float ps = __builtin_sqrtf(f[F_CS_] + R);
+        const float ta = f[F_CA] + R, ts = f[F_CS_] + R;
+        const float ra = frsq(ta), rs = frsq(ts);
+        const float pa = ta * ra, ps = ts * rs;
         const float A1 = pa + f[F_SA], A2 = ps + f[F_SS];
-        if (GRAD) {
-            const float g = f[F_DC] * frcp(pa + ps);
-            if (kind & K_ELL) {
+        const float inv_sum = frcp(pa + ps);
+        float iDa = 0.f, iDs = 0.f;
+        if (kind & K_ELL) {
+            const float k2x2 = f[F_K2] * x2;
+            if (HESS) {
+                iDa = frcp(fmaf(A1, A1, k2x2));
+                iDs = frcp(fmaf(A2, A2, k2x2));
+            }
+            if (GRAD) {
+                const float g = f[F_DC] * inv_sum;
+                const float k = f[F_K];
                 const float B1 = pa + f[F_Q2SA], B2 = ps + f[F_Q2SS];
-                const float k = f[F_K], k2 = f[F_K2];
                 const float Nx = k * xp * (g + f[F_DS]);
-                const float Dx = A1 * A2 + k2 * x2;
+                const float Dx = fmaf(A1, A2, k2x2);
                 const float Ny = k * yp * (g + f[F_Q2DS]);
-                const float Dy = B1 * B2 - k2 * y2;
-                ax = f[F_PF] * atan2f(Nx, Dx);
-                ay = 0.5f * f[F_PF] * log1pf(2.0f * Ny * frcp(Dy - Ny));
-            } else {
-                const float t = f[F_PF] * (g + f[F_DS]) * frcp(A1 * A2);
+                const float Dy = fmaf(B1, B2, -f[F_K2] * y2);
+                const AtanRedF ra_ = atan_reduce_f(Nx, Dx);
+                const AtanhRedF rh = atanh_reduce_f(Ny, Dy);
+                ax = f[F_PF] * atan_finish_f(ra_, ra_.num * frcp(ra_.den));
+                ay = f[F_PF] * atanh_finish_f(rh, rh.num * frcp(rh.den));
+            }
+        } else {
+            const float i12 = frcp(A1 * A2);
+            if (HESS) {
+                const float iA1 = i12 * A2, iA2 = i12 * A1;
+                iDa = iA1 * iA1;
+                iDs = iA2 * iA2;
+            }
+            if (GRAD) {
+                const float g = f[F_DC] * inv_sum;
+                const float t = f[F_PF] * (g + f[F_DS]) * i12;
                 ax = t * xp;
                 ay = t * yp;
             }
         }
         if (HESS) {
-            const float k2x2 = f[F_K2] * x2;
-            const float Da = A1 * A1 + k2x2, Ds = A2 * A2 + k2x2;
-            const float ha = f[F_HF] * frcp(pa * Da), hs = f[F_HF] * frcp(ps * Ds);
-            hxx = ha * (f[F_CA] + y2 + f[F_SA] * pa) - hs * (f[F_CS_] + y2 + f[F_SS] * ps);
-            hyy = ha * (f[F_SA2] + x2 + f[F_SA] * pa) - hs * (f[F_SS2] + x2 + f[F_SS] * ps);
+            const float ha = f[F_HF] * ra * iDa, hs = f[F_HF] * rs * iDs;
+            const float sa = f[F_SA] * pa, ss = f[F_SS] * ps;
+            hxx = ha * (f[F_CA] + y2 + sa) - hs * (f[F_CS_] + y2 + ss);
+            hyy = ha * (f[F_SA2] + x2 + sa) - hs * (f[F_SS2] + x2 + ss);
             hxy = -xp * yp * (ha - hs);
         }
     } else {
-        const float pa = __builtin_sqrtf(f[F_CA] + R);
+        const float ta = f[F_CA] + R;
+        const float ra = frsq(ta);
+        const float pa = ta * ra;
         const float A1 = pa + f[F_SA];
-        if (GRAD) {
-            if (kind & K_ELL) {
-                const float k = f[F_K];
+        float iDa = 0.f;
+        if (kind & K_ELL) {
+            const float k = f[F_K];
+            if (GRAD) {
                 const float B1 = pa + f[F_Q2SA];
-                const float ky = k * yp;
-                ax = f[F_PF] * atan2f(k * xp, A1);
-                ay = 0.5f * f[F_PF] * log1pf(2.0f * ky * frcp(B1 - ky));
-            } else {
-                const float t = f[F_PF] * frcp(A1);
+                const AtanRedF ra_ = atan_reduce_f(k * xp, A1);
+                const AtanhRedF rh = atanh_reduce_f(k * yp, B1);
+                ax = f[F_PF] * atan_finish_f(ra_, ra_.num * frcp(ra_.den));
+                ay = f[F_PF] * atanh_finish_f(rh, rh.num * frcp(rh.den));
+            }
+            if (HESS) iDa = frcp(fmaf(A1, A1, f[F_K2] * x2));
+        } else {
+            const float iA1 = frcp(A1);
+            if (GRAD) {
+                const float t = f[F_PF] * iA1;
                 ax = t * xp;
                 ay = t * yp;
             }
+            iDa = iA1 * iA1;
         }
         if (HESS) {
-            const float Da = A1 * A1 + f[F_K2] * x2;
-            const float ha = f[F_HF] * frcp(pa * Da);
-            hxx = ha * (f[F_CA] + y2 + f[F_SA] * pa);
-            hyy = ha * (f[F_SA2] + x2 + f[F_SA] * pa);
+            const float ha = f[F_HF] * ra * iDa;
+            const float sa = f[F_SA] * pa;
+            hxx = ha * (f[F_CA] + y2 + sa);
+            hyy = ha * (f[F_SA2] + x2 + sa);
             hxy = -xp * yp * ha;
         }
     }

@@ -165,7 +165,7 @@ struct MapArgs {
 };
 
 template <int PREC, bool GRAD, bool HESS, bool STAGE, int PPT>
-__global__ void __launch_bounds__(1024) map_kernel(MapArgs a) {
+__global__ void __launch_bounds__(256) map_kernel(MapArgs a) {
     extern __shared__ double lds[];
     const int bx = blockDim.x, by = blockDim.y;
     const int i_base = blockIdx.x * bx * PPT + threadIdx.x;
@@ -279,7 +279,7 @@ static MapKernelFn pick_mode(bool grad, bool hess, bool stage, int ppt) {
 
 bool map_tuning_valid(const lens_map_tuning_t &t) {
     if (t.block_x <= 0 || t.block_x % 64 != 0 || t.block_y <= 0) return false;
-    if ((long long)t.block_x * t.block_y > 1024) return false;
+    if ((long long)t.block_x * t.block_y > 256) return false;
     if (t.pix_per_thread != 1 && t.pix_per_thread != 2) return false;
     if (t.stage != 0 && t.stage != 1) return false;
     if (t.stage == 1 && (t.lds_chunk < 1 || t.lds_chunk > 256)) return false;

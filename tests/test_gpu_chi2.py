@@ -1,0 +1,166 @@
+"""GPU parity of the source-plane chi^2 batch against the FP64 oracle, through
+the C ABI: batched (persistent, device work queue), per-sample launches and a
+captured HIP graph, on even and uneven sample sizes."""
+import numpy as np
+import pytest
+
+from lensutil import RTOL, chi2_source_bound
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_06352_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context(0, check=True)
+
+
+def device_model(B, ctx, c):
+    fixed = B.table_from_physical(B.to_device(c["fixed"], B.PHYS_KEYS), 0, ctx)
+    free = B.table_from_physical(B.to_device(c["free"], B.PHYS_KEYS), 0, ctx)
+    off = torch.as_tensor(c["free_off"], dtype=torch.int32, device="cuda")
+    return fixed, free, off
+
+
+def oracle_model(O, c):
+    return O.phys_to_pots(c["fixed"]), O.phys_to_pots(c["free"]), c["free_off"]
+
+
+def gpu_catalog(B, c):
+    return B.catalog_to_device(B.catalog_with_dlsds(c["catalog"], c["zl"]))
+
+
+def check_samples(O, c, got, samples, rtol):
+    fixed, free, off = oracle_model(O, c)
+    cat = O.catalog_f(c["catalog"], c["zl"])
+    sub_off = []
+    sub_free = {k: [] for k in free}
+    for m in samples:
+        for k in free:
+            sub_free[k].append(free[k][off[m]:off[m + 1]])
+    sub_free = {k: np.concatenate(v) for k, v in sub_free.items()}
+    sizes = [off[m + 1] - off[m] for m in samples]
+    sub_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    ref = O.chi2_source(fixed, sub_free, sub_off, cat)
+    for r, m in enumerate(samples):
+        bx, by, sabs = O.unlens(fixed, sub_free, sub_off, r, cat)
+        bound = chi2_source_bound(bx, by, sabs, cat, rtol)
+        assert abs(got[m] - ref[r]) <= bound, (m, got[m], ref[r], bound)
+    return ref
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_source_chi2_matches_oracle(B, ctx, oracle, prec):
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=192)
+    fixed, free, off = device_model(B, ctx, c)
+    res = B.chi2_batch(fixed, free, off, gpu_catalog(B, c), prec=prec, ctx=ctx)
+    torch.cuda.synchronize()
+    got = res["chi2"].cpu().numpy()
+    check_samples(oracle, c, got, list(range(192)), RTOL[prec])
+
+
+def test_paths_agree_bit_for_bit_on_uneven_samples(B, ctx, oracle):
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=300, uneven=True)
+    sizes = np.diff(c["free_off"])
+    assert sizes.min() < sizes.max()
+    fixed, free, off = device_model(B, ctx, c)
+    cat = gpu_catalog(B, c)
+    a = B.chi2_batch(fixed, free, off, cat, path=B.PATH_BATCHED, ctx=ctx)["chi2"]
+    b = B.chi2_batch(fixed, free, off, cat, path=B.PATH_PER_SAMPLE, ctx=ctx)["chi2"]
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    check_samples(oracle, c, a.cpu().numpy(), list(range(0, 300, 7)), RTOL[0])
+
+
+def test_samples_without_free_potentials_and_empty_batch(B, ctx, oracle):
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=4)
+    # sample 1 and 3 keep no free potential at all
+    free, off = c["free"], c["free_off"]
+    keep = np.r_[off[0]:off[1], off[2]:off[3]]
+    c["free"] = {k: v[keep] for k, v in free.items()}
+    n0 = off[1] - off[0]
+    c["free_off"] = np.array([0, n0, n0, len(keep), len(keep)], np.int32)
+    fixed, freet, offt = device_model(B, ctx, c)
+    got = B.chi2_batch(fixed, freet, offt, gpu_catalog(B, c), ctx=ctx)["chi2"].cpu().numpy()
+    ref = check_samples(oracle, c, got, [0, 1, 2, 3], RTOL[0])
+    assert got[1] == got[3]
+    # an empty batch is a valid no-op
+    empty_off = torch.zeros(1, dtype=torch.int32, device="cuda")
+    empty = {k: v[:0] for k, v in freet.items()}
+    r = B.chi2_batch(fixed, empty, empty_off, gpu_catalog(B, c), ctx=ctx)
+    assert r["chi2"].numel() == 0
+
+
+def test_captured_graph_replays_equal_eager(B, ctx):
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=256, uneven=True)
+    fixed, free, off = device_model(B, ctx, c)
+    cat = gpu_catalog(B, c)
+    eager = B.chi2_batch(fixed, free, off, cat, ctx=ctx)["chi2"].clone()
+    plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx)
+    for r in range(4):
+        plan.chi2.fill_(-1.0)
+        out = plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {r}"
+        # eager work between replays
+        x = torch.randn(1000, device="cuda").sum()
+        B.chi2_batch(fixed, free, off, cat, ctx=ctx)
+        torch.cuda.synchronize()
+        del x
+    # a replay sees new parameter values in the same buffers
+    free["x0"].add_(0.25)
+    out = plan.launch()
+    new = B.chi2_batch(fixed, free, off, cat, ctx=ctx)["chi2"]
+    torch.cuda.synchronize()
+    assert torch.equal(out, new) and not torch.equal(out, eager)
+    plan.close()
+
+
+def test_full_config3_batch_sampled(B, ctx, oracle):
+    """All 4096 samples on the GPU in the benchmark's launch configuration
+    (unchecked context, batched path); 48 sampled samples against the oracle."""
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3()
+    uctx = B.Context(0, check=False)
+    fixed, free, off = device_model(B, uctx, c)
+    got = B.chi2_batch(fixed, free, off, gpu_catalog(B, c), ctx=uctx)["chi2"].cpu().numpy()
+    uctx.status()
+    rng = np.random.default_rng(33)
+    samples = sorted(set([0, 4095] + list(rng.integers(0, 4096, 46))))
+    check_samples(oracle, c, got, samples, RTOL[0])
+    uctx.close()
+
+
+def test_invalid_catalogue_rejected(B, ctx):
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=2)
+    fixed, free, off = device_model(B, ctx, c)
+    cat = gpu_catalog(B, c)
+    bad = dict(cat)
+    bad["sig"] = cat["sig"].clone()
+    bad["sig"][3] = 0.0
+    with pytest.raises(B.LensError):
+        B.chi2_batch(fixed, free, off, bad, ctx=ctx)
+    bad = dict(cat)
+    bad["off"] = cat["off"].clone()
+    bad["off"][5] = bad["off"][4] - 1
+    with pytest.raises(B.LensError):
+        B.chi2_batch(fixed, free, off, bad, ctx=ctx)
+    badoff = off.clone()
+    badoff[-1] += 1
+    with pytest.raises(B.LensError):
+        B.chi2_batch(fixed, free, badoff, cat, ctx=ctx)
