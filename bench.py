@@ -75,6 +75,33 @@ def cpu_baseline_map(c, budget_s=12.0):
                        f"5 channels, {dt:.1f} s")
 
 
+def bench_serving(map_rate, chi2_rate, n_requests):
+    """Poisson stream of mixed map / chi^2 requests at 0.7x the single-stream
+    capacity estimated from the measured map and chi^2 rates; served with 4
+    slots and chi^2 merging, then the same stream on the plain path (one
+    request at a time, no merging)."""
+    import math
+
+    from paper_2004_06352_amd import inputs, serve
+    models = inputs.config5_models()
+    sides = (512, 1024, 2048, 4096)
+    mean_pix = float(np.mean([s * s for s in sides]))
+    mean_npot = float(np.mean([m[0] for m in models]))
+    mean_samples = (4096 - 64) / math.log(4096 / 64)
+    t_map = mean_pix * mean_npot / map_rate + 2e-4
+    t_chi2 = mean_samples / chi2_rate + 2e-4
+    rate = 0.7 / (0.5 * t_map + 0.5 * t_chi2)
+    dicts = inputs.config5_requests(n_requests=n_requests, rate_hz=rate, map_sides=sides)
+    be = serve.GpuBackend(n_slots=4, models=models)
+    out = {"workload": f"cfg5_poisson_{n_requests}req", "rate_hz": rate}
+    for name, slots, merge in (("served", 4, True), ("plain", 1, False)):
+        reqs = [serve.Req.from_dict(d) for d in dicts]
+        be.prepare(reqs)
+        st = serve.Scheduler(be, n_slots=slots, merge_chi2=merge).run(reqs)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +110,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-chi2", action="store_true")
     ap.add_argument("--only-map", action="store_true", help="primary map metric only")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout "
@@ -107,6 +137,13 @@ def main():
     def step():
         B.hessian_map(table, grid, f, B.FP64, ctx=ctx, out=out)
 
+    tuned = {}
+    if not args.no_tune:
+        from paper_2004_06352_amd import tune
+        for prec in (B.FP64, B.FP32_ACC64, B.FP32_COMP32):
+            best, _ = tune.tune_map(ctx, table, grid, prec, reps=2)
+            tuned[prec] = list(best)
+        log(f"tuned launch shapes: {tuned}")
     log(f"map {nx}x{ny} x {npot} potentials, FP64, steps={args.steps}")
     wall, ev = timed_steps(step, args.steps, args.warmup, torch)
     evals = nx * ny * npot
@@ -127,7 +164,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": c2["name"], "grid": [nx, ny], "potentials": npot,
-                   "channels": 5, "precision": "fp64"},
+                   "channels": 5, "precision": "fp64",
+                   "launch": ctx.get_map_tuning(B.FP64)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "kernel": "map_kernel<fp64, grad+hess>", "flops_per_eval": FLOPS_PER_EVAL,
@@ -171,6 +209,10 @@ def main():
                                                     penalty=100.0, ctx=ctx), 3, 1, torch)
             secondary[f"chi2_image_{name}_samples_per_s"] = S4 * 3 / w
         secondary["chi2_image_workload"] = c4["name"]
+    if not args.no_chi2 and not args.only_map and not args.no_serve:
+        log("serving stream")
+        secondary["serving"] = bench_serving(value, secondary["chi2_source_batched_samples_per_s"],
+                                             args.serve_requests)
     rec["secondary"] = secondary
     if not args.no_cpu:
         log("cpu baseline (oracle)")

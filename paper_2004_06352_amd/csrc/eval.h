@@ -167,8 +167,8 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
         if (zero) dx = 1.0;  // any regular point; the contribution is dropped
     }
     const double cp = c[D_C], sp = c[D_S];
-    const double xp = dx * cp + dy * sp;
-    const double yp = dy * cp - dx * sp;
+    const double xp = fma(dx, cp, dy * sp);
+    const double yp = fma(dy, cp, -(dx * sp));
     const double x2 = xp * xp, y2 = yp * yp;
     const double R = fma(c[D_Q2], x2, y2);
     double ax = 0.0, ay = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
@@ -229,8 +229,8 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
         if (HESS) {
             const double ha = c[D_HF] * ra * iDa, hs = c[D_HF] * rs * iDs;
             const double sa = c[D_SA] * pa, ss = c[D_SS] * ps;
-            hxx = ha * (c[D_CA] + y2 + sa) - hs * (c[D_CS_] + y2 + ss);
-            hyy = ha * (c[D_SA2] + x2 + sa) - hs * (c[D_SS2] + x2 + ss);
+            hxx = fma(ha, c[D_CA] + y2 + sa, -(hs * (c[D_CS_] + y2 + ss)));
+            hyy = fma(ha, c[D_SA2] + x2 + sa, -(hs * (c[D_SS2] + x2 + ss)));
             hxy = -xp * yp * (ha - hs);
         }
     } else {
@@ -276,15 +276,15 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
     }
     if (zero) ax = ay = hxx = hxy = hyy = 0.0;
     if (GRAD) {
-        acc[0] += cp * ax - sp * ay;
-        acc[1] += sp * ax + cp * ay;
+        acc[0] += fma(cp, ax, -(sp * ay));
+        acc[1] += fma(sp, ax, cp * ay);
     }
     if (HESS) {
         const double c2 = c[D_C2], s2 = c[D_S2], cs = c[D_CS], cms = c[D_CMS];
         const double t = 2.0 * cs * hxy;
-        acc[2] += c2 * hxx - t + s2 * hyy;
-        acc[3] += cs * (hxx - hyy) + cms * hxy;
-        acc[4] += s2 * hxx + t + c2 * hyy;
+        acc[2] += fma(c2, hxx, fma(s2, hyy, -t));
+        acc[3] += fma(cs, hxx - hyy, cms * hxy);
+        acc[4] += fma(s2, hxx, fma(c2, hyy, t));
     }
 }
 
@@ -366,8 +366,8 @@ __device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, dou
         if (zero) dx = 1.0;
     }
     const double cpd = c[D_C], spd = c[D_S];
-    const float xp = (float)(dx * cpd + dy * spd);
-    const float yp = (float)(dy * cpd - dx * spd);
+    const float xp = (float)fma(dx, cpd, dy * spd);
+    const float yp = (float)fma(dy, cpd, -(dx * spd));
     const float x2 = xp * xp, y2 = yp * yp;
     const float R = fmaf(f[F_Q2], x2, y2);
     float ax = 0.f, ay = 0.f, hxx = 0.f, hxy = 0.f, hyy = 0.f;
@@ -414,8 +414,8 @@ __device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, dou
         if (HESS) {
             const float ha = f[F_HF] * ra * iDa, hs = f[F_HF] * rs * iDs;
             const float sa = f[F_SA] * pa, ss = f[F_SS] * ps;
-            hxx = ha * (f[F_CA] + y2 + sa) - hs * (f[F_CS_] + y2 + ss);
-            hyy = ha * (f[F_SA2] + x2 + sa) - hs * (f[F_SS2] + x2 + ss);
+            hxx = fmaf(ha, f[F_CA] + y2 + sa, -(hs * (f[F_CS_] + y2 + ss)));
+            hyy = fmaf(ha, f[F_SA2] + x2 + sa, -(hs * (f[F_SS2] + x2 + ss)));
             hxy = -xp * yp * (ha - hs);
         }
     } else {
@@ -454,15 +454,15 @@ __device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, dou
     if (zero) ax = ay = hxx = hxy = hyy = 0.f;
     if (GRAD) {
         const float cp = (float)cpd, sp = (float)spd;
-        out[0] = cp * ax - sp * ay;
-        out[1] = sp * ax + cp * ay;
+        out[0] = fmaf(cp, ax, -(sp * ay));
+        out[1] = fmaf(sp, ax, cp * ay);
     }
     if (HESS) {
         const float c2 = f[F_C2], s2 = f[F_S2], cs = f[F_CS], cms = f[F_CMS];
         const float t = 2.0f * cs * hxy;
-        out[2] = c2 * hxx - t + s2 * hyy;
-        out[3] = cs * (hxx - hyy) + cms * hxy;
-        out[4] = s2 * hxx + t + c2 * hyy;
+        out[2] = fmaf(c2, hxx, fmaf(s2, hyy, -t));
+        out[3] = fmaf(cs, hxx - hyy, cms * hxy);
+        out[4] = fmaf(s2, hxx, fmaf(c2, hyy, t));
     }
 }
 

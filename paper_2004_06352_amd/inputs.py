@@ -147,15 +147,17 @@ def draw_samples(rng, n_samples, uneven=False):
     Returns (free table concatenated over samples, free_off int32 [S+1]).
     uneven=True keeps the three halos and a random subset (0-3, order kept) of
     the three free galaxies in each sample, so sample sizes differ (3-6)."""
-    rows, off = [], [0]
-    for _ in range(n_samples):
-        draw = [[rng.uniform(lo, hi) for lo, hi in pr] for pr in _FREE_PRIORS]
-        if uneven:
-            keep = [0, 1, 2] + [3 + g for g in range(3) if rng.random() < 0.5]
-            draw = [draw[i] for i in keep]
-        rows.extend(draw)
-        off.append(len(rows))
-    return _table(rows), np.asarray(off, dtype=np.int32)
+    lo = np.array([[p[0] for p in pr] for pr in _FREE_PRIORS])
+    hi = np.array([[p[1] for p in pr] for pr in _FREE_PRIORS])
+    draw = lo + rng.random((n_samples, N_FREE, 7)) * (hi - lo)
+    if uneven:
+        keep = np.ones((n_samples, N_FREE), dtype=bool)
+        keep[:, 3:] = rng.random((n_samples, N_FREE - 3)) < 0.5
+    else:
+        keep = np.ones((n_samples, N_FREE), dtype=bool)
+    rows = draw[keep]
+    off = np.concatenate([[0], np.cumsum(keep.sum(axis=1))]).astype(np.int32)
+    return _table(rows), off
 
 
 def load_catalog(path=CATALOG_PATH):
@@ -203,23 +205,35 @@ def config4(seed=3, n_samples=512, n=1000):
     return c3
 
 
+def config5_models(seed=5, n_models=32, pot_range=(50, 1000)):
+    """Pool of lens models served by map requests: potential counts
+    log-uniform in pot_range (config-2 generator).  Returns [(npot, seed)]."""
+    rng = np.random.default_rng(seed + 1000)
+    out = []
+    for _ in range(n_models):
+        npot = int(round(math.exp(rng.uniform(math.log(pot_range[0]), math.log(pot_range[1])))))
+        out.append((npot, int(rng.integers(1 << 30))))
+    return out
+
+
 def config5_requests(seed=5, n_requests=2000, rate_hz=10.0,
-                     map_sides=(512, 1024, 2048, 4096), pot_range=(50, 1000),
+                     map_sides=(512, 1024, 2048, 4096), n_models=32, pot_range=(50, 1000),
                      batch_range=(64, 4096)):
-    """Poisson stream of mixed requests: half lensing maps (side from map_sides,
-    potentials log-uniform in pot_range, drawn with the config-2 generator),
-    half chi^2 batches (size log-uniform in batch_range, config-3 model).
-    Returns a list of dicts with arrival time t [s]."""
+    """Poisson stream of mixed requests: half lensing maps (side from
+    map_sides, model drawn from a pool of n_models lens models with potential
+    counts log-uniform in pot_range), half chi^2 batches (size log-uniform in
+    batch_range, config-3 model, fresh samples per request).  Returns a list of
+    dicts with arrival time t [s]."""
     rng = np.random.default_rng(seed)
+    models = config5_models(seed, n_models, pot_range)
     t, reqs = 0.0, []
     for r in range(n_requests):
         t += rng.exponential(1.0 / rate_hz)
         if rng.random() < 0.5:
             side = int(rng.choice(map_sides))
-            npot = int(round(math.exp(rng.uniform(math.log(pot_range[0]),
-                                                  math.log(pot_range[1])))))
-            reqs.append(dict(id=r, t=t, kind="map", side=side, npot=npot,
-                             seed=int(rng.integers(1 << 30))))
+            mid = int(rng.integers(n_models))
+            reqs.append(dict(id=r, t=t, kind="map", side=side, model=mid,
+                             npot=models[mid][0], model_seed=models[mid][1]))
         else:
             bs = int(round(math.exp(rng.uniform(math.log(batch_range[0]),
                                                 math.log(batch_range[1])))))

@@ -1,0 +1,25 @@
+"""The map autotuner: every candidate launch configuration gives bit-identical
+maps (launch shape never changes what is summed or in which order), and the
+chosen configuration is installed in the context."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_tuner_candidates_are_bit_identical(prec):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_06352_amd import binding as B
+    from paper_2004_06352_amd import inputs, tune
+    c = inputs.config1()
+    ctx = B.Context(0, check=False)
+    table = B.table_from_physical(B.to_device(c["pots"], B.PHYS_KEYS), 0, ctx)
+    grid = (300, 170, -100.0, -60.0, 0.66, 0.7)
+    best, results = tune.tune_map(ctx, table, grid, prec, reps=1, use_cache=False)
+    assert len(results) == len(tune.candidates()), "some launch shape changed the output"
+    assert ctx.get_map_tuning(prec) == tuple(best)
+    assert results[0][1] <= results[-1][1]
+    ctx.close()
