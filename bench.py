@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--only-map", action="store_true", help="primary map metric only")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--launch", default="", help="fixed FP64 map launch bx,by,ppt,stage,chunk")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -137,8 +140,19 @@ def main():
     def step():
         B.hessian_map(table, grid, f, B.FP64, ctx=ctx, out=out)
 
+    if args.copy_probe_mib:
+        # a plain device copy of known size: the reference the HBM byte
+        # counters of the map kernel are scaled by
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tuned = {}
-    if not args.no_tune:
+    if args.launch:
+        ctx.set_map_tuning(B.FP64, tuple(int(v) for v in args.launch.split(",")))
+    elif not args.no_tune:
         from paper_2004_06352_amd import tune
         for prec in (B.FP64, B.FP32_ACC64, B.FP32_COMP32):
             best, _ = tune.tune_map(ctx, table, grid, prec, reps=2)

@@ -29,7 +29,8 @@ __global__ void __launch_bounds__(64) fixed_alpha_points_kernel(Derived tab, int
                                                                 const double *__restrict__ X,
                                                                 const double *__restrict__ Y,
                                                                 int nimg_pad,
-                                                                double *__restrict__ afix) {
+                                                                double *__restrict__ afix,
+                                                                Series S) {
     const int t = blockIdx.x * 64 + threadIdx.x;
     const int c = blockIdx.y;
     const int k0 = c * FIXED_CHUNK, k1 = min(tab.n, k0 + FIXED_CHUNK);
@@ -37,11 +38,11 @@ __global__ void __launch_bounds__(64) fixed_alpha_points_kernel(Derived tab, int
     double acc[5] = {0, 0, 0, 0, 0};
     for (int k = k0; k < k1; ++k) {
         if (PREC == 0) {
-            eval_pot_f64<true, false>(ConstD{tab.d + k, tab.stride}, x, y, acc);
+            eval_pot_f64<true, false>(ConstD{tab.d + k, tab.stride}, x, y, acc, S);
         } else {
             float o[5];
             eval_pot_f32<true, false>(ConstD{tab.d + k, tab.stride},
-                                      ConstF{tab.f + k, tab.stride}, x, y, o);
+                                      ConstF{tab.f + k, tab.stride}, x, y, o, S);
             acc[0] += (double)o[0];
             acc[1] += (double)o[1];
         }
@@ -60,10 +61,10 @@ hipError_t launch_fixed_alpha_points(Derived fixedt, int nimg, const double *x, 
     if (grid.y > 65535u) return hipErrorInvalidConfiguration;
     if (prec == 0)
         hipLaunchKernelGGL(fixed_alpha_points_kernel<0>, grid, dim3(64), 0, st, fixedt, nimg, x, y,
-                           nimg_pad, afix);
+                           nimg_pad, afix, make_series());
     else
         hipLaunchKernelGGL(fixed_alpha_points_kernel<1>, grid, dim3(64), 0, st, fixedt, nimg, x, y,
-                           nimg_pad, afix);
+                           nimg_pad, afix, make_series());
     return hipGetLastError();
 }
 
@@ -110,11 +111,11 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
             }
             for (int k = k0; k < k1; ++k) {
                 if (PREC == 0) {
-                    eval_pot_f64<true, false>(ConstD{a.freet.d + k, a.freet.stride}, x, y, acc);
+                    eval_pot_f64<true, false>(ConstD{a.freet.d + k, a.freet.stride}, x, y, acc, a.S);
                 } else {
                     float o[5];
                     eval_pot_f32<true, false>(ConstD{a.freet.d + k, a.freet.stride},
-                                              ConstF{a.freet.f + k, a.freet.stride}, x, y, o);
+                                              ConstF{a.freet.f + k, a.freet.stride}, x, y, o, a.S);
                     acc[0] += (double)o[0];
                     acc[1] += (double)o[1];
                 }
@@ -156,7 +157,9 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
     }
 }
 
-hipError_t launch_chi2_src(const Chi2SrcLaunch &c, hipStream_t st) {
+hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
+    Chi2SrcLaunch c = c0;
+    c.S = make_series();
     const size_t shmem = (size_t)2 * c.nimg * sizeof(double);
     if (c.prec == 0)
         hipLaunchKernelGGL(chi2_src_kernel<0>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
@@ -187,11 +190,11 @@ __global__ void __launch_bounds__(256) alpha_grid_kernel(AlphaGridLaunch a) {
     }
     for (int k = k0; k < k1; ++k) {
         if (PREC == 0) {
-            eval_pot_f64<true, false>(ConstD{a.freet.d + k, a.freet.stride}, x, y, acc);
+            eval_pot_f64<true, false>(ConstD{a.freet.d + k, a.freet.stride}, x, y, acc, a.S);
         } else {
             float o[5];
             eval_pot_f32<true, false>(ConstD{a.freet.d + k, a.freet.stride},
-                                      ConstF{a.freet.f + k, a.freet.stride}, x, y, o);
+                                      ConstF{a.freet.f + k, a.freet.stride}, x, y, o, a.S);
             acc[0] += (double)o[0];
             acc[1] += (double)o[1];
         }
@@ -202,7 +205,9 @@ __global__ void __launch_bounds__(256) alpha_grid_kernel(AlphaGridLaunch a) {
     }
 }
 
-hipError_t launch_alpha_grid(const AlphaGridLaunch &L, hipStream_t st) {
+hipError_t launch_alpha_grid(const AlphaGridLaunch &L0, hipStream_t st) {
+    AlphaGridLaunch L = L0;
+    L.S = make_series();
     const size_t nv = (size_t)L.grid.nx * L.grid.ny;
     if (nv == 0 || L.nsamp <= 0) return hipSuccess;
     dim3 grid((unsigned)((nv + 255) / 256), L.nsamp);

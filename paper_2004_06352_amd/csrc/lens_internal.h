@@ -81,6 +81,25 @@ struct PotSoA {
     const double *x0, *y0, *b0, *eps, *phi, *rcore, *rcut;
 };
 
+// Taylor coefficients of atan and atanh (Horner order, highest first).  They
+// travel as a kernel argument so that the kernels read them from scalar
+// registers (literal FP64 constants would be held in vector registers and
+// copied before every fused multiply-add).
+struct Series {
+    double at[10];  // 1/21, -1/19, 1/17, ..., -1/3
+    double ah[9];   // 1/19, 1/17, ..., 1/3
+    float atf[4];   // 1/9, -1/7, 1/5, -1/3
+    float ahf[4];   // 1/9, 1/7, 1/5, 1/3
+};
+inline Series make_series() {
+    Series S;
+    for (int i = 0; i < 10; ++i) S.at[i] = ((i % 2) ? -1.0 : 1.0) / (21 - 2 * i);
+    for (int i = 0; i < 9; ++i) S.ah[i] = 1.0 / (19 - 2 * i);
+    for (int i = 0; i < 4; ++i) S.atf[i] = (float)(((i % 2) ? -1.0 : 1.0) / (9 - 2 * i));
+    for (int i = 0; i < 4; ++i) S.ahf[i] = (float)(1.0 / (9 - 2 * i));
+    return S;
+}
+
 struct GridArgs {
     int nx, ny;
     double x0, y0, dx, dy;
@@ -128,6 +147,7 @@ struct Chi2SrcLaunch {
     int persistent;           // 1: pull samples from *queue until exhausted
     int grid_blocks;
     int prec;
+    Series S;                 // filled by the launch wrapper
 };
 hipError_t launch_fixed_alpha_points(Derived fixedt, int nimg, const double *x, const double *y,
                                      int nchunk, int nimg_pad, double *afix, int prec,
@@ -163,6 +183,7 @@ struct AlphaGridLaunch {
     const double *afix_x, *afix_y; // fixed-potential deflection (nv each) or NULL
     double *out;
     int prec;
+    Series S;                  // filled by the launch wrapper
 };
 hipError_t launch_alpha_grid(const AlphaGridLaunch &L, hipStream_t st);
 

@@ -162,6 +162,7 @@ struct MapArgs {
     double dlsds;
     void *out[5];
     int chunk;
+    Series S;
 };
 
 template <int PREC, bool GRAD, bool HESS, bool STAGE, int PPT>
@@ -192,10 +193,10 @@ __global__ void __launch_bounds__(256) map_kernel(MapArgs a) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             if (PREC == 0) {
-                eval_pot_f64<GRAD, HESS>(cd, x[p], y, acc[p]);
+                eval_pot_f64<GRAD, HESS>(cd, x[p], y, acc[p], a.S);
             } else {
                 float o[5];
-                eval_pot_f32<GRAD, HESS>(cd, cf, x[p], y, o);
+                eval_pot_f32<GRAD, HESS>(cd, cf, x[p], y, o, a.S);
 #pragma unroll
                 for (int ch = 0; ch < 5; ++ch) {
                     const bool used = (ch < 2) ? GRAD : HESS;
@@ -300,6 +301,7 @@ hipError_t launch_map(const MapLaunch &m, hipStream_t st) {
     a.dlsds = m.dlsds;
     for (int c = 0; c < 5; ++c) a.out[c] = m.out[c];
     a.chunk = t.lds_chunk;
+    a.S = make_series();
     const long long span_x = (long long)t.block_x * t.pix_per_thread;
     dim3 grid((unsigned)((m.grid.nx + span_x - 1) / span_x),
               (unsigned)((m.grid.ny + t.block_y - 1) / t.block_y));
