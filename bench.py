@@ -52,6 +52,41 @@ def timed_steps(fn, steps, warmup, torch):
     return wall, float(np.mean(ev))
 
 
+MAP_SOURCES = ("paper_2004_06352_amd/csrc/maps.hip", "paper_2004_06352_amd/csrc/eval.h",
+               "paper_2004_06352_amd/csrc/lens_internal.h")
+COUNTERS = os.path.join(ROOT, "profiles", "map_kernel_cfg2_2048sq_502pot_counters.md")
+
+
+def map_source_hash():
+    """Hash of the sources that define the map kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in MAP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per FP64 map launch from the committed FETCH_SIZE / WRITE_SIZE
+    passes, each scaled by what the same counter read for a plain copy of known
+    size; None when the counters were taken on other kernel sources."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    with open(COUNTERS) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != map_source_hash():
+        return None
+    copy_bytes = float(kv["copy_bytes"])
+    fetch = float(kv["map_fetch_kib"]) * copy_bytes / (1024 * float(kv["copy_fetch_kib"]))
+    write = float(kv["map_write_kib"]) * copy_bytes / (1024 * float(kv["copy_write_kib"]))
+    return (fetch + write) * 1024
+
+
 def cpu_baseline_map(c, budget_s=12.0):
     """The oracle on a strip of rows of the same map (all potentials)."""
     from oracle import oracle as O
@@ -181,7 +216,9 @@ def main():
                    "channels": 5, "precision": "fp64",
                    "launch": ctx.get_map_tuning(B.FP64)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes": 5 * 8 * nx * ny,
                      "kernel": "map_kernel<fp64, grad+hess>", "flops_per_eval": FLOPS_PER_EVAL,
                      "avg_launch_ms": ev * 1e3},
     }
@@ -202,6 +239,10 @@ def main():
         free = B.table_from_physical(B.to_device(c3["free"], B.PHYS_KEYS), 0, ctx)
         off = torch.as_tensor(c3["free_off"], dtype=torch.int32, device="cuda")
         S = int(off.numel()) - 1
+        if not args.no_tune:
+            from paper_2004_06352_amd import tune
+            bpc, _ = tune.tune_chi2(ctx, fixed, free, off, cat)
+            secondary["chi2_source_blocks_per_cu"] = bpc
         for name, path in (("batched", B.PATH_BATCHED), ("per_sample", B.PATH_PER_SAMPLE)):
             n = 10 if path == B.PATH_BATCHED else 3
             w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=path, ctx=ctx),

@@ -156,7 +156,7 @@ typedef struct {
  * system i are img_offset[i] .. img_offset[i+1]-1. */
 typedef struct {
     int32_t n_sys;             /* >= 1 */
-    int32_t n_img;             /* total images = img_offset[n_sys], 1..4096 */
+    int32_t n_img;             /* total images = img_offset[n_sys], 1..4000 */
     const int32_t *img_offset; /* device [n_sys+1], non-decreasing, [0] = 0 */
     const double *x, *y;       /* observed positions c_ij [arcsec] */
     const double *sigma;       /* position error sigma_ij [arcsec], > 0 */
@@ -193,6 +193,10 @@ lens_status_t lens_set_map_tuning(lens_ctx_t *ctx, lens_precision_t prec,
                                   const lens_map_tuning_t *tuning);
 lens_status_t lens_get_map_tuning(lens_ctx_t *ctx, lens_precision_t prec,
                                   lens_map_tuning_t *out);
+/* Number of persistent 256-thread blocks per compute unit that the batched
+ * chi^2 path launches (1..32, default 4).  Does not change any result. */
+lens_status_t lens_set_chi2_tuning(lens_ctx_t *ctx, int32_t blocks_per_cu);
+lens_status_t lens_get_chi2_tuning(lens_ctx_t *ctx, int32_t *blocks_per_cu);
 
 /* ---- parameter prologue ------------------------------------------------- */
 /* Physical -> amplitude form on the device (Sec. 2.2 parameters):

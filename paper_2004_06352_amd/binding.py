@@ -34,7 +34,8 @@ POT_KEYS = ("x0", "y0", "b0", "eps", "phi", "rcore", "rcut")
 PHYS_KEYS = ("x0", "y0", "sigma", "e", "phi", "rcore", "rcut")
 
 EXPORTS = ("lens_ctx_create", "lens_ctx_destroy", "lens_ctx_status", "lens_set_map_tuning",
-           "lens_get_map_tuning", "lens_table_from_physical", "lens_grad_map",
+           "lens_get_map_tuning", "lens_set_chi2_tuning", "lens_get_chi2_tuning",
+           "lens_table_from_physical", "lens_grad_map",
            "lens_hessian_map", "lens_chi2_batch", "lens_find_images", "lens_chi2_plan_create",
            "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_dlsds",
            "lens_b0_from_sigma", "lens_eps_from_e", "lens_last_error", "lens_abi_version")
@@ -100,6 +101,8 @@ def lib():
         L.lens_ctx_status.argtypes = [vp]
         L.lens_set_map_tuning.argtypes = [vp, i32, C.POINTER(MapTuning)]
         L.lens_get_map_tuning.argtypes = [vp, i32, C.POINTER(MapTuning)]
+        L.lens_set_chi2_tuning.argtypes = [vp, i32]
+        L.lens_get_chi2_tuning.argtypes = [vp, C.POINTER(i32)]
         L.lens_table_from_physical.argtypes = [vp, C.POINTER(_Phys), i32, vp, vp, vp]
         L.lens_grad_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp, vp]
         L.lens_hessian_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp,
@@ -172,6 +175,14 @@ class Context:
         t = MapTuning()
         _check(lib().lens_get_map_tuning(self.handle, prec, C.byref(t)))
         return t.as_tuple()
+
+    def set_chi2_tuning(self, blocks_per_cu):
+        _check(lib().lens_set_chi2_tuning(self.handle, int(blocks_per_cu)))
+
+    def get_chi2_tuning(self):
+        v = C.c_int32()
+        _check(lib().lens_get_chi2_tuning(self.handle, C.byref(v)))
+        return v.value
 
 
 _contexts = {}

@@ -53,6 +53,7 @@ struct lens_ctx {
     int *host_small = nullptr;   // pinned mirror
     int num_cu = 256;
     lens_map_tuning_t tune[3];
+    int chi2_blocks_per_cu = 4;  // persistent chi^2 blocks (256 threads) per CU
 };
 
 struct lens_chi2_plan {
@@ -248,8 +249,8 @@ lens_status_t check_batch(const lens_model_batch_t *b) {
 lens_status_t check_catalog(const lens_catalog_t *c) {
     if (!c) return fail(LENS_EINVAL, "catalog is NULL");
     if (c->n_sys < 1) return fail(LENS_EINVAL, "catalog.n_sys = %d", c->n_sys);
-    if (c->n_img < 1 || c->n_img > 4096)
-        return fail(LENS_EINVAL, "catalog.n_img = %d (1..4096)", c->n_img);
+    if (c->n_img < 1 || c->n_img > 4000)
+        return fail(LENS_EINVAL, "catalog.n_img = %d (1..4000)", c->n_img);
     TRY(check_range(c->img_offset, ((size_t)c->n_sys + 1) * sizeof(int32_t),
                     "catalog.img_offset"));
     const size_t b = (size_t)c->n_img * sizeof(double);
@@ -296,7 +297,7 @@ struct SrcPlan {
 
 SrcPlan plan_src(Carve &cv, const lens_model_batch_t *b, const lens_catalog_t *c, bool sources) {
     SrcPlan p;
-    p.nchunk = (b->fixed.n + 31) / 32;
+    p.nchunk = (b->fixed.n + FIXED_CHUNK - 1) / FIXED_CHUNK;
     p.nimg_pad = (c->n_img + 63) / 64 * 64;
     p.o_fix = cv.take(derived_bytes(b->fixed.n));
     p.o_free = cv.take(derived_bytes(b->free.n));
@@ -306,7 +307,9 @@ SrcPlan plan_src(Carve &cv, const lens_model_batch_t *b, const lens_catalog_t *c
     return p;
 }
 
-int batched_blocks(const lens_ctx_t *ctx, int S) { return std::max(1, std::min(S, ctx->num_cu * 8)); }
+int batched_blocks(const lens_ctx_t *ctx, int S) {
+    return std::max(1, std::min(S, ctx->num_cu * ctx->chi2_blocks_per_cu));
+}
 
 // Prologues, fixed deflection at the constraints, then the per-sample kernel.
 lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
@@ -469,6 +472,20 @@ lens_status_t lens_get_map_tuning(lens_ctx_t *ctx, lens_precision_t prec, lens_m
     if (!ctx || !out) return fail(LENS_EINVAL, "NULL argument");
     TRY(check_prec(prec));
     *out = ctx->tune[prec];
+    return LENS_OK;
+}
+
+lens_status_t lens_set_chi2_tuning(lens_ctx_t *ctx, int32_t blocks_per_cu) {
+    if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
+    if (blocks_per_cu < 1 || blocks_per_cu > 32)
+        return fail(LENS_EINVAL, "blocks_per_cu = %d (1..32)", blocks_per_cu);
+    ctx->chi2_blocks_per_cu = blocks_per_cu;
+    return LENS_OK;
+}
+
+lens_status_t lens_get_chi2_tuning(lens_ctx_t *ctx, int32_t *blocks_per_cu) {
+    if (!ctx || !blocks_per_cu) return fail(LENS_EINVAL, "NULL argument");
+    *blocks_per_cu = ctx->chi2_blocks_per_cu;
     return LENS_OK;
 }
 

@@ -4,14 +4,15 @@
 // sum the scatter over sigma^2) and the per-sample vertex deflection grids of
 // the image-plane chi^2 (Sec. 4.2, stage 1).
 //
-// Design (gfx950): one wave64 per model sample.  Lanes stride over the
-// catalogue's images; the sample's free potentials are walked in index order
-// with wave-uniform loads.  Unlensed positions go to LDS, then lanes take one
-// system each and the per-system sums are combined by a shuffle reduction.
-// The batched path launches a few persistent waves per CU that pull sample
-// indices from a device counter until the batch is exhausted, so samples of
-// uneven size balance across the chip; the per-sample path launches the same
-// kernel once per sample.  Both produce bit-identical results.
+// Design (gfx950): one 256-thread block per model sample.  Threads stride
+// over the catalogue's images; the sample's free potentials are walked in
+// index order with wave-uniform loads.  Unlensed positions go to LDS, then
+// threads take one system each and the per-system sums are combined by
+// shuffle reductions in a fixed order.  The batched path launches a few
+// persistent blocks per CU that pull sample indices from a device counter
+// until the batch is exhausted, so samples of uneven size balance across the
+// chip; the per-sample path launches the same kernel once per sample.  Both
+// produce bit-identical results.
 #include <math.h>
 
 #include "eval.h"
@@ -22,7 +23,6 @@ namespace lens {
 // Fixed-potential deflection at the catalogue points, as partial sums over
 // chunks of FIXED_CHUNK potentials: afix[(c*2 + {0,1})*nimg_pad + t].
 // Summed by the consumer in chunk order (deterministic).
-constexpr int FIXED_CHUNK = 32;
 
 template <int PREC>
 __global__ void __launch_bounds__(64) fixed_alpha_points_kernel(Derived tab, int nimg,
@@ -87,22 +87,29 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// One block of SRC_BLOCK threads per sample: threads over images, then over
+// systems; per-wave shuffle sums combined in a fixed order, so a sample's
+// chi^2 does not depend on the batch it is evaluated in or on the path.
+constexpr int SRC_BLOCK = 256;
+
 template <int PREC>
-__global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
-    extern __shared__ double sh[];  // [2][nimg]: unlensed x then y
-    const int lane = threadIdx.x;
+__global__ void __launch_bounds__(SRC_BLOCK) chi2_src_kernel(Chi2SrcLaunch a) {
+    extern __shared__ double sh[];  // [2][nimg]: unlensed x then y; then wave partials
+    __shared__ int s_next;
+    double *red = sh + 2 * (size_t)a.nimg;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int m = a.sample0 + blockIdx.x;
     for (;;) {
         if (a.persistent) {
-            int got = 0;
-            if (lane == 0) got = atomicAdd(a.queue, 1);
-            m = __shfl(got, 0, 64);
+            if (tid == 0) s_next = atomicAdd(a.queue, 1);
+            __syncthreads();
+            m = s_next;
         }
         if (m >= a.n_samples) break;
         const int nf = a.freet.n;
         const int k0 = min(max(a.free_off[m], 0), nf);
         const int k1 = min(max(a.free_off[m + 1], k0), nf);
-        for (int t = lane; t < a.nimg; t += 64) {
+        for (int t = tid; t < a.nimg; t += SRC_BLOCK) {
             const double x = a.x[t], y = a.y[t];
             double acc[5] = {0, 0, 0, 0, 0};
             for (int c = 0; c < a.nchunk; ++c) {
@@ -126,7 +133,7 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
         }
         __syncthreads();
         double part = 0.0;
-        for (int i = lane; i < a.nsys; i += 64) {
+        for (int i = tid; i < a.nsys; i += SRC_BLOCK) {
             const int o0 = min(max(a.img_off[i], 0), a.nimg);
             const int o1 = min(max(a.img_off[i + 1], o0), a.nimg);
             const int M = o1 - o0;
@@ -151,7 +158,13 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
             }
         }
         part = wave_sum(part);
-        if (lane == 0 && a.chi2) a.chi2[m] = part;
+        if (lane == 0) red[wave] = part;
+        __syncthreads();
+        if (tid == 0 && a.chi2) {
+            double total = red[0];
+            for (int w = 1; w < SRC_BLOCK / 64; ++w) total += red[w];
+            a.chi2[m] = total;
+        }
         __syncthreads();
         if (!a.persistent) break;
     }
@@ -160,11 +173,11 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
     Chi2SrcLaunch c = c0;
     c.S = make_series();
-    const size_t shmem = (size_t)2 * c.nimg * sizeof(double);
+    const size_t shmem = ((size_t)2 * c.nimg + SRC_BLOCK / 64) * sizeof(double);
     if (c.prec == 0)
-        hipLaunchKernelGGL(chi2_src_kernel<0>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
+        hipLaunchKernelGGL(chi2_src_kernel<0>, dim3(c.grid_blocks), dim3(SRC_BLOCK), shmem, st, c);
     else
-        hipLaunchKernelGGL(chi2_src_kernel<1>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
+        hipLaunchKernelGGL(chi2_src_kernel<1>, dim3(c.grid_blocks), dim3(SRC_BLOCK), shmem, st, c);
     return hipGetLastError();
 }
 

@@ -105,6 +105,10 @@ struct GridArgs {
     double x0, y0, dx, dy;
 };
 
+// Fixed-potential deflections at catalogue points are summed in chunks of
+// this many potentials (partial sums combined in chunk order).
+constexpr int FIXED_CHUNK = 8;
+
 // status word bits written by device code
 enum StatusBits : int { ST_INVALID_TABLE = 1, ST_OVERFLOW = 2 };
 

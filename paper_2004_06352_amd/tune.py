@@ -116,3 +116,37 @@ def tune_map(ctx: B.Context, table, grid, prec=B.FP64, hess=True, reps=3, use_ca
                       "time": time.time()}
         _save(cache)
     return best, results
+
+
+def tune_chi2(ctx: B.Context, fixed, free, free_off, cat, prec=B.FP64, reps=3,
+              choices=(1, 2, 4, 8, 16, 32), verbose=False):
+    """Pick and install the number of persistent blocks per CU of the batched
+    source-plane chi^2 for this batch; every choice must give bit-identical
+    chi^2 values.  Returns (best, [(blocks_per_cu, seconds), ...])."""
+    ref = None
+    results = []
+    for bpc in choices:
+        ctx.set_chi2_tuning(bpc)
+        out = B.chi2_batch(fixed, free, free_off, cat, prec=prec, ctx=ctx)["chi2"]
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            if verbose:
+                print("rejected (output differs):", bpc)
+            continue
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            B.chi2_batch(fixed, free, free_off, cat, prec=prec, ctx=ctx)
+        ev1.record()
+        ev1.synchronize()
+        sec = ev0.elapsed_time(ev1) * 1e-3 / reps
+        results.append((bpc, sec))
+        if verbose:
+            print(f"blocks/CU {bpc}: {sec * 1e6:.1f} us")
+    results.sort(key=lambda r: r[1])
+    best = results[0][0]
+    ctx.set_chi2_tuning(best)
+    return best, results

@@ -128,6 +128,26 @@ def test_special_potentials(B, ctx, oracle):
         assert_within(got, ref, mag, RTOL[prec], f"special potentials prec={prec}")
 
 
+def test_fp32_modes_where_single_precision_is_weakest(B, ctx, oracle):
+    """Pixels within a few mas of tiny cores 70" from the origin, ellipticity
+    1e-7, strong ellipticity, and the far field 1000" away: the FP32 modes keep
+    1e-5 of the scale (offsets and rotation are formed in FP64)."""
+    rows = [(50.0, -50.0, 0.5, 1e-7, 0.4, 0.005, 10.0),
+            (50.01, -49.99, 1.0, 0.45, 2.0, 0.001, 5.0),
+            (0.0, 0.0, 40.0, 0.2, 0.5, 5.0, 1000.0)]
+    a = np.array(rows)
+    pots = {k: a[:, i].copy() for i, k in enumerate(B.POT_KEYS)}
+    grids = [(64, 64, 50.0 - 0.0325, -50.0 - 0.0325, 1e-3, 1e-3),
+             (48, 40, 49.99, -50.02, 1.7e-3, 1.3e-3),
+             (32, 32, 900.0, -1000.0, 1.0, 1.0)]
+    for grid in grids:
+        ref, mag = oracle.lens_map(pots, grid, 0.8)
+        for prec in (1, 2):
+            got = run_map(B, ctx, amp_to_device(B, pots), grid, 0.8, prec)
+            w = assert_within(got, ref, mag, RTOL[prec], f"fp32 hazard {grid} prec={prec}")
+            print(f"hazard grid {grid[:2]} prec={prec}: max err/scale {w:.3g}")
+
+
 def test_singular_centre_contributes_zero(B, ctx, oracle):
     one = {k: v[3:4] for k, v in special_pots().items()}
     grid = (3, 3, 0.0, 0.0, 1.0, 1.0)  # (1, 1) is the centre
