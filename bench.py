@@ -241,8 +241,8 @@ def main():
         S = int(off.numel()) - 1
         if not args.no_tune:
             from paper_2004_06352_amd import tune
-            bpc, _ = tune.tune_chi2(ctx, fixed, free, off, cat)
-            secondary["chi2_source_blocks_per_cu"] = bpc
+            wpc, _ = tune.tune_chi2(ctx, fixed, free, off, cat)
+            secondary["chi2_source_waves_per_cu"] = wpc
         for name, path in (("batched", B.PATH_BATCHED), ("per_sample", B.PATH_PER_SAMPLE)):
             n = 10 if path == B.PATH_BATCHED else 3
             w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=path, ctx=ctx),

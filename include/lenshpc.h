@@ -193,10 +193,11 @@ lens_status_t lens_set_map_tuning(lens_ctx_t *ctx, lens_precision_t prec,
                                   const lens_map_tuning_t *tuning);
 lens_status_t lens_get_map_tuning(lens_ctx_t *ctx, lens_precision_t prec,
                                   lens_map_tuning_t *out);
-/* Number of persistent 256-thread blocks per compute unit that the batched
- * chi^2 path launches (1..32, default 4).  Does not change any result. */
-lens_status_t lens_set_chi2_tuning(lens_ctx_t *ctx, int32_t blocks_per_cu);
-lens_status_t lens_get_chi2_tuning(lens_ctx_t *ctx, int32_t *blocks_per_cu);
+/* Number of persistent one-wave blocks per compute unit that the batched
+ * source-plane chi^2 launches (1..64, default 16; each wave evaluates whole
+ * samples).  Does not change any result. */
+lens_status_t lens_set_chi2_tuning(lens_ctx_t *ctx, int32_t waves_per_cu);
+lens_status_t lens_get_chi2_tuning(lens_ctx_t *ctx, int32_t *waves_per_cu);
 
 /* ---- parameter prologue ------------------------------------------------- */
 /* Physical -> amplitude form on the device (Sec. 2.2 parameters):

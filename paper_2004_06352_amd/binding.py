@@ -176,8 +176,8 @@ class Context:
         _check(lib().lens_get_map_tuning(self.handle, prec, C.byref(t)))
         return t.as_tuple()
 
-    def set_chi2_tuning(self, blocks_per_cu):
-        _check(lib().lens_set_chi2_tuning(self.handle, int(blocks_per_cu)))
+    def set_chi2_tuning(self, waves_per_cu):
+        _check(lib().lens_set_chi2_tuning(self.handle, int(waves_per_cu)))
 
     def get_chi2_tuning(self):
         v = C.c_int32()

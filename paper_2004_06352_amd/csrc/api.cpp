@@ -49,11 +49,11 @@ struct lens_ctx {
     uint32_t flags = 0;
     void *scratch = nullptr;
     size_t scratch_size = 0;
-    int *small = nullptr;        // device: [0] status, [1] queue, [2..] spare
+    int *small = nullptr;        // device: [0] status, [2] overflow word, others spare
     int *host_small = nullptr;   // pinned mirror
     int num_cu = 256;
     lens_map_tuning_t tune[3];
-    int chi2_blocks_per_cu = 4;  // persistent chi^2 blocks (256 threads) per CU
+    int chi2_blocks_per_cu = 16;  // persistent chi^2 waves (one-wave blocks) per CU
 };
 
 struct lens_chi2_plan {
@@ -291,7 +291,7 @@ lens_status_t check_contents(lens_ctx_t *ctx, const lens_model_batch_t *b,
 }
 
 struct SrcPlan {
-    size_t o_fix, o_free, o_afix, o_src;
+    size_t o_fix, o_free, o_afix, o_rec, o_src;
     int nchunk, nimg_pad;
 };
 
@@ -302,6 +302,7 @@ SrcPlan plan_src(Carve &cv, const lens_model_batch_t *b, const lens_catalog_t *c
     p.o_fix = cv.take(derived_bytes(b->fixed.n));
     p.o_free = cv.take(derived_bytes(b->free.n));
     p.o_afix = cv.take((size_t)std::max(p.nchunk, 1) * 2 * p.nimg_pad * sizeof(double));
+    p.o_rec = cv.take((size_t)3 * p.nimg_pad * sizeof(double));
     p.o_src = sources ? cv.take((size_t)std::max(b->n_samples, 1) * c->n_sys * 2 * sizeof(double))
                       : 0;
     return p;
@@ -337,16 +338,17 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
     L.sig = c->sigma;
     L.f = c->dlsds;
     L.afix = afix;
+    L.rec = (double *)sc(ctx, p.o_rec);
     L.nchunk = p.nchunk;
     L.nimg_pad = p.nimg_pad;
     L.chi2 = chi2;
     L.src_x = sources ? (double *)sc(ctx, p.o_src) : nullptr;
     L.src_y = sources ? L.src_x + (size_t)b->n_samples * c->n_sys : nullptr;
-    L.queue = ctx->small + 1;
+    const bool batched = path == LENS_CHI2_PATH_BATCHED;
     L.prec = prec == LENS_FP64 ? 0 : 1;
     if (b->n_samples == 0) return LENS_OK;
-    if (path == LENS_CHI2_PATH_BATCHED) {
-        HIP_TRY(launch_zero_i32(ctx->small + 1, 1, st));
+    HIP_TRY(launch_chi2_prep(L, st));
+    if (batched) {
         L.persistent = 1;
         L.grid_blocks = batched_blocks(ctx, b->n_samples);
         HIP_TRY(launch_chi2_src(L, st));
@@ -477,8 +479,8 @@ lens_status_t lens_get_map_tuning(lens_ctx_t *ctx, lens_precision_t prec, lens_m
 
 lens_status_t lens_set_chi2_tuning(lens_ctx_t *ctx, int32_t blocks_per_cu) {
     if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
-    if (blocks_per_cu < 1 || blocks_per_cu > 32)
-        return fail(LENS_EINVAL, "blocks_per_cu = %d (1..32)", blocks_per_cu);
+    if (blocks_per_cu < 1 || blocks_per_cu > 64)
+        return fail(LENS_EINVAL, "waves_per_cu = %d (1..64)", blocks_per_cu);
     ctx->chi2_blocks_per_cu = blocks_per_cu;
     return LENS_OK;
 }

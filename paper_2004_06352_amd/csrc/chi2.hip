@@ -4,16 +4,19 @@
 // sum the scatter over sigma^2) and the per-sample vertex deflection grids of
 // the image-plane chi^2 (Sec. 4.2, stage 1).
 //
-// Design (gfx950): one 256-thread block per model sample.  Threads stride
-// over the catalogue's images; the sample's free potentials are walked in
-// index order with wave-uniform loads.  Unlensed positions go to LDS, then
-// threads take one system each and the per-system sums are combined by
-// shuffle reductions in a fixed order.  The batched path launches a few
-// persistent blocks per CU that pull sample indices from a device counter
-// until the batch is exhausted, so samples of uneven size balance across the
-// chip; the per-sample path launches the same kernel once per sample.  Both
-// produce bit-identical results.
+// Design (gfx950): one wave per model sample.  What all samples share (the
+// fixed potentials' deflection at each image, each image's Dls/Ds) is
+// computed once per call; a sample then costs its free potentials at its
+// images, staged through LDS and evaluated for several images per lane.
+// Unlensed positions go to LDS, lanes take one system each and the sums are
+// combined by a shuffle reduction in a fixed order.  The batched path
+// launches a few waves per SIMD that stride over the batch (a shared work
+// counter would serialise every wave on one L2 atomic); the per-sample path
+// launches the same kernel once per sample.  Both produce bit-identical
+// results.
 #include <math.h>
+
+#include <algorithm>
 
 #include "eval.h"
 
@@ -21,8 +24,9 @@ namespace lens {
 
 // ---------------------------------------------------------------------------
 // Fixed-potential deflection at the catalogue points, as partial sums over
-// chunks of FIXED_CHUNK potentials: afix[(c*2 + {0,1})*nimg_pad + t].
-// Summed by the consumer in chunk order (deterministic).
+// chunks of FIXED_CHUNK potentials (staged through LDS):
+// afix[(c*2 + {0,1})*nimg_pad + t].  Combined by the prep kernel in a fixed
+// order (deterministic).
 
 template <int PREC>
 __global__ void __launch_bounds__(64) fixed_alpha_points_kernel(Derived tab, int nimg,
@@ -31,18 +35,33 @@ __global__ void __launch_bounds__(64) fixed_alpha_points_kernel(Derived tab, int
                                                                 int nimg_pad,
                                                                 double *__restrict__ afix,
                                                                 Series S) {
-    const int t = blockIdx.x * 64 + threadIdx.x;
+    __shared__ double pd[FIXED_CHUNK * NDER];
+    __shared__ float pf[FIXED_CHUNK * NDERF];
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x * 64 + lane;
     const int c = blockIdx.y;
-    const int k0 = c * FIXED_CHUNK, k1 = min(tab.n, k0 + FIXED_CHUNK);
+    const int k0 = c * FIXED_CHUNK, cnt = min(tab.n - k0, FIXED_CHUNK);
+    const int st = tab.stride;
+    for (int e = lane; e < cnt * NDER; e += 64) {
+        const int ci = e / cnt, kk = e - ci * cnt;
+        pd[kk * NDER + ci] = tab.d[(size_t)ci * st + k0 + kk];
+    }
+    if (PREC != 0) {
+        for (int e = lane; e < cnt * NDERF; e += 64) {
+            const int ci = e / cnt, kk = e - ci * cnt;
+            pf[kk * NDERF + ci] = tab.f[(size_t)ci * st + k0 + kk];
+        }
+    }
     const double x = t < nimg ? X[t] : 0.0, y = t < nimg ? Y[t] : 0.0;
+    __syncthreads();
     double acc[5] = {0, 0, 0, 0, 0};
-    for (int k = k0; k < k1; ++k) {
+    for (int kk = 0; kk < cnt; ++kk) {
         if (PREC == 0) {
-            eval_pot_f64<true, false>(ConstD{tab.d + k, tab.stride}, x, y, acc, S);
+            eval_pot_f64<true, false>(ConstD{pd + kk * NDER, 1}, x, y, acc, S);
         } else {
             float o[5];
-            eval_pot_f32<true, false>(ConstD{tab.d + k, tab.stride},
-                                      ConstF{tab.f + k, tab.stride}, x, y, o, S);
+            eval_pot_f32<true, false>(ConstD{pd + kk * NDER, 1}, ConstF{pf + kk * NDERF, 1}, x,
+                                      y, o, S);
             acc[0] += (double)o[0];
             acc[1] += (double)o[1];
         }
@@ -87,60 +106,121 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One block of SRC_BLOCK threads per sample: threads over images, then over
-// systems; per-wave shuffle sums combined in a fixed order, so a sample's
-// chi^2 does not depend on the batch it is evaluated in or on the path.
-constexpr int SRC_BLOCK = 256;
+// Per-image constants that every sample shares, computed once per call:
+// rec[0][t], rec[1][t] = fixed-potential deflection (the chunk partial sums
+// combined by one wave per image: lane l adds chunks l, l+64, ... in order,
+// then a fixed shuffle tree), rec[2][t] = the image's Dls/Ds (its system's,
+// found by bisection over the image offsets staged in LDS).
+constexpr int PREP_OFF_MAX = 4097;
+
+__global__ void __launch_bounds__(256) chi2_prep_kernel(Chi2SrcLaunch a) {
+    __shared__ int s_off[PREP_OFF_MAX];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int t = blockIdx.x * 4 + (tid >> 6);
+    double ax = 0.0, ay = 0.0;
+    if (t < a.nimg) {
+        for (int c = lane; c < a.nchunk; c += 64) {
+            ax += a.afix[((size_t)c * 2 + 0) * a.nimg_pad + t];
+            ay += a.afix[((size_t)c * 2 + 1) * a.nimg_pad + t];
+        }
+    }
+    const bool staged = a.nsys + 1 <= PREP_OFF_MAX;
+    if (staged)
+        for (int i = tid; i <= a.nsys; i += 256) s_off[i] = a.img_off[i];
+    __syncthreads();
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    if (t < a.nimg && lane == 0) {
+        const int i = system_of(staged ? s_off : a.img_off, a.nsys, t);
+        a.rec[t] = ax;
+        a.rec[(size_t)a.nimg_pad + t] = ay;
+        a.rec[2 * (size_t)a.nimg_pad + t] = a.f[i];
+    }
+}
+
+// One wave per sample.  Lane l owns images l, l+64, ... in groups of
+// SRC_IPL slots; the sample's free potentials are staged through LDS in
+// chunks and each staged potential is evaluated for all of the lane's slots
+// (the same potential order for every image).  Unlensed positions go to LDS,
+// then lanes take one system each; the per-lane sums are combined by a
+// shuffle reduction in a fixed order, so a sample's chi^2 does not depend on
+// the batch it is evaluated in, on the path or on the launch shape.
+constexpr int SRC_IPL = 4;
 
 template <int PREC>
-__global__ void __launch_bounds__(SRC_BLOCK) chi2_src_kernel(Chi2SrcLaunch a) {
-    extern __shared__ double sh[];  // [2][nimg]: unlensed x then y; then wave partials
-    __shared__ int s_next;
-    double *red = sh + 2 * (size_t)a.nimg;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int m = a.sample0 + blockIdx.x;
-    for (;;) {
-        if (a.persistent) {
-            if (tid == 0) s_next = atomicAdd(a.queue, 1);
-            __syncthreads();
-            m = s_next;
-        }
-        if (m >= a.n_samples) break;
-        const int nf = a.freet.n;
-        const int k0 = min(max(a.free_off[m], 0), nf);
-        const int k1 = min(max(a.free_off[m + 1], k0), nf);
-        for (int t = tid; t < a.nimg; t += SRC_BLOCK) {
-            const double x = a.x[t], y = a.y[t];
-            double acc[5] = {0, 0, 0, 0, 0};
-            for (int c = 0; c < a.nchunk; ++c) {
-                acc[0] += a.afix[((size_t)c * 2 + 0) * a.nimg_pad + t];
-                acc[1] += a.afix[((size_t)c * 2 + 1) * a.nimg_pad + t];
+__global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
+    extern __shared__ double sh[];  // [2][nimg] unlensed x, y; then the staged potentials
+    double *sx = sh, *sy = sh + a.nimg;
+    double *pd = sh + 2 * (size_t)a.nimg;
+    float *pf = reinterpret_cast<float *>(pd + (size_t)a.chunk * NDER);
+    const int lane = threadIdx.x;
+    const int pad = a.nimg_pad, st = a.freet.stride, nf = a.freet.n;
+    for (int m = a.sample0 + blockIdx.x; m < a.n_samples; m += gridDim.x) {
+        const int k0 = __builtin_amdgcn_readfirstlane(min(max(a.free_off[m], 0), nf));
+        const int k1 = __builtin_amdgcn_readfirstlane(min(max(a.free_off[m + 1], k0), nf));
+        for (int g0 = 0; g0 < a.nimg; g0 += 64 * SRC_IPL) {
+            double x[SRC_IPL], y[SRC_IPL], acc[SRC_IPL][5];
+#pragma unroll
+            for (int j = 0; j < SRC_IPL; ++j) {
+                const int t = g0 + j * 64 + lane;
+                const bool ok = t < a.nimg;
+                x[j] = ok ? a.x[t] : 0.0;
+                y[j] = ok ? a.y[t] : 0.0;
+                acc[j][0] = ok ? a.rec[t] : 0.0;
+                acc[j][1] = ok ? a.rec[pad + t] : 0.0;
+                acc[j][2] = acc[j][3] = acc[j][4] = 0.0;
             }
-            for (int k = k0; k < k1; ++k) {
-                if (PREC == 0) {
-                    eval_pot_f64<true, false>(ConstD{a.freet.d + k, a.freet.stride}, x, y, acc, a.S);
-                } else {
-                    float o[5];
-                    eval_pot_f32<true, false>(ConstD{a.freet.d + k, a.freet.stride},
-                                              ConstF{a.freet.f + k, a.freet.stride}, x, y, o, a.S);
-                    acc[0] += (double)o[0];
-                    acc[1] += (double)o[1];
+            for (int kc = k0; kc < k1; kc += a.chunk) {
+                const int cnt = min(a.chunk, k1 - kc);
+                __syncthreads();
+                for (int e = lane; e < cnt * NDER; e += 64) {
+                    const int ci = e / cnt, kk = e - ci * cnt;
+                    pd[kk * NDER + ci] = a.freet.d[(size_t)ci * st + kc + kk];
+                }
+                if (PREC != 0) {
+                    for (int e = lane; e < cnt * NDERF; e += 64) {
+                        const int ci = e / cnt, kk = e - ci * cnt;
+                        pf[kk * NDERF + ci] = a.freet.f[(size_t)ci * st + kc + kk];
+                    }
+                }
+                __syncthreads();
+                for (int kk = 0; kk < cnt; ++kk) {
+                    const ConstD cd{pd + kk * NDER, 1};
+#pragma unroll
+                    for (int j = 0; j < SRC_IPL; ++j) {
+                        if (g0 + j * 64 >= a.nimg) break;  // uniform: no image in this slot
+                        if (PREC == 0) {
+                            eval_pot_f64<true, false>(cd, x[j], y[j], acc[j], a.S);
+                        } else {
+                            float o[5];
+                            eval_pot_f32<true, false>(cd, ConstF{pf + kk * NDERF, 1}, x[j], y[j],
+                                                      o, a.S);
+                            acc[j][0] += (double)o[0];
+                            acc[j][1] += (double)o[1];
+                        }
+                    }
                 }
             }
-            const double f = a.f[system_of(a.img_off, a.nsys, t)];
-            sh[t] = x - f * acc[0];
-            sh[a.nimg + t] = y - f * acc[1];
+#pragma unroll
+            for (int j = 0; j < SRC_IPL; ++j) {
+                const int t = g0 + j * 64 + lane;
+                if (t < a.nimg) {
+                    const double f = a.rec[2 * (size_t)pad + t];
+                    sx[t] = x[j] - f * acc[j][0];
+                    sy[t] = y[j] - f * acc[j][1];
+                }
+            }
         }
         __syncthreads();
         double part = 0.0;
-        for (int i = tid; i < a.nsys; i += SRC_BLOCK) {
+        for (int i = lane; i < a.nsys; i += 64) {
             const int o0 = min(max(a.img_off[i], 0), a.nimg);
             const int o1 = min(max(a.img_off[i + 1], o0), a.nimg);
             const int M = o1 - o0;
             double mx = 0.0, my = 0.0;
             for (int t = o0; t < o1; ++t) {
-                mx += sh[t];
-                my += sh[a.nimg + t];
+                mx += sx[t];
+                my += sy[t];
             }
             if (M > 0) {
                 mx /= M;
@@ -148,7 +228,7 @@ __global__ void __launch_bounds__(SRC_BLOCK) chi2_src_kernel(Chi2SrcLaunch a) {
             }
             double s = 0.0;
             for (int t = o0; t < o1; ++t) {
-                const double ex = sh[t] - mx, ey = sh[a.nimg + t] - my;
+                const double ex = sx[t] - mx, ey = sy[t] - my;
                 s += (ex * ex + ey * ey) / (a.sig[t] * a.sig[t]);
             }
             part += s;
@@ -158,26 +238,38 @@ __global__ void __launch_bounds__(SRC_BLOCK) chi2_src_kernel(Chi2SrcLaunch a) {
             }
         }
         part = wave_sum(part);
-        if (lane == 0) red[wave] = part;
-        __syncthreads();
-        if (tid == 0 && a.chi2) {
-            double total = red[0];
-            for (int w = 1; w < SRC_BLOCK / 64; ++w) total += red[w];
-            a.chi2[m] = total;
-        }
-        __syncthreads();
+        if (lane == 0 && a.chi2) a.chi2[m] = part;
+        __syncthreads();  // sx, sy are rewritten by the next sample
         if (!a.persistent) break;
     }
+}
+
+// LDS: the unlensed positions plus a chunk of staged potentials; the chunk
+// shrinks for large catalogues so that a block stays within 64 KiB.
+static int src_chunk(int nimg, int prec) {
+    const size_t per = NDER * sizeof(double) + (prec ? NDERF * sizeof(float) : 0);
+    const size_t avail = 65536 - 2 * (size_t)nimg * sizeof(double);
+    return (int)std::max<size_t>(1, std::min<size_t>(8, avail / per));
+}
+
+hipError_t launch_chi2_prep(const Chi2SrcLaunch &c, hipStream_t st) {
+    if (c.nimg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(chi2_prep_kernel, dim3((c.nimg + 3) / 4), dim3(256), 0, st, c);
+    return hipGetLastError();
 }
 
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
     Chi2SrcLaunch c = c0;
     c.S = make_series();
-    const size_t shmem = ((size_t)2 * c.nimg + SRC_BLOCK / 64) * sizeof(double);
+    c.chunk = src_chunk(c.nimg, c.prec);
+    const size_t shmem =
+        2 * (size_t)c.nimg * sizeof(double) +
+        (size_t)c.chunk * (NDER * sizeof(double) + (c.prec ? NDERF * sizeof(float) : 0));
+    if (shmem > 65536) return hipErrorInvalidValue;
     if (c.prec == 0)
-        hipLaunchKernelGGL(chi2_src_kernel<0>, dim3(c.grid_blocks), dim3(SRC_BLOCK), shmem, st, c);
+        hipLaunchKernelGGL(chi2_src_kernel<0>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
     else
-        hipLaunchKernelGGL(chi2_src_kernel<1>, dim3(c.grid_blocks), dim3(SRC_BLOCK), shmem, st, c);
+        hipLaunchKernelGGL(chi2_src_kernel<1>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
     return hipGetLastError();
 }
 

@@ -8,15 +8,14 @@
 // image position are the exactly-specified FP64 expressions, bit-identical to
 // any other evaluation of the same expressions.
 //
-// Design (gfx950): one thread per grid cell (two triangles).  A thread loads
-// its four corner deflections once per grid, bounds its unlensed corners over
-// the sources' range of Dls/Ds once per chunk of sources, and then walks the
-// chunk (staged in LDS, read by broadcast), rejecting almost every source with
-// four comparisons; a wave skips the rest of the work when no lane keeps the
-// source.  Kept sources are tested exactly: corners unlensed with the
-// source's own Dls/Ds, an exact bounding-box test per triangle, and only then
-// the orientation tests (a floating-point filter with an exact expansion
-// fallback).  Found images are appended to per-source slots
+// Design (gfx950): one thread per grid cell (two triangles), a wave per 8 x 8
+// tile of cells.  A thread loads its four corner deflections once per grid;
+// the wave bounds its whole tile in the source plane once per source (64
+// sources tested at a time, one per lane), so almost every (tile, source)
+// pair is rejected without any per-cell work.  Surviving sources are tested
+// exactly: corners unlensed with the source's own Dls/Ds, an exact
+// bounding-box test per triangle, and only then the orientation tests (a
+// floating-point filter with an exact expansion fallback).  Found images are appended to per-source slots
 // with one atomic each; a second pass orders each slot list by triangle id.
 #include <math.h>
 
@@ -141,30 +140,26 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Bounds of u = v - f a over f in [f0, f1] (0 < f0 <= f1), in the rounded
-// operations u itself is computed with: rounding is monotone, so fl(v - fl(f a))
-// lies in [fl(v - max(fl(f0 a), fl(f1 a))), fl(v - min(fl(f0 a), fl(f1 a)))].
-__device__ __forceinline__ void u_range(double v, double a, double f0, double f1, double &lo,
-                                        double &hi) {
-    const double p0 = f0 * a, p1 = f1 * a;
-    lo = v - fmax(p0, p1);
-    hi = v - fmin(p0, p1);
-}
-
 constexpr int SRC_CHUNK = 256;  // sources staged in LDS per round (= block size)
+constexpr int TILE = 8;         // a wave covers TILE x TILE cells
 
-// One thread per cell (two triangles).  Sources are staged in LDS in chunks;
-// for each chunk a thread bounds its cell's unlensed vertices over the chunk's
-// range of f, so a source outside that box (by the same half-open rule as the
-// per-triangle box) is rejected with four comparisons; otherwise the corners
-// are unlensed with the source's own f and both triangles are tested.
+// One thread per cell (two triangles); a wave covers an 8 x 8 tile of cells
+// and a block 2 x 2 such tiles.  Each wave bounds its tile once: vertex
+// coordinates [vl, vh] (monotone in the index) and deflections [al, ah] (wave
+// min / max).  Rounding is monotone, so for a source with Dls/Ds f > 0 every
+// unlensed vertex fl(v - fl(f a)) of the tile lies in
+// [fl(vl - fl(f ah)), fl(vh - fl(f al))]; a source outside that box (by the
+// half-open rule of the per-triangle box) cannot be inside any of the tile's
+// triangles.  Lanes test 64 sources against the tile box at once; the wave
+// then walks only the surviving sources, unlensing its corners with the
+// source's own f and testing both triangles exactly.
 __global__ void __launch_bounds__(256) find_images_kernel(ImgLaunch L) {
     __shared__ double s_px[SRC_CHUNK], s_py[SRC_CHUNK], s_f[SRC_CHUNK];
-    __shared__ double s_fr[8];
     const int nx = L.grid.nx, ny = L.grid.ny;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i_raw = blockIdx.x * 64 + lane;
-    const int j_raw = blockIdx.y * 4 + wave;
+    const int ti0 = blockIdx.x * 2 * TILE + (wave & 1) * TILE;
+    const int tj0 = blockIdx.y * 2 * TILE + (wave >> 1) * TILE;
+    const int i_raw = ti0 + (lane & (TILE - 1)), j_raw = tj0 + lane / TILE;
     const bool valid = (i_raw + 1 < nx) && (j_raw + 1 < ny);
     const int i = min(i_raw, nx - 2), j = min(j_raw, ny - 2);
     const int g = blockIdx.z;
@@ -179,77 +174,68 @@ __global__ void __launch_bounds__(256) find_images_kernel(ImgLaunch L) {
     const double y0 = grid_coord(L.grid.y0, j, L.grid.dy);
     const double y1 = grid_coord(L.grid.y0, j + 1, L.grid.dy);
     const long long t0 = 2LL * ((long long)j * (nx - 1) + i);
-    const double inf = __builtin_inf();
+
+    // tile box: clamped cells lie inside the grid, so the vertex range runs
+    // from the first clamped cell's low corner to the last one's high corner
+    const int ci0 = min(ti0, nx - 2), ci1 = min(ti0 + TILE - 1, nx - 2);
+    const int cj0 = min(tj0, ny - 2), cj1 = min(tj0 + TILE - 1, ny - 2);
+    const double vxl = grid_coord(L.grid.x0, ci0, L.grid.dx);
+    const double vxh = grid_coord(L.grid.x0, ci1 + 1, L.grid.dx);
+    const double vyl = grid_coord(L.grid.y0, cj0, L.grid.dy);
+    const double vyh = grid_coord(L.grid.y0, cj1 + 1, L.grid.dy);
+    const double axl = wave_min(fmin(fmin(a00x, a10x), fmin(a01x, a11x)));
+    const double axh = wave_max(fmax(fmax(a00x, a10x), fmax(a01x, a11x)));
+    const double ayl = wave_min(fmin(fmin(a00y, a10y), fmin(a01y, a11y)));
+    const double ayh = wave_max(fmax(fmax(a00y, a10y), fmax(a01y, a11y)));
+
     for (int q0 = 0; q0 < L.nq; q0 += SRC_CHUNK) {
         const int nqc = min(SRC_CHUNK, L.nq - q0);
         __syncthreads();
-        double fl = inf, fh = -inf;
         if (tid < nqc) {
             const size_t gq = (size_t)g * L.nq + q0 + tid;
             s_px[tid] = L.sx[gq];
             s_py[tid] = L.sy[gq];
-            fl = fh = s_f[tid] = L.f[q0 + tid];
-        }
-        fl = wave_min(fl);
-        fh = wave_max(fh);
-        if (lane == 0) {
-            s_fr[wave] = fl;
-            s_fr[4 + wave] = fh;
+            s_f[tid] = L.f[q0 + tid];
         }
         __syncthreads();
-        const double f0 = fmin(fmin(s_fr[0], s_fr[1]), fmin(s_fr[2], s_fr[3]));
-        const double f1 = fmax(fmax(s_fr[4], s_fr[5]), fmax(s_fr[6], s_fr[7]));
-        double lx, hx, ly, hy, l2, h2;
-        u_range(x0, a00x, f0, f1, lx, hx);
-        u_range(x1, a10x, f0, f1, l2, h2);
-        lx = fmin(lx, l2);
-        hx = fmax(hx, h2);
-        u_range(x0, a01x, f0, f1, l2, h2);
-        lx = fmin(lx, l2);
-        hx = fmax(hx, h2);
-        u_range(x1, a11x, f0, f1, l2, h2);
-        lx = fmin(lx, l2);
-        hx = fmax(hx, h2);
-        u_range(y0, a00y, f0, f1, ly, hy);
-        u_range(y0, a10y, f0, f1, l2, h2);
-        ly = fmin(ly, l2);
-        hy = fmax(hy, h2);
-        u_range(y1, a01y, f0, f1, l2, h2);
-        ly = fmin(ly, l2);
-        hy = fmax(hy, h2);
-        u_range(y1, a11y, f0, f1, l2, h2);
-        ly = fmin(ly, l2);
-        hy = fmax(hy, h2);
-        if (!valid) {
-            lx = ly = inf;
-            hx = hy = -inf;
-        }
-        for (int qq = 0; qq < nqc; ++qq) {
-            const double px = s_px[qq], py = s_py[qq];
-            if (!((px >= lx) & (px < hx) & (py >= ly) & (py < hy))) continue;
-            const double f = s_f[qq];
-            const size_t gq = (size_t)g * L.nq + q0 + qq;
-            const double u00x = x0 - f * a00x, u00y = y0 - f * a00y;
-            const double u10x = x1 - f * a10x, u10y = y0 - f * a10y;
-            const double u01x = x0 - f * a01x, u01y = y1 - f * a01y;
-            const double u11x = x1 - f * a11x, u11y = y1 - f * a11y;
-            // T0 = (v[i,j], v[i+1,j], v[i,j+1])
-            if (box_may_hold(u00x, u00y, u10x, u10y, u01x, u01y, px, py) &&
-                tri_contains(u00x, u00y, u10x, u10y, u01x, u01y, px, py))
-                store_image(L, gq, t0, u00x, u00y, u10x, u10y, u01x, u01y, x0, y0, x1, y0, x0,
-                            y1, px, py);
-            // T1 = (v[i+1,j+1], v[i,j+1], v[i+1,j])
-            if (box_may_hold(u11x, u11y, u01x, u01y, u10x, u10y, px, py) &&
-                tri_contains(u11x, u11y, u01x, u01y, u10x, u10y, px, py))
-                store_image(L, gq, t0 + 1, u11x, u11y, u01x, u01y, u10x, u10y, x1, y1, x0, y1,
-                            x1, y0, px, py);
+        for (int b0 = 0; b0 < nqc; b0 += 64) {
+            bool cand = false;
+            if (b0 + lane < nqc) {
+                const double f = s_f[b0 + lane], px = s_px[b0 + lane], py = s_py[b0 + lane];
+                const double lx = vxl - f * axh, hx = vxh - f * axl;
+                const double ly = vyl - f * ayh, hy = vyh - f * ayl;
+                cand = (px >= lx) & (px < hx) & (py >= ly) & (py < hy);
+            }
+            unsigned long long mask = __ballot(cand);
+            while (mask) {
+                const int qq = b0 + __builtin_ctzll(mask);
+                mask &= mask - 1;
+                if (!valid) continue;
+                const double px = s_px[qq], py = s_py[qq], f = s_f[qq];
+                const size_t gq = (size_t)g * L.nq + q0 + qq;
+                const double u00x = x0 - f * a00x, u00y = y0 - f * a00y;
+                const double u10x = x1 - f * a10x, u10y = y0 - f * a10y;
+                const double u01x = x0 - f * a01x, u01y = y1 - f * a01y;
+                const double u11x = x1 - f * a11x, u11y = y1 - f * a11y;
+                // T0 = (v[i,j], v[i+1,j], v[i,j+1])
+                if (box_may_hold(u00x, u00y, u10x, u10y, u01x, u01y, px, py) &&
+                    tri_contains(u00x, u00y, u10x, u10y, u01x, u01y, px, py))
+                    store_image(L, gq, t0, u00x, u00y, u10x, u10y, u01x, u01y, x0, y0, x1, y0,
+                                x0, y1, px, py);
+                // T1 = (v[i+1,j+1], v[i,j+1], v[i+1,j])
+                if (box_may_hold(u11x, u11y, u01x, u01y, u10x, u10y, px, py) &&
+                    tri_contains(u11x, u11y, u01x, u01y, u10x, u10y, px, py))
+                    store_image(L, gq, t0 + 1, u11x, u11y, u01x, u01y, u10x, u10y, x1, y1, x0,
+                                y1, x1, y0, px, py);
+            }
         }
     }
 }
 
 hipError_t launch_find_images(const ImgLaunch &L, hipStream_t st) {
     if (L.grid.nx < 2 || L.grid.ny < 2 || L.n_grids <= 0 || L.nq <= 0) return hipSuccess;
-    dim3 grid((L.grid.nx - 1 + 63) / 64, (L.grid.ny - 1 + 3) / 4, L.n_grids);
+    const int span = 2 * TILE;
+    dim3 grid((L.grid.nx - 1 + span - 1) / span, (L.grid.ny - 1 + span - 1) / span, L.n_grids);
     if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(find_images_kernel, grid, dim3(256), 0, st, L);
     return hipGetLastError();

@@ -147,15 +147,17 @@ struct Chi2SrcLaunch {
     int nchunk, nimg_pad;
     double *chi2;             // [S] or NULL
     double *src_x, *src_y;    // [S*nsys] barycentric sources, or NULL
-    int *queue;               // batched path: work counter (zeroed before)
-    int persistent;           // 1: pull samples from *queue until exhausted
+    double *rec;              // [3][nimg_pad]: fixed deflection x, y and Dls/Ds per image
+    int persistent;           // 1: stride over the batch by the grid size
     int grid_blocks;
     int prec;
+    int chunk;                // potentials per LDS stage (set by the launch wrapper)
     Series S;                 // filled by the launch wrapper
 };
 hipError_t launch_fixed_alpha_points(Derived fixedt, int nimg, const double *x, const double *y,
                                      int nchunk, int nimg_pad, double *afix, int prec,
                                      hipStream_t st);
+hipError_t launch_chi2_prep(const Chi2SrcLaunch &c, hipStream_t st);
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c, hipStream_t st);
 
 // Image plane

@@ -119,10 +119,10 @@ def tune_map(ctx: B.Context, table, grid, prec=B.FP64, hess=True, reps=3, use_ca
 
 
 def tune_chi2(ctx: B.Context, fixed, free, free_off, cat, prec=B.FP64, reps=3,
-              choices=(1, 2, 4, 8, 16, 32), verbose=False):
-    """Pick and install the number of persistent blocks per CU of the batched
+              choices=(4, 8, 12, 16, 24, 32), verbose=False):
+    """Pick and install the number of persistent waves per CU of the batched
     source-plane chi^2 for this batch; every choice must give bit-identical
-    chi^2 values.  Returns (best, [(blocks_per_cu, seconds), ...])."""
+    chi^2 values.  Returns (best, [(waves_per_cu, seconds), ...])."""
     ref = None
     results = []
     for bpc in choices:
@@ -145,7 +145,7 @@ def tune_chi2(ctx: B.Context, fixed, free, free_off, cat, prec=B.FP64, reps=3,
         sec = ev0.elapsed_time(ev1) * 1e-3 / reps
         results.append((bpc, sec))
         if verbose:
-            print(f"blocks/CU {bpc}: {sec * 1e6:.1f} us")
+            print(f"waves/CU {bpc}: {sec * 1e6:.1f} us")
     results.sort(key=lambda r: r[1])
     best = results[0][0]
     ctx.set_chi2_tuning(best)
