@@ -559,8 +559,10 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
     const size_t nv = (size_t)G.nx * G.ny;
     const size_t o_afix = cv.take(2 * nv * sizeof(double));
     const size_t fixed_bytes = cv.off;
-    // per-sample working set: deflection grid + slots
-    const size_t per_sample = 2 * nv * sizeof(double) +
+    // per-sample working set: deflection grid, tile bounds, slots
+    int ntx, nty;
+    image_tiles(G.nx, G.ny, ntx, nty);
+    const size_t per_sample = 2 * nv * sizeof(double) + (size_t)ntx * nty * 4 * sizeof(double) +
                               (size_t)c->n_sys * (sizeof(int) + 2 * sizeof(double) + sizeof(int) +
                                                   (size_t)kmax * (sizeof(long long) + 2 * sizeof(double))) +
                               4096;
@@ -577,6 +579,7 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
     const size_t o_iy = cv.take((size_t)chunk * c->n_sys * kmax * sizeof(double));
     const size_t o_part = cv.take((size_t)chunk * c->n_sys * sizeof(double));
     const size_t o_miss = cv.take((size_t)chunk * c->n_sys * sizeof(int));
+    const size_t o_tb = cv.take((size_t)chunk * ntx * nty * 4 * sizeof(double));
     TRY(ensure_scratch(ctx, cv.off));
     TRY(check_contents(ctx, b, c, st));
     HIP_TRY(launch_zero_i32(ctx->small + 2, 1, st));  // overflow word
@@ -631,6 +634,7 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
         I.tri = tri;
         I.ix = ix;
         I.iy = iy;
+        I.tb = (double *)sc(ctx, o_tb);
         HIP_TRY(launch_find_images(I, st));
         HIP_TRY(launch_sort_images(ns * c->n_sys, kmax, count, tri, ix, iy, st));
         AssignLaunch Q;
@@ -686,6 +690,12 @@ lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *
     TRY(check_range(img_y, (size_t)n_src * kmax * 8, "img_y"));
     if (n_src == 0) return LENS_OK;
     DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
+    int ntx, nty;
+    image_tiles(grid->nx, grid->ny, ntx, nty);
+    Carve cv;
+    const size_t o_tb = cv.take((size_t)ntx * nty * 4 * sizeof(double));
+    TRY(ensure_scratch(ctx, cv.off));
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(launch_zero_i32(nimg, n_src, st));
     HIP_TRY(launch_fill_i64((long long *)img_tri, (size_t)n_src * kmax, -1, st));
@@ -704,6 +714,7 @@ lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *
     I.tri = (long long *)img_tri;
     I.ix = img_x;
     I.iy = img_y;
+    I.tb = (double *)sc(ctx, o_tb);
     HIP_TRY(launch_find_images(I, st));
     HIP_TRY(launch_sort_images(n_src, kmax, nimg, (long long *)img_tri, img_x, img_y, st));
     std::vector<int32_t> cnt(n_src);

@@ -8,12 +8,12 @@
 // image position are the exactly-specified FP64 expressions, bit-identical to
 // any other evaluation of the same expressions.
 //
-// Design (gfx950): one thread per grid cell (two triangles), a wave per 8 x 8
-// tile of cells.  A thread loads its four corner deflections once per grid;
-// the wave bounds its whole tile in the source plane once per source (64
-// sources tested at a time, one per lane), so almost every (tile, source)
-// pair is rejected without any per-cell work.  Surviving sources are tested
-// exactly: corners unlensed with the source's own Dls/Ds, an exact
+// Design (gfx950): the grid is cut into tiles of 8 x 8 cells.  A first pass
+// reads the deflection grid once and writes each tile's deflection bounds; a
+// second pass gives each lane a tile and bounds the tile in the source plane
+// for each source, so almost every (tile, source) pair is rejected without
+// touching the tile's cells.  A wave then visits only tiles with surviving
+// sources (lane = cell) and tests those sources exactly: corners unlensed with the source's own Dls/Ds, an exact
 // bounding-box test per triangle, and only then the orientation tests (a
 // floating-point filter with an exact expansion fallback).  Found images are appended to per-source slots
 // with one atomic each; a second pass orders each slot list by triangle id.
@@ -141,52 +141,108 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 constexpr int SRC_CHUNK = 256;  // sources staged in LDS per round (= block size)
-constexpr int TILE = 8;         // a wave covers TILE x TILE cells
+constexpr int TILE = 8;         // image-search tiles of TILE x TILE cells
 
-// One thread per cell (two triangles); a wave covers an 8 x 8 tile of cells
-// and a block 2 x 2 such tiles.  Each wave bounds its tile once: vertex
-// coordinates [vl, vh] (monotone in the index) and deflections [al, ah] (wave
-// min / max).  Rounding is monotone, so for a source with Dls/Ds f > 0 every
-// unlensed vertex fl(v - fl(f a)) of the tile lies in
-// [fl(vl - fl(f ah)), fl(vh - fl(f al))]; a source outside that box (by the
-// half-open rule of the per-triangle box) cannot be inside any of the tile's
-// triangles.  Lanes test 64 sources against the tile box at once; the wave
-// then walks only the surviving sources, unlensing its corners with the
-// source's own f and testing both triangles exactly.
-__global__ void __launch_bounds__(256) find_images_kernel(ImgLaunch L) {
-    __shared__ double s_px[SRC_CHUNK], s_py[SRC_CHUNK], s_f[SRC_CHUNK];
+// ---------------------------------------------------------------------------
+// Pass 1: deflection bounds of every tile of TILE x TILE cells, i.e. of its
+// (TILE+1) x (TILE+1) vertices (fewer at the grid's last row and column):
+// tb[((g*nty + ty)*ntx + tx)*4 + {0,1,2,3}] = min ax, max ax, min ay, max ay.
+// A tile holding a NaN deflection gets infinite bounds (it is never culled).
+// A block takes one row of tiles and TB_TILES consecutive tiles of it: each
+// thread reduces one vertex column over the tile row's TILE+1 vertex rows
+// (coalesced loads), then one thread per tile combines its TILE+1 columns.
+constexpr int TB_TILES = 32;
+constexpr int TB_COLS = TB_TILES * TILE + 1;
+
+__global__ void __launch_bounds__(256) tile_bounds_kernel(ImgLaunch L) {
+    __shared__ double s_b[4][TB_COLS];
+    __shared__ int s_bad[TB_COLS];
     const int nx = L.grid.nx, ny = L.grid.ny;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ti0 = blockIdx.x * 2 * TILE + (wave & 1) * TILE;
-    const int tj0 = blockIdx.y * 2 * TILE + (wave >> 1) * TILE;
-    const int i_raw = ti0 + (lane & (TILE - 1)), j_raw = tj0 + lane / TILE;
-    const bool valid = (i_raw + 1 < nx) && (j_raw + 1 < ny);
-    const int i = min(i_raw, nx - 2), j = min(j_raw, ny - 2);
-    const int g = blockIdx.z;
+    const int tid = threadIdx.x;
+    const int tx0 = blockIdx.x * TB_TILES, ty = blockIdx.y, g = blockIdx.z;
     const size_t nv = (size_t)nx * ny;
     const double *ax = L.alpha + (size_t)g * 2 * nv;
     const double *ay = ax + nv;
-    const size_t i00 = (size_t)j * nx + i, i10 = i00 + 1, i01 = i00 + nx, i11 = i01 + 1;
-    const double a00x = ax[i00], a00y = ay[i00], a10x = ax[i10], a10y = ay[i10];
-    const double a01x = ax[i01], a01y = ay[i01], a11x = ax[i11], a11y = ay[i11];
-    const double x0 = grid_coord(L.grid.x0, i, L.grid.dx);
-    const double x1 = grid_coord(L.grid.x0, i + 1, L.grid.dx);
-    const double y0 = grid_coord(L.grid.y0, j, L.grid.dy);
-    const double y1 = grid_coord(L.grid.y0, j + 1, L.grid.dy);
-    const long long t0 = 2LL * ((long long)j * (nx - 1) + i);
+    const double inf = __builtin_inf();
+    const int c0 = tx0 * TILE, j0 = ty * TILE, j1 = min(j0 + TILE, ny - 1);
+    for (int k = tid; k < TB_COLS; k += 256) {
+        const int c = c0 + k;
+        double xl = inf, xh = -inf, yl = inf, yh = -inf;
+        bool bad = false;
+        if (c < nx) {
+#pragma unroll
+            for (int r = 0; r <= TILE; ++r) {
+                const int j = j0 + r;
+                if (j > j1) break;
+                const size_t v = (size_t)j * nx + c;
+                const double a = ax[v], b = ay[v];
+                bad |= (a != a) | (b != b);
+                xl = fmin(xl, a);
+                xh = fmax(xh, a);
+                yl = fmin(yl, b);
+                yh = fmax(yh, b);
+            }
+        }
+        s_b[0][k] = xl;
+        s_b[1][k] = xh;
+        s_b[2][k] = yl;
+        s_b[3][k] = yh;
+        s_bad[k] = bad;
+    }
+    __syncthreads();
+    const int tx = tx0 + tid;
+    if (tid < TB_TILES && tx < L.ntx) {
+        double xl = inf, xh = -inf, yl = inf, yh = -inf;
+        bool bad = false;
+        for (int k = tid * TILE; k <= tid * TILE + TILE; ++k) {
+            xl = fmin(xl, s_b[0][k]);
+            xh = fmax(xh, s_b[1][k]);
+            yl = fmin(yl, s_b[2][k]);
+            yh = fmax(yh, s_b[3][k]);
+            bad |= s_bad[k] != 0;
+        }
+        double *r = L.tb + (((size_t)g * L.nty + ty) * L.ntx + tx) * 4;
+        r[0] = bad ? -inf : xl;
+        r[1] = bad ? inf : xh;
+        r[2] = bad ? -inf : yl;
+        r[3] = bad ? inf : yh;
+    }
+}
 
-    // tile box: clamped cells lie inside the grid, so the vertex range runs
-    // from the first clamped cell's low corner to the last one's high corner
-    const int ci0 = min(ti0, nx - 2), ci1 = min(ti0 + TILE - 1, nx - 2);
-    const int cj0 = min(tj0, ny - 2), cj1 = min(tj0 + TILE - 1, ny - 2);
-    const double vxl = grid_coord(L.grid.x0, ci0, L.grid.dx);
-    const double vxh = grid_coord(L.grid.x0, ci1 + 1, L.grid.dx);
-    const double vyl = grid_coord(L.grid.y0, cj0, L.grid.dy);
-    const double vyh = grid_coord(L.grid.y0, cj1 + 1, L.grid.dy);
-    const double axl = wave_min(fmin(fmin(a00x, a10x), fmin(a01x, a11x)));
-    const double axh = wave_max(fmax(fmax(a00x, a10x), fmax(a01x, a11x)));
-    const double ayl = wave_min(fmin(fmin(a00y, a10y), fmin(a01y, a11y)));
-    const double ayh = wave_max(fmax(fmax(a00y, a10y), fmax(a01y, a11y)));
+// Pass 2.  Lane t of a wave owns tile t of a run of 64 tiles and tests 64
+// sources at a time against its tile's box in the source plane: with vertex
+// coordinates in [vl, vh] (monotone in the index) and deflections in
+// [al, ah], rounding is monotone, so for Dls/Ds f > 0 every unlensed vertex
+// fl(v - fl(f a)) of the tile lies in [fl(vl - fl(f ah)), fl(vh - fl(f al))].
+// A source outside that box (by the half-open rule of the per-triangle box)
+// cannot be inside any of the tile's triangles.  The wave then visits only
+// tiles with surviving sources: lane = cell, corners loaded once, each
+// surviving source unlensed with its own f and both triangles tested exactly.
+__global__ void __launch_bounds__(256) find_images_kernel(ImgLaunch L) {
+    __shared__ double s_px[SRC_CHUNK], s_py[SRC_CHUNK], s_f[SRC_CHUNK];
+    const int nx = L.grid.nx, ny = L.grid.ny;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int g = blockIdx.y;
+    const int ntile = L.ntx * L.nty;
+    const int T = (blockIdx.x * 4 + (tid >> 6)) * 64 + lane;
+    const bool tile_ok = T < ntile;
+    const int tx = tile_ok ? T % L.ntx : 0, ty = tile_ok ? T / L.ntx : 0;
+    const double inf = __builtin_inf();
+    double axl = inf, axh = -inf, ayl = inf, ayh = -inf;
+    if (tile_ok) {
+        const double *r = L.tb + (((size_t)g * L.nty + ty) * L.ntx + tx) * 4;
+        axl = r[0];
+        axh = r[1];
+        ayl = r[2];
+        ayh = r[3];
+    }
+    const double vxl = grid_coord(L.grid.x0, tx * TILE, L.grid.dx);
+    const double vxh = grid_coord(L.grid.x0, min(tx * TILE + TILE, nx - 1), L.grid.dx);
+    const double vyl = grid_coord(L.grid.y0, ty * TILE, L.grid.dy);
+    const double vyh = grid_coord(L.grid.y0, min(ty * TILE + TILE, ny - 1), L.grid.dy);
+    const size_t nv = (size_t)nx * ny;
+    const double *ax = L.alpha + (size_t)g * 2 * nv;
+    const double *ay = ax + nv;
 
     for (int q0 = 0; q0 < L.nq; q0 += SRC_CHUNK) {
         const int nqc = min(SRC_CHUNK, L.nq - q0);
@@ -199,45 +255,79 @@ __global__ void __launch_bounds__(256) find_images_kernel(ImgLaunch L) {
         }
         __syncthreads();
         for (int b0 = 0; b0 < nqc; b0 += 64) {
-            bool cand = false;
-            if (b0 + lane < nqc) {
-                const double f = s_f[b0 + lane], px = s_px[b0 + lane], py = s_py[b0 + lane];
+            const int nb = min(64, nqc - b0);
+            unsigned long long mask = 0;
+            for (int k = 0; k < nb; ++k) {
+                const double f = s_f[b0 + k], px = s_px[b0 + k], py = s_py[b0 + k];
                 const double lx = vxl - f * axh, hx = vxh - f * axl;
                 const double ly = vyl - f * ayh, hy = vyh - f * ayl;
-                cand = (px >= lx) & (px < hx) & (py >= ly) & (py < hy);
+                if ((px >= lx) & (px < hx) & (py >= ly) & (py < hy)) mask |= 1ull << k;
             }
-            unsigned long long mask = __ballot(cand);
-            while (mask) {
-                const int qq = b0 + __builtin_ctzll(mask);
-                mask &= mask - 1;
-                if (!valid) continue;
-                const double px = s_px[qq], py = s_py[qq], f = s_f[qq];
-                const size_t gq = (size_t)g * L.nq + q0 + qq;
-                const double u00x = x0 - f * a00x, u00y = y0 - f * a00y;
-                const double u10x = x1 - f * a10x, u10y = y0 - f * a10y;
-                const double u01x = x0 - f * a01x, u01y = y1 - f * a01y;
-                const double u11x = x1 - f * a11x, u11y = y1 - f * a11y;
-                // T0 = (v[i,j], v[i+1,j], v[i,j+1])
-                if (box_may_hold(u00x, u00y, u10x, u10y, u01x, u01y, px, py) &&
-                    tri_contains(u00x, u00y, u10x, u10y, u01x, u01y, px, py))
-                    store_image(L, gq, t0, u00x, u00y, u10x, u10y, u01x, u01y, x0, y0, x1, y0,
-                                x0, y1, px, py);
-                // T1 = (v[i+1,j+1], v[i,j+1], v[i+1,j])
-                if (box_may_hold(u11x, u11y, u01x, u01y, u10x, u10y, px, py) &&
-                    tri_contains(u11x, u11y, u01x, u01y, u10x, u10y, px, py))
-                    store_image(L, gq, t0 + 1, u11x, u11y, u01x, u01y, u10x, u10y, x1, y1, x0,
-                                y1, x1, y0, px, py);
+            unsigned long long busy = __ballot(mask != 0ull);
+            while (busy) {
+                const int owner = __builtin_ctzll(busy);
+                busy &= busy - 1;
+                const unsigned lo = __builtin_amdgcn_readlane((unsigned)mask, owner);
+                const unsigned hi = __builtin_amdgcn_readlane((unsigned)(mask >> 32), owner);
+                unsigned long long srcs = ((unsigned long long)hi << 32) | lo;
+                const int T2 = (blockIdx.x * 4 + (tid >> 6)) * 64 + owner;
+                const int cx = T2 % L.ntx, cy = T2 / L.ntx;
+                const int i_raw = cx * TILE + (lane & (TILE - 1)), j_raw = cy * TILE + lane / TILE;
+                const bool valid = (i_raw + 1 < nx) && (j_raw + 1 < ny);
+                const int i = min(i_raw, nx - 2), j = min(j_raw, ny - 2);
+                const size_t i00 = (size_t)j * nx + i, i10 = i00 + 1, i01 = i00 + nx,
+                             i11 = i01 + 1;
+                const double a00x = ax[i00], a00y = ay[i00], a10x = ax[i10], a10y = ay[i10];
+                const double a01x = ax[i01], a01y = ay[i01], a11x = ax[i11], a11y = ay[i11];
+                const double x0 = grid_coord(L.grid.x0, i, L.grid.dx);
+                const double x1 = grid_coord(L.grid.x0, i + 1, L.grid.dx);
+                const double y0 = grid_coord(L.grid.y0, j, L.grid.dy);
+                const double y1 = grid_coord(L.grid.y0, j + 1, L.grid.dy);
+                const long long t0 = 2LL * ((long long)j * (nx - 1) + i);
+                while (srcs) {
+                    const int qq = b0 + __builtin_ctzll(srcs);
+                    srcs &= srcs - 1;
+                    if (!valid) continue;
+                    const double px = s_px[qq], py = s_py[qq], f = s_f[qq];
+                    const size_t gq = (size_t)g * L.nq + q0 + qq;
+                    const double u00x = x0 - f * a00x, u00y = y0 - f * a00y;
+                    const double u10x = x1 - f * a10x, u10y = y0 - f * a10y;
+                    const double u01x = x0 - f * a01x, u01y = y1 - f * a01y;
+                    const double u11x = x1 - f * a11x, u11y = y1 - f * a11y;
+                    // T0 = (v[i,j], v[i+1,j], v[i,j+1])
+                    if (box_may_hold(u00x, u00y, u10x, u10y, u01x, u01y, px, py) &&
+                        tri_contains(u00x, u00y, u10x, u10y, u01x, u01y, px, py))
+                        store_image(L, gq, t0, u00x, u00y, u10x, u10y, u01x, u01y, x0, y0, x1,
+                                    y0, x0, y1, px, py);
+                    // T1 = (v[i+1,j+1], v[i,j+1], v[i+1,j])
+                    if (box_may_hold(u11x, u11y, u01x, u01y, u10x, u10y, px, py) &&
+                        tri_contains(u11x, u11y, u01x, u01y, u10x, u10y, px, py))
+                        store_image(L, gq, t0 + 1, u11x, u11y, u01x, u01y, u10x, u10y, x1, y1,
+                                    x0, y1, x1, y0, px, py);
+                }
             }
         }
     }
 }
 
-hipError_t launch_find_images(const ImgLaunch &L, hipStream_t st) {
-    if (L.grid.nx < 2 || L.grid.ny < 2 || L.n_grids <= 0 || L.nq <= 0) return hipSuccess;
-    const int span = 2 * TILE;
-    dim3 grid((L.grid.nx - 1 + span - 1) / span, (L.grid.ny - 1 + span - 1) / span, L.n_grids);
-    if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(find_images_kernel, grid, dim3(256), 0, st, L);
+void image_tiles(int nx, int ny, int &ntx, int &nty) {
+    ntx = (nx - 1 + TILE - 1) / TILE;
+    nty = (ny - 1 + TILE - 1) / TILE;
+}
+
+hipError_t launch_find_images(const ImgLaunch &L0, hipStream_t st) {
+    if (L0.grid.nx < 2 || L0.grid.ny < 2 || L0.n_grids <= 0 || L0.nq <= 0) return hipSuccess;
+    ImgLaunch L = L0;
+    image_tiles(L.grid.nx, L.grid.ny, L.ntx, L.nty);
+    const long long ntile = (long long)L.ntx * L.nty;
+    if (L.n_grids > 65535) return hipErrorInvalidConfiguration;
+    if (L.nty > 65535) return hipErrorInvalidConfiguration;
+    dim3 g1((unsigned)((L.ntx + TB_TILES - 1) / TB_TILES), L.nty, L.n_grids);
+    hipLaunchKernelGGL(tile_bounds_kernel, g1, dim3(256), 0, st, L);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g2((unsigned)((ntile + 255) / 256), L.n_grids);
+    hipLaunchKernelGGL(find_images_kernel, g2, dim3(256), 0, st, L);
     return hipGetLastError();
 }
 

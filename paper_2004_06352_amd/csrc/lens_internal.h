@@ -173,7 +173,10 @@ struct ImgLaunch {
     int *count;                // [n_grids*nq]
     long long *tri;            // [n_grids*nq*kmax]
     double *ix, *iy;           // [n_grids*nq*kmax]
+    double *tb;                // [n_grids*ntx*nty*4] tile deflection bounds (scratch)
+    int ntx, nty;              // tiles per row / column (set by the launcher)
 };
+void image_tiles(int nx, int ny, int &ntx, int &nty);
 hipError_t launch_find_images(const ImgLaunch &L, hipStream_t st);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 hipError_t launch_fill_i64(long long *p, size_t n, long long v, hipStream_t st);
