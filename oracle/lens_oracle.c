@@ -14,7 +14,9 @@
  * What is computed, and where it comes from:
  *   - Lens equation beta = theta - alpha(theta), alpha = grad psi: paper Sec. 2.1, Eq. (1).
  *   - Deflection map = sum over potentials of each potential's gradient: Sec. 4.1, Eq. (10).
- *   - Hessian (second derivatives) map, the input of kappa/gamma/mu: Sec. 2.4, Eqs. (7)-(9).
+ *   - Hessian (second derivatives) map, the input of kappa/gamma/mu: Sec. 2.4, Eqs. (7)-(9);
+ *     the derived maps themselves (kappa, shear, det A^-1, mu): Sec. 2.4 with
+ *     Sec. 2.1's magnification matrix.
  *   - The paper names only the parameters of its sub-halo models (centre,
  *     velocity dispersion, ellipticity, orientation, profile parameters;
  *     Sec. 2.2) and cites Eliasdottir et al. (2007) for them.  The profile
@@ -198,6 +200,36 @@ void or_map(const or_pots_t *P, int nx, int ny, double gx0, double gy0,
                 if (mag) mag[c * np + (size_t)j * nx + i] = dlsds * macc[c];
             }
         }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Derived maps from the summed second derivatives H (already scaled by      */
+/* Dls/Ds).  Sec. 2.4, Eqs. (7)-(9) with Sec. 2.1's magnification matrix     */
+/* A^-1 = [[1 - kappa - gamma1, -gamma2], [-gamma2, 1 - kappa + gamma1]]:    */
+/*   kappa  = (Hxx + Hyy) / 2        (half the Laplacian, Eq. (7))           */
+/*   gamma1 = (Hxx - Hyy) / 2, gamma2 = Hxy, gamma = sqrt(gamma1^2+gamma2^2) */
+/*            (the shear of the summed Hessian; Eq. (8) read this way)        */
+/*   det    = (1 - kappa)^2 - gamma^2  (the determinant of A^-1)              */
+/*   mu     = 1 / det                  (Sec. 2.1; Eq. (9)'s "+" read as "-")  */
+/* ------------------------------------------------------------------------- */
+void or_derived(long n, const double *hxx, const double *hxy, const double *hyy,
+                double *kappa, double *gamma1, double *gamma2, double *gamma,
+                double *det, double *mu)
+{
+    long i;
+    for (i = 0; i < n; i++) {
+        double k = 0.5 * (hxx[i] + hyy[i]);
+        double g1 = 0.5 * (hxx[i] - hyy[i]);
+        double g2 = hxy[i];
+        double gg = g1 * g1 + g2 * g2;
+        double d = (1.0 - k) * (1.0 - k) - gg;
+        kappa[i] = k;
+        gamma1[i] = g1;
+        gamma2[i] = g2;
+        gamma[i] = sqrt(gg);
+        det[i] = d;
+        mu[i] = 1.0 / d;
     }
 }
 

@@ -155,6 +155,21 @@ def lens_map(pots, grid, dlsds=1.0, want_mag=True):
     return out, mag
 
 
+def derived(hxx, hxy, hyy):
+    """kappa, gamma1, gamma2, gamma, det (of the inverse magnification matrix)
+    and mu from a summed second-derivative map (see lens_oracle.c)."""
+    hxx, hxy, hyy = (np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (hxx, hxy, hyy))
+    shape = hxx.shape
+    n = hxx.size
+    outs = {k: np.zeros(n) for k in ("kappa", "gamma1", "gamma2", "gamma", "det", "mu")}
+    L = lib()
+    L.or_derived.argtypes = [C.c_long] + [C.POINTER(C.c_double)] * 9
+    L.or_derived.restype = None
+    L.or_derived(n, _ptr(hxx), _ptr(hxy), _ptr(hyy), _ptr(outs["kappa"]), _ptr(outs["gamma1"]),
+                 _ptr(outs["gamma2"]), _ptr(outs["gamma"]), _ptr(outs["det"]), _ptr(outs["mu"]))
+    return {k: v.reshape(shape) for k, v in outs.items()}
+
+
 def dlsds(zl, zs, om=0.3, ol=0.7):
     out = C.c_double()
     rc = lib().or_dlsds(float(zl), float(zs), float(om), float(ol), C.byref(out))

@@ -32,6 +32,10 @@ MUTANTS = [
      "part += (ex * ex + ey * ey) / C->sig[t];"),
     ("barycentre not a mean", "sx[i] = M > 0 ? mx / M : 0.0;", "sx[i] = M > 0 ? mx : 0.0;"),
     ("assignment tie", "if (bj < 0 || d2 < best) {", "if (bj < 0 || d2 <= best) {"),
+    ("magnification sign", "double d = (1.0 - k) * (1.0 - k) - gg;",
+     "double d = (1.0 - k) * (1.0 - k) + gg;"),
+    ("convergence not halved", "double k = 0.5 * (hxx[i] + hyy[i]);", "double k = hxx[i] + hyy[i];"),
+    ("shear component halved", "double g2 = hxy[i];", "double g2 = 0.5 * hxy[i];"),
     ("ellipticity conversion", "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 - e * e)); }",
      "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 + e * e)); }"),
 ]
@@ -53,6 +57,9 @@ PINS = [
     (pins.test_assignment_rules, {}),
     (pins.test_source_chi2_zero_lens_closed_form, {}),
     (pins.test_image_chi2_zero_lens_closed_form, {}),
+    (pins.test_derived_sis_closed_form, {}),
+    (pins.test_derived_circular_dpie_shear_is_mean_minus_local_convergence, {"a": 0.5, "s": 30.0}),
+    (pins.test_derived_det_is_jacobian_of_lens_mapping, {}),
 ]
 
 

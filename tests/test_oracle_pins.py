@@ -541,3 +541,100 @@ def test_image_chi2_zero_lens_closed_form(oracle):
         assert res["y"][0, i, 0] == pytest.approx(my, abs=1e-12)
     assert res["chi2"][0] == pytest.approx(want, rel=1e-9)
     assert res["nmiss"][0] == miss
+
+
+# --------------------------------------------------------------------------
+# Derived maps: convergence, shear, det of the inverse magnification matrix, mu
+# --------------------------------------------------------------------------
+def _derived_at(oracle, p, x, y, f=1.0):
+    v, m = oracle.pot_eval(p, x, y)
+    d = oracle.derived(np.array([f * v[2]]), np.array([f * v[3]]), np.array([f * v[4]]))
+    return {k: float(val[0]) for k, val in d.items()}, v, m
+
+
+def test_derived_sis_closed_form(oracle):
+    """Singular isothermal sphere scaled by f = Dls/Ds: kappa = gamma = f b0/(2r),
+    so det A^-1 = (1 - kappa)^2 - gamma^2 = 1 - f b0/r and mu = 1/(1 - f b0/r)
+    (infinite on the Einstein ring r = f b0, negative inside it)."""
+    b0 = 9.0
+    for _ in range(60):
+        f = RNG.uniform(0.3, 1.0)
+        r = 10 ** RNG.uniform(-1, 2.5)
+        t = RNG.uniform(0, 2 * math.pi)
+        d, _, _ = _derived_at(oracle, pot(0, 0, b0), r * math.cos(t), r * math.sin(t), f)
+        k = f * b0 / (2 * r)
+        assert d["kappa"] == pytest.approx(k, rel=1e-13)
+        assert d["gamma"] == pytest.approx(k, rel=1e-12)
+        assert d["det"] == pytest.approx(1 - f * b0 / r, rel=1e-10, abs=1e-13 * (1 + f * b0 / r))
+        if abs(1 - f * b0 / r) > 1e-3:
+            assert d["mu"] == pytest.approx(1 / (1 - f * b0 / r), rel=1e-9)
+        # tangential shear: gamma1 + i gamma2 = -gamma e^{2 i t} for a point mass-like profile
+        assert d["gamma1"] == pytest.approx(-k * math.cos(2 * t), abs=1e-12 * k)
+        assert d["gamma2"] == pytest.approx(-k * math.sin(2 * t), abs=1e-12 * k)
+
+
+@pytest.mark.parametrize("a,s", [(0.5, 30.0), (2.0, 400.0)])
+def test_derived_circular_dpie_shear_is_mean_minus_local_convergence(oracle, a, s):
+    """For an axisymmetric lens gamma(r) = kbar(r) - kappa(r), with the mean
+    convergence kbar = alpha(r)/r from the enclosed-mass deflection and
+    kappa(r) = (b0 F/2)[1/sqrt(a^2+r^2) - 1/sqrt(s^2+r^2)]."""
+    b0 = 15.0
+    F = s / (s - a)
+    for r in [0.05, 0.8, 2.5, 11.0, 60.0, 900.0]:
+        t = RNG.uniform(0, 2 * math.pi)
+        d, _, m = _derived_at(oracle, pot(0, 0, b0, 0.0, RNG.uniform(0, 3), a, s),
+                              r * math.cos(t), r * math.sin(t))
+        with mp.workdps(50):
+            R = mp.mpf(r)
+            alpha = b0 * F * (mp.sqrt(a * a + R * R) - a - mp.sqrt(s * s + R * R) + s) / R
+            kap = b0 * F / 2 * (1 / mp.sqrt(a * a + R * R) - 1 / mp.sqrt(s * s + R * R))
+            gam = float(alpha / R - kap)
+            kap = float(kap)
+        scale = max(m[2], m[4]) + 1e-300
+        assert d["kappa"] == pytest.approx(kap, rel=1e-12, abs=1e-14 * scale)
+        assert d["gamma"] == pytest.approx(gam, rel=1e-9, abs=1e-13 * scale)
+
+
+def test_derived_det_is_jacobian_of_lens_mapping(oracle):
+    """det A^-1 equals the determinant of d beta / d theta for beta = theta - f alpha,
+    by central differences of the deflection (O(h^2)); mu det = 1."""
+    for _ in range(40):
+        p = [RNG.uniform(-3, 3), RNG.uniform(-3, 3), RNG.uniform(2, 30), RNG.uniform(0, 0.5),
+             RNG.uniform(0, math.pi), RNG.uniform(0.05, 4), RNG.uniform(20, 500)]
+        f = RNG.uniform(0.4, 1.0)
+        x, y = RNG.uniform(-40, 40, 2)
+        h = 1e-4
+        axp, _ = oracle.pot_eval(p, x + h, y)
+        axm, _ = oracle.pot_eval(p, x - h, y)
+        ayp, _ = oracle.pot_eval(p, x, y + h)
+        aym, _ = oracle.pot_eval(p, x, y - h)
+        j11 = 1 - f * (axp[0] - axm[0]) / (2 * h)
+        j12 = -f * (ayp[0] - aym[0]) / (2 * h)
+        j21 = -f * (axp[1] - axm[1]) / (2 * h)
+        j22 = 1 - f * (ayp[1] - aym[1]) / (2 * h)
+        d, v, m = _derived_at(oracle, p, x, y, f)
+        scale = 1 + f * max(m[2], m[3], m[4])
+        assert abs(d["det"] - (j11 * j22 - j12 * j21)) < 1e-6 * scale * scale
+        assert d["mu"] * d["det"] == pytest.approx(1.0, rel=1e-14)
+
+
+def test_derived_rotation_covariance(oracle):
+    """Rotating lens and point by t leaves kappa, gamma, det unchanged and turns
+    (gamma1, gamma2) by 2t."""
+    for _ in range(30):
+        p = [0.0, 0.0, RNG.uniform(2, 30), RNG.uniform(0, 0.5), RNG.uniform(0, math.pi),
+             RNG.uniform(0.05, 4), RNG.uniform(20, 500)]
+        x, y = RNG.uniform(-30, 30, 2)
+        t = RNG.uniform(0, 2 * math.pi)
+        q = list(p)
+        q[4] = p[4] + t
+        xr, yr = rot(t) @ np.array([x, y])
+        d0, _, m = _derived_at(oracle, p, x, y)
+        d1, _, _ = _derived_at(oracle, q, xr, yr)
+        sc = max(m[2], m[3], m[4])
+        for k in ("kappa", "gamma", "det"):
+            assert d1[k] == pytest.approx(d0[k], rel=1e-11, abs=1e-12 * sc)
+        g1 = d0["gamma1"] * math.cos(2 * t) - d0["gamma2"] * math.sin(2 * t)
+        g2 = d0["gamma1"] * math.sin(2 * t) + d0["gamma2"] * math.cos(2 * t)
+        assert d1["gamma1"] == pytest.approx(g1, abs=1e-11 * sc)
+        assert d1["gamma2"] == pytest.approx(g2, abs=1e-11 * sc)
