@@ -35,10 +35,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_steps(fn, steps, warmup, torch):
+def timed_steps(fn, steps, warmup, torch, per_step=True):
+    """Wall time of `steps` calls of fn and the mean per-call time on the
+    current stream from HIP events.  per_step=False brackets the whole loop
+    with one pair of events: an event record between calls costs ~17 us of
+    device time here, which would dominate calls of ~70 us."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if not per_step:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, e0.elapsed_time(e1) * 1e-3 / steps
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
@@ -232,6 +247,15 @@ def main():
         secondary[f"map_{name}_evals_per_s"] = evals * n / w32
         secondary[f"map_{name}_avg_launch_ms"] = e32 * 1e3
         del o32
+    # derived maps (convergence, shear, magnification, det) in FP64: second
+    # derivatives only, with the derived epilogue; six planes written
+    od = {k: torch.empty((ny, nx), dtype=torch.float64, device="cuda") for k in B.DERIVED}
+    nd = max(3, args.steps // 2)
+    wd, ed = timed_steps(lambda: B.derived_map(table, grid, f, B.FP64, ctx=ctx, out=od), nd, 1,
+                         torch)
+    secondary["derived_map_fp64_evals_per_s"] = evals * nd / wd
+    secondary["derived_map_fp64_avg_launch_ms"] = ed * 1e3
+    del od
     if not args.no_chi2 and not args.only_map:
         c3 = inputs.config3()
         cat = B.catalog_to_device(B.catalog_with_dlsds(c3["catalog"], c3["zl"]))
@@ -244,15 +268,16 @@ def main():
             wpc, _ = tune.tune_chi2(ctx, fixed, free, off, cat)
             secondary["chi2_source_waves_per_cu"] = wpc
         for name, path in (("batched", B.PATH_BATCHED), ("per_sample", B.PATH_PER_SAMPLE)):
-            n = 10 if path == B.PATH_BATCHED else 3
+            n = 50 if path == B.PATH_BATCHED else 3
             w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=path, ctx=ctx),
-                               n, 1, torch)
+                               n, 1, torch, per_step=False)
             secondary[f"chi2_source_{name}_samples_per_s"] = S * n / w
-        plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx)
-        w, e = timed_steps(plan.launch, 20, 2, torch)
-        secondary["chi2_source_graph_samples_per_s"] = S * 20 / w
+        for name, resident in (("graph", False), ("graph_fixed_resident", True)):
+            plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, resident=resident)
+            w, e = timed_steps(plan.launch, 50, 2, torch, per_step=False)
+            secondary[f"chi2_source_{name}_samples_per_s"] = S * 50 / w
+            plan.close()
         secondary["chi2_source_workload"] = c3["name"]
-        plan.close()
         # image-plane chi^2: 1000^2 grid, 512 samples of the same model
         c4 = inputs.config4()
         off4 = torch.as_tensor(c4["free_off"], dtype=torch.int32, device="cuda")
@@ -261,7 +286,8 @@ def main():
         for name, prec in (("fp64", B.FP64), ("fp32_acc64", B.FP32_ACC64)):
             w, e = timed_steps(lambda: B.chi2_batch(fixed, free4, off4, cat, mode=B.CHI2_IMAGE,
                                                     prec=prec, grid=c4["grid"], kmax=64,
-                                                    penalty=100.0, ctx=ctx), 3, 1, torch)
+                                                    penalty=100.0, ctx=ctx), 3, 1, torch,
+                               per_step=False)
             secondary[f"chi2_image_{name}_samples_per_s"] = S4 * 3 / w
         secondary["chi2_image_workload"] = c4["name"]
     if not args.no_chi2 and not args.only_map and not args.no_serve:

@@ -225,6 +225,24 @@ lens_status_t lens_hessian_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
                                void *hxx, void *hxy, void *hyy, void *ax, void *ay,
                                void *stream);
 
+/* Derived maps (Sec. 2.4, Eqs. (7)-(9), with the inverse magnification matrix
+ * of Sec. 2.1, A^-1 = [[1 - kappa - gamma1, -gamma2], [-gamma2, 1 - kappa +
+ * gamma1]]), from H = dlsds * sum_k d^2 psi_k at every grid point:
+ *   kappa  = (Hxx + Hyy)/2             convergence
+ *   gamma1 = (Hxx - Hyy)/2, gamma2 = Hxy, gamma = sqrt(gamma1^2 + gamma2^2)
+ *   det    = (1 - kappa)^2 - gamma^2   det A^-1 (zero on the critical lines)
+ *   mu     = 1/det                     magnification (infinite where det = 0)
+ * The paper prints gamma^2 with the off-diagonal term inside the quarter and
+ * mu with (1 - kappa)^2 + gamma^2; the forms above are the ones its Sec. 2.1
+ * matrix gives.  Computed in one pass with the second derivatives, which are
+ * not stored.  Any output may be NULL (at least one is required); element
+ * type as for lens_grad_map (the derived values are formed in FP64 from the
+ * accumulated sums and rounded once). */
+lens_status_t lens_derived_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                               const lens_grid_t *grid, double dlsds, lens_precision_t prec,
+                               void *kappa, void *gamma1, void *gamma2, void *gamma, void *mu,
+                               void *det, void *stream);
+
 /* ---- chi^2 of a batch of samples (Sec. 2.2 Eq. (6); Sec. 2.3; Sec. 4.2) --- */
 /* chi2[m] for every sample m (device, n_samples doubles).
  * Source mode: chi2 = sum_i sum_j |beta_ij - mean_j beta_ij|^2 / sigma_ij^2,
@@ -267,10 +285,29 @@ lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *
 /* ---- captured batches (batching form) ------------------------------------ */
 /* Record the whole of one lens_chi2_batch call (batched path) into a HIP
  * graph bound to these exact buffers and shapes; replaying it re-evaluates
- * the batch with whatever the buffers then hold.  Source mode only. */
+ * the batch with whatever the buffers then hold.  Source mode only.  The plan
+ * owns its scratch (device memory allocated here, freed by
+ * lens_chi2_plan_destroy), so other calls on the context do not disturb it;
+ * it uses the context's status word and device, so destroy plans before
+ * their context.  Creating a plan synchronises `stream`. */
 lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *batch,
                                     const lens_catalog_t *cat, const lens_chi2_opts_t *opts,
                                     double *chi2, void *stream, lens_chi2_plan_t **out);
+
+/* Plan flags.
+ *   LENS_PLAN_FIXED_RESIDENT  the fixed potentials and the catalogue are read
+ *     once, when the plan is created: their per-image constants (the fixed
+ *     potentials' deflection at every constraint, each image's Dls/Ds) are
+ *     computed then and kept in the plan, and a launch evaluates only the
+ *     free potentials (the case of a sampler, where only the free parameters
+ *     change between evaluations).  The fixed table and catalogue buffers must
+ *     not change while the plan is used; results are bit-identical to the
+ *     plain batched path on the same inputs. */
+#define LENS_PLAN_FIXED_RESIDENT 1u
+lens_status_t lens_chi2_plan_create_ex(lens_ctx_t *ctx, const lens_model_batch_t *batch,
+                                       const lens_catalog_t *cat, const lens_chi2_opts_t *opts,
+                                       double *chi2, uint32_t flags, void *stream,
+                                       lens_chi2_plan_t **out);
 lens_status_t lens_chi2_plan_launch(lens_chi2_plan_t *plan, void *stream);
 lens_status_t lens_chi2_plan_destroy(lens_chi2_plan_t *plan);
 

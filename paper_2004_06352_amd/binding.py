@@ -36,7 +36,8 @@ PHYS_KEYS = ("x0", "y0", "sigma", "e", "phi", "rcore", "rcut")
 EXPORTS = ("lens_ctx_create", "lens_ctx_destroy", "lens_ctx_status", "lens_set_map_tuning",
            "lens_get_map_tuning", "lens_set_chi2_tuning", "lens_get_chi2_tuning",
            "lens_table_from_physical", "lens_grad_map",
-           "lens_hessian_map", "lens_chi2_batch", "lens_find_images", "lens_chi2_plan_create",
+           "lens_hessian_map", "lens_derived_map", "lens_chi2_batch", "lens_find_images",
+           "lens_chi2_plan_create", "lens_chi2_plan_create_ex",
            "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_dlsds",
            "lens_b0_from_sigma", "lens_eps_from_e", "lens_last_error", "lens_abi_version")
 
@@ -107,12 +108,17 @@ def lib():
         L.lens_grad_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp, vp]
         L.lens_hessian_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp,
                                        vp, vp, vp, vp]
+        L.lens_derived_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp,
+                                       vp, vp, vp, vp, vp]
         L.lens_chi2_batch.argtypes = [vp, C.POINTER(_Batch), C.POINTER(_Cat), C.POINTER(_Opts),
                                       vp, vp, vp, vp, vp]
         L.lens_find_images.argtypes = [vp, vp, vp, C.POINTER(_Grid), i32, vp, vp, vp, i32, vp,
                                        vp, vp, vp, vp]
         L.lens_chi2_plan_create.argtypes = [vp, C.POINTER(_Batch), C.POINTER(_Cat),
                                             C.POINTER(_Opts), vp, vp, C.POINTER(vp)]
+        L.lens_chi2_plan_create_ex.argtypes = [vp, C.POINTER(_Batch), C.POINTER(_Cat),
+                                               C.POINTER(_Opts), vp, C.c_uint32, vp,
+                                               C.POINTER(vp)]
         L.lens_chi2_plan_launch.argtypes = [vp, vp]
         L.lens_chi2_plan_destroy.argtypes = [vp]
         L.lens_dlsds.argtypes = [dbl, dbl, dbl, dbl, C.POINTER(dbl)]
@@ -271,6 +277,23 @@ def hessian_map(table, grid, dlsds=1.0, prec=FP64, with_alpha=True, ctx=None, ou
     return out
 
 
+DERIVED = ("kappa", "gamma1", "gamma2", "gamma", "mu", "det")
+
+
+def derived_map(table, grid, dlsds=1.0, prec=FP64, names=DERIVED, ctx=None, out=None):
+    """dict of (ny, nx) planes of the derived maps named in `names` (a subset
+    of kappa, gamma1, gamma2, gamma, mu, det)."""
+    ctx = _ctx(ctx)
+    nx, ny = int(grid[0]), int(grid[1])
+    dev = table["x0"].device
+    if out is None:
+        out = {k: torch.empty((ny, nx), dtype=_out_dtype(prec), device=dev) for k in names}
+    T, G = _pot(table), _grid(grid)
+    _check(lib().lens_derived_map(ctx.handle, C.byref(T), C.byref(G), float(dlsds), prec,
+                                  *[_ptr(out.get(k)) for k in DERIVED], _stream(dev)))
+    return out
+
+
 def _batch(fixed, free, free_off):
     return _Batch(int(free_off.numel()) - 1, free_off.data_ptr(), _pot(free), _pot(fixed))
 
@@ -345,11 +368,15 @@ def find_images(alpha, grid, src_x, src_y, f, kmax=16, ctx=None):
     return nimg, tri, ix, iy, st == -4
 
 
+PLAN_FIXED_RESIDENT = 1
+
+
 class Chi2Plan:
     """A source-plane lens_chi2_batch recorded into a HIP graph; launch()
-    replays it on the current stream over the same buffers."""
+    replays it on the current stream over the same buffers.  resident=True:
+    the fixed potentials and the catalogue are read once, at creation."""
 
-    def __init__(self, fixed, free, free_off, cat, prec=FP64, ctx=None):
+    def __init__(self, fixed, free, free_off, cat, prec=FP64, ctx=None, resident=False):
         self.ctx = _ctx(ctx)
         dev = free_off.device
         S = int(free_off.numel()) - 1
@@ -360,9 +387,10 @@ class Chi2Plan:
         h = C.c_void_p()
         self.stream = torch.cuda.Stream(device=dev)
         self.stream.wait_stream(torch.cuda.current_stream(dev))
-        _check(lib().lens_chi2_plan_create(self.ctx.handle, C.byref(B), C.byref(K), C.byref(O),
-                                           _ptr(self.chi2), C.c_void_p(self.stream.cuda_stream),
-                                           C.byref(h)))
+        _check(lib().lens_chi2_plan_create_ex(self.ctx.handle, C.byref(B), C.byref(K),
+                                              C.byref(O), _ptr(self.chi2),
+                                              PLAN_FIXED_RESIDENT if resident else 0,
+                                              C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.handle = h
 
     def launch(self):

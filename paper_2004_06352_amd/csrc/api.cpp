@@ -58,6 +58,7 @@ struct lens_ctx {
 
 struct lens_chi2_plan {
     lens_ctx_t *ctx = nullptr;
+    void *mem = nullptr;  // the plan's own scratch (derived tables, per-image constants)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -167,12 +168,14 @@ PotSoA soa(const lens_pot_table_t *t) {
     return PotSoA{t->x0, t->y0, t->b0, t->eps, t->phi, t->rcore, t->rcut};
 }
 
-Derived derived_at(lens_ctx_t *ctx, size_t off, int n) {
+Derived derived_in(char *base, size_t off, int n) {
     const int st = derived_stride(n);
-    double *d = (double *)sc(ctx, off);
+    double *d = (double *)(base + off);
     float *f = (float *)(d + (size_t)NDER * st);
     return Derived{d, f, n, st};
 }
+
+Derived derived_at(lens_ctx_t *ctx, size_t off, int n) { return derived_in(sc(ctx, off), 0, n); }
 
 lens_status_t run_prologue(lens_ctx_t *ctx, const lens_pot_table_t *t, const Derived &D,
                            hipStream_t st) {
@@ -202,7 +205,7 @@ lens_status_t status_check(lens_ctx_t *ctx, hipStream_t st) {
 
 lens_status_t map_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const lens_grid_t *grid,
                          double dlsds, lens_precision_t prec, void *out[5], bool grad, bool hess,
-                         hipStream_t st) {
+                         hipStream_t st, void *const *dout = nullptr) {
     if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
     TRY(check_prec(prec));
     TRY(check_table(table, "table"));
@@ -213,6 +216,10 @@ lens_status_t map_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const l
     const char *names[5] = {"ax", "ay", "hxx", "hxy", "hyy"};
     for (int c = 0; c < 5; ++c)
         if (out[c]) TRY(check_range(out[c], np * esz, names[c]));
+    const char *dnames[6] = {"kappa", "gamma1", "gamma2", "gamma", "mu", "det"};
+    if (dout)
+        for (int c = 0; c < 6; ++c)
+            if (dout[c]) TRY(check_range(dout[c], np * esz, dnames[c]));
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
     Carve cv;
@@ -227,6 +234,10 @@ lens_status_t map_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const l
     m.grid = GridArgs{grid->nx, grid->ny, grid->x0, grid->y0, grid->dx, grid->dy};
     m.dlsds = dlsds;
     for (int c = 0; c < 5; ++c) m.out[c] = out[c];
+    if (dout) {
+        m.derived = true;
+        for (int c = 0; c < 6; ++c) m.dout[c] = dout[c];
+    }
     m.prec = prec;
     m.grad = grad;
     m.hess = hess;
@@ -291,17 +302,16 @@ lens_status_t check_contents(lens_ctx_t *ctx, const lens_model_batch_t *b,
 }
 
 struct SrcPlan {
-    size_t o_fix, o_free, o_afix, o_rec, o_src;
-    int nchunk, nimg_pad;
+    size_t o_fix, o_free, o_rec, o_src;
+    int nimg_pad;
+    char *base = nullptr;  // scratch the offsets refer to (the context's, or a plan's own)
 };
 
 SrcPlan plan_src(Carve &cv, const lens_model_batch_t *b, const lens_catalog_t *c, bool sources) {
     SrcPlan p;
-    p.nchunk = (b->fixed.n + FIXED_CHUNK - 1) / FIXED_CHUNK;
     p.nimg_pad = (c->n_img + 63) / 64 * 64;
     p.o_fix = cv.take(derived_bytes(b->fixed.n));
     p.o_free = cv.take(derived_bytes(b->free.n));
-    p.o_afix = cv.take((size_t)std::max(p.nchunk, 1) * 2 * p.nimg_pad * sizeof(double));
     p.o_rec = cv.take((size_t)3 * p.nimg_pad * sizeof(double));
     p.o_src = sources ? cv.take((size_t)std::max(b->n_samples, 1) * c->n_sys * 2 * sizeof(double))
                       : 0;
@@ -312,19 +322,31 @@ int batched_blocks(const lens_ctx_t *ctx, int S) {
     return std::max(1, std::min(S, ctx->num_cu * ctx->chi2_blocks_per_cu));
 }
 
+// Which parts of the source-plane sequence to issue: everything; only what
+// depends on the fixed potentials and the catalogue (their prologue and the
+// per-image constants); or only what depends on the free potentials (their
+// prologue and the per-sample kernel, the per-image constants being ready).
+enum SrcParts { SRC_ALL, SRC_FIXED_ONLY, SRC_FREE_ONLY };
+
 // Prologues, fixed deflection at the constraints, then the per-sample kernel.
 lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
                            lens_precision_t prec, lens_chi2_path_t path, const SrcPlan &p,
-                           double *chi2, bool sources, hipStream_t st, bool with_check) {
-    const Derived DF = derived_at(ctx, p.o_fix, b->fixed.n);
-    const Derived DV = derived_at(ctx, p.o_free, b->free.n);
+                           double *chi2, bool sources, hipStream_t st, bool with_check,
+                           SrcParts parts = SRC_ALL) {
+    char *base = p.base ? p.base : sc(ctx, 0);
+    const Derived DF = derived_in(base, p.o_fix, b->fixed.n);
+    const Derived DV = derived_in(base, p.o_free, b->free.n);
     if (with_check) TRY(status_reset(ctx, st));
-    TRY(run_prologue(ctx, &b->fixed, DF, st));
-    TRY(run_prologue(ctx, &b->free, DV, st));
+    if (parts == SRC_ALL)
+        HIP_TRY(launch_prologue2(soa(&b->fixed), b->fixed.n, const_cast<double *>(DF.d),
+                                 const_cast<float *>(DF.f), DF.stride, soa(&b->free), b->free.n,
+                                 const_cast<double *>(DV.d), const_cast<float *>(DV.f),
+                                 DV.stride, ctx->small, st));
+    else if (parts == SRC_FIXED_ONLY)
+        TRY(run_prologue(ctx, &b->fixed, DF, st));
+    else
+        TRY(run_prologue(ctx, &b->free, DV, st));
     if (with_check) TRY(status_check(ctx, st));
-    double *afix = (double *)sc(ctx, p.o_afix);
-    HIP_TRY(launch_fixed_alpha_points(DF, c->n_img, c->x, c->y, p.nchunk, p.nimg_pad, afix, prec,
-                                      st));
     Chi2SrcLaunch L;
     L.freet = DV;
     L.free_off = b->free_offset;
@@ -337,17 +359,16 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
     L.y = c->y;
     L.sig = c->sigma;
     L.f = c->dlsds;
-    L.afix = afix;
-    L.rec = (double *)sc(ctx, p.o_rec);
-    L.nchunk = p.nchunk;
+    L.fixedt = DF;
+    L.rec = (double *)(base + p.o_rec);
     L.nimg_pad = p.nimg_pad;
     L.chi2 = chi2;
-    L.src_x = sources ? (double *)sc(ctx, p.o_src) : nullptr;
+    L.src_x = sources ? (double *)(base + p.o_src) : nullptr;
     L.src_y = sources ? L.src_x + (size_t)b->n_samples * c->n_sys : nullptr;
     const bool batched = path == LENS_CHI2_PATH_BATCHED;
     L.prec = prec == LENS_FP64 ? 0 : 1;
-    if (b->n_samples == 0) return LENS_OK;
-    HIP_TRY(launch_chi2_prep(L, st));
+    if (parts != SRC_FREE_ONLY) HIP_TRY(launch_chi2_prep(L, st));
+    if (parts == SRC_FIXED_ONLY || b->n_samples == 0) return LENS_OK;
     if (batched) {
         L.persistent = 1;
         L.grid_blocks = batched_blocks(ctx, b->n_samples);
@@ -528,6 +549,18 @@ lens_status_t lens_hessian_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
     void *out[5] = {ax, ay, hxx, hxy, hyy};
     return map_common(ctx, table, grid, dlsds, prec, out, ax != nullptr, true,
                       (hipStream_t)stream);
+}
+
+lens_status_t lens_derived_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                               const lens_grid_t *grid, double dlsds, lens_precision_t prec,
+                               void *kappa, void *gamma1, void *gamma2, void *gamma, void *mu,
+                               void *det, void *stream) {
+    void *dout[6] = {kappa, gamma1, gamma2, gamma, mu, det};
+    bool any = false;
+    for (int c = 0; c < 6; ++c) any |= dout[c] != nullptr;
+    if (!any) return fail(LENS_EINVAL, "no output requested");
+    void *out[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    return map_common(ctx, table, grid, dlsds, prec, out, false, true, (hipStream_t)stream, dout);
 }
 
 lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
@@ -726,51 +759,74 @@ lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *
 }
 
 // ---------------------------------------------------------------------------
-lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *b,
-                                    const lens_catalog_t *c, const lens_chi2_opts_t *o,
-                                    double *chi2, void *stream, lens_chi2_plan_t **out) {
+lens_status_t lens_chi2_plan_create_ex(lens_ctx_t *ctx, const lens_model_batch_t *b,
+                                       const lens_catalog_t *c, const lens_chi2_opts_t *o,
+                                       double *chi2, uint32_t flags, void *stream,
+                                       lens_chi2_plan_t **out) {
     if (!out) return fail(LENS_EINVAL, "out is NULL");
     *out = nullptr;
     TRY(check_chi2_args(ctx, b, c, o));
     if (o->mode != LENS_CHI2_SOURCE)
         return fail(LENS_EUNSUPPORTED, "captured plans cover the source-plane mode");
+    if (flags & ~LENS_PLAN_FIXED_RESIDENT)
+        return fail(LENS_EINVAL, "unknown plan flags %u", (unsigned)flags);
+    const bool resident = (flags & LENS_PLAN_FIXED_RESIDENT) != 0;
     TRY(check_range(chi2, (size_t)b->n_samples * sizeof(double), "chi2"));
     DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
     hipStream_t st = (hipStream_t)stream;
     Carve cv;
     SrcPlan sp = plan_src(cv, b, c, false);
-    TRY(ensure_scratch(ctx, cv.off));
     TRY(check_contents(ctx, b, c, st));
-    // validate table contents once, outside the capture
-    TRY(status_reset(ctx, st));
-    TRY(run_prologue(ctx, &b->fixed, derived_at(ctx, sp.o_fix, b->fixed.n), st));
-    TRY(run_prologue(ctx, &b->free, derived_at(ctx, sp.o_free, b->free.n), st));
-    TRY(status_check(ctx, st));
-    HIP_TRY(hipStreamSynchronize(st));
     lens_chi2_plan_t *p = new lens_chi2_plan_t();
     p->ctx = ctx;
-    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipMalloc(&p->mem, std::max<size_t>(cv.off, 256));
     if (e != hipSuccess) {
+        (void)hipGetLastError();
         delete p;
-        return fail(LENS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+        return fail(LENS_ENOMEM, "hipMalloc(%zu) for the plan failed", cv.off);
     }
-    lens_status_t s =
-        src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, chi2, false, st, false);
-    e = hipStreamEndCapture(st, &p->graph);
-    if (s != LENS_OK || e != hipSuccess) {
+    sp.base = (char *)p->mem;
+    auto bail = [&](lens_status_t s) {
+        (void)hipStreamSynchronize(st);
         if (p->graph) (void)hipGraphDestroy(p->graph);
+        (void)hipFree(p->mem);
         delete p;
-        if (s != LENS_OK) return s;
-        return fail(LENS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        return s;
+    };
+    // validate the tables once, outside the capture (checked contexts), and
+    // with LENS_PLAN_FIXED_RESIDENT compute the per-image constants now
+    lens_status_t s = src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr,
+                                   false, st, checked(ctx), SRC_FIXED_ONLY);
+    if (s == LENS_OK && checked(ctx)) {
+        s = status_reset(ctx, st);
+        const Derived DV = derived_in(sp.base, sp.o_free, b->free.n);
+        if (s == LENS_OK) s = run_prologue(ctx, &b->free, DV, st);
+        if (s == LENS_OK) s = status_check(ctx, st);
     }
+    if (s != LENS_OK) return bail(s);
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e)));
+    s = src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, chi2, false, st, false,
+                     resident ? SRC_FREE_ONLY : SRC_ALL);
+    e = hipStreamEndCapture(st, &p->graph);
+    if (s != LENS_OK) return bail(s);
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e)));
     e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(p->graph);
-        delete p;
-        return fail(LENS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    }
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)));
     *out = p;
     return LENS_OK;
+}
+
+lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *b,
+                                    const lens_catalog_t *c, const lens_chi2_opts_t *o,
+                                    double *chi2, void *stream, lens_chi2_plan_t **out) {
+    return lens_chi2_plan_create_ex(ctx, b, c, o, chi2, 0u, stream, out);
 }
 
 lens_status_t lens_chi2_plan_launch(lens_chi2_plan_t *p, void *stream) {
@@ -785,6 +841,7 @@ lens_status_t lens_chi2_plan_destroy(lens_chi2_plan_t *p) {
     DeviceGuard dg(p->ctx->device);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->mem) (void)hipFree(p->mem);  // waits for launches still using it
     delete p;
     return LENS_OK;
 }

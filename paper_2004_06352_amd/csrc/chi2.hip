@@ -6,8 +6,9 @@
 //
 // Design (gfx950): one wave per model sample.  What all samples share (the
 // fixed potentials' deflection at each image, each image's Dls/Ds) is
-// computed once per call; a sample then costs its free potentials at its
-// images, staged through LDS and evaluated for several images per lane.
+// computed once per call, one block per image; a sample then costs its free
+// potentials at its images, staged through LDS and evaluated for several
+// images per lane.
 // Unlensed positions go to LDS, lanes take one system each and the sums are
 // combined by a shuffle reduction in a fixed order.  The batched path
 // launches a few waves per SIMD that stride over the batch (a shared work
@@ -21,71 +22,6 @@
 #include "eval.h"
 
 namespace lens {
-
-// ---------------------------------------------------------------------------
-// Fixed-potential deflection at the catalogue points, as partial sums over
-// chunks of FIXED_CHUNK potentials (staged through LDS):
-// afix[(c*2 + {0,1})*nimg_pad + t].  Combined by the prep kernel in a fixed
-// order (deterministic).
-
-template <int PREC>
-__global__ void __launch_bounds__(64) fixed_alpha_points_kernel(Derived tab, int nimg,
-                                                                const double *__restrict__ X,
-                                                                const double *__restrict__ Y,
-                                                                int nimg_pad,
-                                                                double *__restrict__ afix,
-                                                                Series S) {
-    __shared__ double pd[FIXED_CHUNK * NDER];
-    __shared__ float pf[FIXED_CHUNK * NDERF];
-    const int lane = threadIdx.x;
-    const int t = blockIdx.x * 64 + lane;
-    const int c = blockIdx.y;
-    const int k0 = c * FIXED_CHUNK, cnt = min(tab.n - k0, FIXED_CHUNK);
-    const int st = tab.stride;
-    for (int e = lane; e < cnt * NDER; e += 64) {
-        const int ci = e / cnt, kk = e - ci * cnt;
-        pd[kk * NDER + ci] = tab.d[(size_t)ci * st + k0 + kk];
-    }
-    if (PREC != 0) {
-        for (int e = lane; e < cnt * NDERF; e += 64) {
-            const int ci = e / cnt, kk = e - ci * cnt;
-            pf[kk * NDERF + ci] = tab.f[(size_t)ci * st + k0 + kk];
-        }
-    }
-    const double x = t < nimg ? X[t] : 0.0, y = t < nimg ? Y[t] : 0.0;
-    __syncthreads();
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int kk = 0; kk < cnt; ++kk) {
-        if (PREC == 0) {
-            eval_pot_f64<true, false>(ConstD{pd + kk * NDER, 1}, x, y, acc, S);
-        } else {
-            float o[5];
-            eval_pot_f32<true, false>(ConstD{pd + kk * NDER, 1}, ConstF{pf + kk * NDERF, 1}, x,
-                                      y, o, S);
-            acc[0] += (double)o[0];
-            acc[1] += (double)o[1];
-        }
-    }
-    if (t < nimg) {
-        afix[((size_t)c * 2 + 0) * nimg_pad + t] = acc[0];
-        afix[((size_t)c * 2 + 1) * nimg_pad + t] = acc[1];
-    }
-}
-
-hipError_t launch_fixed_alpha_points(Derived fixedt, int nimg, const double *x, const double *y,
-                                     int nchunk, int nimg_pad, double *afix, int prec,
-                                     hipStream_t st) {
-    if (nchunk <= 0 || nimg <= 0) return hipSuccess;
-    dim3 grid((nimg + 63) / 64, nchunk);
-    if (grid.y > 65535u) return hipErrorInvalidConfiguration;
-    if (prec == 0)
-        hipLaunchKernelGGL(fixed_alpha_points_kernel<0>, grid, dim3(64), 0, st, fixedt, nimg, x, y,
-                           nimg_pad, afix, make_series());
-    else
-        hipLaunchKernelGGL(fixed_alpha_points_kernel<1>, grid, dim3(64), 0, st, fixedt, nimg, x, y,
-                           nimg_pad, afix, make_series());
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int system_of(const int *__restrict__ off, int nsys, int t) {
@@ -107,33 +43,53 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Per-image constants that every sample shares, computed once per call:
-// rec[0][t], rec[1][t] = fixed-potential deflection (the chunk partial sums
-// combined by one wave per image: lane l adds chunks l, l+64, ... in order,
-// then a fixed shuffle tree), rec[2][t] = the image's Dls/Ds (its system's,
-// found by bisection over the image offsets staged in LDS).
+// rec[0][t], rec[1][t] = the fixed potentials' deflection at image t and
+// rec[2][t] = the image's Dls/Ds (its system's, found by bisection over the
+// image offsets staged in LDS).  One block per image: thread l evaluates the
+// fixed potentials l, l+256, ... in that order (lanes hold different
+// potentials, so the kind branches diverge), then a shuffle tree per wave
+// and the four wave sums in order.
 constexpr int PREP_OFF_MAX = 4097;
+constexpr int PREP_BLOCK = 256;
 
-__global__ void __launch_bounds__(256) chi2_prep_kernel(Chi2SrcLaunch a) {
+template <int PREC>
+__global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) {
     __shared__ int s_off[PREP_OFF_MAX];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int t = blockIdx.x * 4 + (tid >> 6);
-    double ax = 0.0, ay = 0.0;
-    if (t < a.nimg) {
-        for (int c = lane; c < a.nchunk; c += 64) {
-            ax += a.afix[((size_t)c * 2 + 0) * a.nimg_pad + t];
-            ay += a.afix[((size_t)c * 2 + 1) * a.nimg_pad + t];
-        }
-    }
+    __shared__ double s_red[2][PREP_BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int t = blockIdx.x;
     const bool staged = a.nsys + 1 <= PREP_OFF_MAX;
     if (staged)
-        for (int i = tid; i <= a.nsys; i += 256) s_off[i] = a.img_off[i];
+        for (int i = tid; i <= a.nsys; i += PREP_BLOCK) s_off[i] = a.img_off[i];
+    double acc[5] = {0, 0, 0, 0, 0};
+    const double x = a.x[t], y = a.y[t];
+    const int st = a.fixedt.stride;
+    for (int k = tid; k < a.fixedt.n; k += PREP_BLOCK) {
+        if (PREC == 0) {
+            eval_pot_f64<true, false, false>(ConstD{a.fixedt.d + k, st}, x, y, acc, a.S);
+        } else {
+            float o[5];
+            eval_pot_f32<true, false, false>(ConstD{a.fixedt.d + k, st},
+                                             ConstF{a.fixedt.f + k, st}, x, y, o, a.S);
+            acc[0] += (double)o[0];
+            acc[1] += (double)o[1];
+        }
+    }
+    const double ax = wave_sum(acc[0]), ay = wave_sum(acc[1]);
+    if (lane == 0) {
+        s_red[0][wave] = ax;
+        s_red[1][wave] = ay;
+    }
     __syncthreads();
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    if (t < a.nimg && lane == 0) {
+    if (tid == 0) {
+        double sx = s_red[0][0], sy = s_red[1][0];
+        for (int w = 1; w < PREP_BLOCK / 64; ++w) {
+            sx += s_red[0][w];
+            sy += s_red[1][w];
+        }
         const int i = system_of(staged ? s_off : a.img_off, a.nsys, t);
-        a.rec[t] = ax;
-        a.rec[(size_t)a.nimg_pad + t] = ay;
+        a.rec[t] = sx;
+        a.rec[(size_t)a.nimg_pad + t] = sy;
         a.rec[2 * (size_t)a.nimg_pad + t] = a.f[i];
     }
 }
@@ -252,9 +208,14 @@ static int src_chunk(int nimg, int prec) {
     return (int)std::max<size_t>(1, std::min<size_t>(8, avail / per));
 }
 
-hipError_t launch_chi2_prep(const Chi2SrcLaunch &c, hipStream_t st) {
-    if (c.nimg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(chi2_prep_kernel, dim3((c.nimg + 3) / 4), dim3(256), 0, st, c);
+hipError_t launch_chi2_prep(const Chi2SrcLaunch &c0, hipStream_t st) {
+    if (c0.nimg <= 0) return hipSuccess;
+    Chi2SrcLaunch c = c0;
+    c.S = make_series();
+    if (c.prec == 0)
+        hipLaunchKernelGGL(chi2_prep_kernel<0>, dim3(c.nimg), dim3(PREP_BLOCK), 0, st, c);
+    else
+        hipLaunchKernelGGL(chi2_prep_kernel<1>, dim3(c.nimg), dim3(PREP_BLOCK), 0, st, c);
     return hipGetLastError();
 }
 
@@ -275,14 +236,21 @@ hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Vertex deflection (Dls/Ds = 1) of samples m0 .. m0+nsamp-1: the fixed part
-// (given) plus the sample's free potentials in index order.
+// (given) plus the sample's free potentials in index order.  A block covers
+// 256 vertices of one sample; the sample's potentials are staged in LDS
+// (chunks of AG_CHUNK) and read by broadcast.
+constexpr int AG_CHUNK = 16;
+
 template <int PREC>
-__global__ void __launch_bounds__(256) alpha_grid_kernel(AlphaGridLaunch a) {
+__global__ void __launch_bounds__(256, 6) alpha_grid_kernel(AlphaGridLaunch a) {
+    __shared__ double pd[AG_CHUNK * NDER];
+    __shared__ float pf[AG_CHUNK * NDERF];
     const size_t nv = (size_t)a.grid.nx * a.grid.ny;
-    const size_t v = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int tid = threadIdx.x;
+    const size_t v = (size_t)blockIdx.x * 256 + tid;
     const int s = blockIdx.y;
     const int m = a.m0 + s;
-    const int nf = a.freet.n;
+    const int nf = a.freet.n, st = a.freet.stride;
     const int k0 = min(max(a.free_off[m], 0), nf);
     const int k1 = min(max(a.free_off[m + 1], k0), nf);
     const int i = (int)(v % a.grid.nx), j = (int)(v / a.grid.nx);
@@ -293,15 +261,30 @@ __global__ void __launch_bounds__(256) alpha_grid_kernel(AlphaGridLaunch a) {
         acc[0] = a.afix_x[v];
         acc[1] = a.afix_y[v];
     }
-    for (int k = k0; k < k1; ++k) {
-        if (PREC == 0) {
-            eval_pot_f64<true, false>(ConstD{a.freet.d + k, a.freet.stride}, x, y, acc, a.S);
-        } else {
-            float o[5];
-            eval_pot_f32<true, false>(ConstD{a.freet.d + k, a.freet.stride},
-                                      ConstF{a.freet.f + k, a.freet.stride}, x, y, o, a.S);
-            acc[0] += (double)o[0];
-            acc[1] += (double)o[1];
+    for (int kc = k0; kc < k1; kc += AG_CHUNK) {
+        const int cnt = min(AG_CHUNK, k1 - kc);
+        __syncthreads();
+        for (int e = tid; e < cnt * NDER; e += 256) {
+            const int ci = e / cnt, kk = e - ci * cnt;
+            pd[kk * NDER + ci] = a.freet.d[(size_t)ci * st + kc + kk];
+        }
+        if (PREC != 0) {
+            for (int e = tid; e < cnt * NDERF; e += 256) {
+                const int ci = e / cnt, kk = e - ci * cnt;
+                pf[kk * NDERF + ci] = a.freet.f[(size_t)ci * st + kc + kk];
+            }
+        }
+        __syncthreads();
+        for (int kk = 0; kk < cnt; ++kk) {
+            if (PREC == 0) {
+                eval_pot_f64<true, false>(ConstD{pd + kk * NDER, 1}, x, y, acc, a.S);
+            } else {
+                float o[5];
+                eval_pot_f32<true, false>(ConstD{pd + kk * NDER, 1}, ConstF{pf + kk * NDERF, 1},
+                                          x, y, o, a.S);
+                acc[0] += (double)o[0];
+                acc[1] += (double)o[1];
+            }
         }
     }
     if (v < nv) {

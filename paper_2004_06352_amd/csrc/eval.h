@@ -1,9 +1,9 @@
 // eval.h -- per-potential deflection / second-derivative evaluation on gfx950.
 //
 // One call evaluates one potential at one point and adds its contribution to
-// the accumulators.  Every lane of a wave evaluates the same potential at the
-// same time, so the branches on the potential's kind are uniform across the
-// wave (the kind is read into a scalar register).
+// the accumulators.  On the hot paths every lane of a wave evaluates the same
+// potential at the same time, so the branches on the potential's kind are
+// uniform across the wave (the kind is read into a scalar register).
 //
 // Math (Keeton 2001 closed forms of the cored isothermal ellipsoid, mapped to
 // the Kassiola-Kovner ellipticity of the dPIE; the paper's Sec. 2.2 model
@@ -48,8 +48,11 @@ struct ConstF {
     __device__ __forceinline__ float operator[](int i) const { return p[i * st]; }
 };
 
+// The kind bits are the low word of the D_KIND entry's bit pattern (no
+// conversion instruction; read into a scalar register on the uniform path).
+__device__ __forceinline__ int kind_bits(double k) { return __double2loint(k); }
 __device__ __forceinline__ int uniform_kind(double k) {
-    return __builtin_amdgcn_readfirstlane((int)k);
+    return __builtin_amdgcn_readfirstlane(__double2loint(k));
 }
 
 // ---------------------------------------------------------------------------
@@ -139,14 +142,16 @@ __device__ __forceinline__ double atanh_finish(const AtanhRed &r, double s, cons
 }
 
 // ---------------------------------------------------------------------------
-template <bool GRAD, bool HESS>
-__device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y, double acc[5],
-                                             const Series &S) {
-    const int kind = uniform_kind(c[D_KIND]);
+// SING: the potential has rcore = 0, and its contribution at its own centre
+// is zero (handled by a separate instance so that regular potentials carry no
+// test for it).
+template <bool GRAD, bool HESS, bool SING>
+__device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, double x, double y,
+                                                  double acc[5], const Series &S) {
     double dx = x - c[D_X0];
     double dy = y - c[D_Y0];
     bool zero = false;
-    if (kind & K_SING) {
+    if (SING) {
         zero = (dx == 0.0) & (dy == 0.0);
         if (zero) dx = 1.0;  // any regular point; the contribution is dropped
     }
@@ -259,7 +264,7 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
             hxy = -xp * yp * ha;
         }
     }
-    if (zero) ax = ay = hxx = hxy = hyy = 0.0;
+    if (SING && zero) ax = ay = hxx = hxy = hyy = 0.0;
     if (GRAD) {
         acc[0] += fma(cp, ax, -(sp * ay));
         acc[1] += fma(sp, ax, cp * ay);
@@ -271,6 +276,19 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
         acc[3] += fma(cs, hxx - hyy, cms * hxy);
         acc[4] += fma(s2, hxx, fma(c2, hyy, t));
     }
+}
+
+// UNIF: every lane of the wave evaluates the same potential (the kind is read
+// into a scalar register and its branches are uniform); otherwise each lane
+// may hold a different potential and the branches diverge.
+template <bool GRAD, bool HESS, bool UNIF = true>
+__device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y, double acc[5],
+                                             const Series &S) {
+    const int kind = UNIF ? uniform_kind(c[D_KIND]) : kind_bits(c[D_KIND]);
+    if (kind & K_SING)
+        eval_pot_f64_impl<GRAD, HESS, true>(c, kind, x, y, acc, S);
+    else
+        eval_pot_f64_impl<GRAD, HESS, false>(c, kind, x, y, acc, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,14 +355,14 @@ __device__ __forceinline__ float atanh_finish_f(const AtanhRedF &r, float s, con
 // FP32 evaluation: offset and rotation in FP64 (|x| ~ 100" would lose
 // ~1e-5" if formed in FP32), the rest in FP32.  out[] receives this
 // potential's rotated contribution.
-template <bool GRAD, bool HESS>
-__device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, double x, double y,
-                                             float out[5], const Series &S) {
-    const int kind = uniform_kind(c[D_KIND]);
+template <bool GRAD, bool HESS, bool SING>
+__device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f, int kind,
+                                                  double x, double y, float out[5],
+                                                  const Series &S) {
     double dx = x - c[D_X0];
     double dy = y - c[D_Y0];
     bool zero = false;
-    if (kind & K_SING) {
+    if (SING) {
         zero = (dx == 0.0) & (dy == 0.0);
         if (zero) dx = 1.0;
     }
@@ -434,7 +452,7 @@ __device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, dou
             hxy = -xp * yp * ha;
         }
     }
-    if (zero) ax = ay = hxx = hxy = hyy = 0.f;
+    if (SING && zero) ax = ay = hxx = hxy = hyy = 0.f;
     if (GRAD) {
         const float cp = (float)cpd, sp = (float)spd;
         out[0] = fmaf(cp, ax, -(sp * ay));
@@ -447,6 +465,16 @@ __device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, dou
         out[3] = fmaf(cs, hxx - hyy, cms * hxy);
         out[4] = fmaf(s2, hxx, fmaf(c2, hyy, t));
     }
+}
+
+template <bool GRAD, bool HESS, bool UNIF = true>
+__device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, double x, double y,
+                                             float out[5], const Series &S) {
+    const int kind = UNIF ? uniform_kind(c[D_KIND]) : kind_bits(c[D_KIND]);
+    if (kind & K_SING)
+        eval_pot_f32_impl<GRAD, HESS, true>(c, f, kind, x, y, out, S);
+    else
+        eval_pot_f32_impl<GRAD, HESS, false>(c, f, kind, x, y, out, S);
 }
 
 // Neumaier compensated addition: s + c carries the sum to about twice the

@@ -35,7 +35,7 @@ enum DerivedIndex : int {
     D_K, D_K2,                         // k, k^2
     D_DC, D_DS, D_Q2DS,                // C_s - C_a, S_s - S_a, q^2 (S_s - S_a)
     D_PF, D_HF,                        // deflection and Hessian prefactors (F included)
-    D_KIND,                            // kind bits, stored as a small integer value
+    D_KIND,                            // kind bits: low word of the entry's bit pattern
     NDER
 };
 // Float copy of the constants used after the FP64 offset/rotation step.
@@ -105,9 +105,6 @@ struct GridArgs {
     double x0, y0, dx, dy;
 };
 
-// Fixed-potential deflections at catalogue points are summed in chunks of
-// this many potentials (partial sums combined in chunk order).
-constexpr int FIXED_CHUNK = 8;
 
 // status word bits written by device code
 enum StatusBits : int { ST_INVALID_TABLE = 1, ST_OVERFLOW = 2 };
@@ -117,6 +114,8 @@ enum StatusBits : int { ST_INVALID_TABLE = 1, ST_OVERFLOW = 2 };
 // HIP error of the launch.
 // ---------------------------------------------------------------------------
 hipError_t launch_zero_i32(int *p, int n, hipStream_t st);
+hipError_t launch_prologue2(PotSoA a, int na, double *dda, float *dfa, int sa, PotSoA b, int nb,
+                            double *ddb, float *dfb, int sb, int *status, hipStream_t st);
 hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, int *status,
                            hipStream_t st);
 hipError_t launch_phys_to_amp(const double *sigma, const double *e, int n, int convention,
@@ -127,6 +126,8 @@ struct MapLaunch {
     GridArgs grid;
     double dlsds;
     void *out[5];  // ax, ay, hxx, hxy, hyy (NULL = not stored)
+    void *dout[6] = {};     // derived: kappa, gamma1, gamma2, gamma, mu, det
+    bool derived = false;   // store the derived maps of the second derivatives instead of out[]
     int prec;
     bool grad, hess;
     lens_map_tuning_t tune;
@@ -143,8 +144,8 @@ struct Chi2SrcLaunch {
     int nsys, nimg;
     const int *img_off;
     const double *x, *y, *sig, *f;
-    const double *afix;       // [nchunk][2][nimg_pad] partial fixed deflections
-    int nchunk, nimg_pad;
+    Derived fixedt;           // derived fixed potentials (shared by all samples)
+    int nimg_pad;
     double *chi2;             // [S] or NULL
     double *src_x, *src_y;    // [S*nsys] barycentric sources, or NULL
     double *rec;              // [3][nimg_pad]: fixed deflection x, y and Dls/Ds per image
@@ -154,9 +155,6 @@ struct Chi2SrcLaunch {
     int chunk;                // potentials per LDS stage (set by the launch wrapper)
     Series S;                 // filled by the launch wrapper
 };
-hipError_t launch_fixed_alpha_points(Derived fixedt, int nimg, const double *x, const double *y,
-                                     int nchunk, int nimg_pad, double *afix, int prec,
-                                     hipStream_t st);
 hipError_t launch_chi2_prep(const Chi2SrcLaunch &c, hipStream_t st);
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c, hipStream_t st);
 

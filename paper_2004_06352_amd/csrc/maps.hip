@@ -81,10 +81,8 @@ hipError_t launch_phys_to_amp(const double *sigma, const double *e, int n, int c
 // Parameter prologue: amplitude-form table -> derived constants (FP64 block
 // and its FP32 copy).  Invalid entries get NaN prefactors (their contribution
 // is NaN) and raise ST_INVALID_TABLE.
-__global__ void prologue_kernel(PotSoA in, int n, double *__restrict__ dd, float *__restrict__ df,
-                                int stride, int *status) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+__device__ __forceinline__ void prologue_one(const PotSoA &in, int k, double *__restrict__ dd,
+                                             float *__restrict__ df, int stride, int *status) {
     const double x0 = in.x0[k], y0 = in.y0[k], b0 = in.b0[k], eps = in.eps[k];
     const double phi = in.phi[k], a = in.rcore[k], s = in.rcut[k];
     const bool cut = isfinite(s);
@@ -139,11 +137,40 @@ __global__ void prologue_kernel(PotSoA in, int n, double *__restrict__ dd, float
     v[D_Q2DS] = q2 * DS;
     v[D_PF] = PF;
     v[D_HF] = HF;
-    v[D_KIND] = (double)kind;
+    v[D_KIND] = __longlong_as_double((long long)kind);  // bit pattern, low word = kind
     for (int i = 0; i < NDER; ++i) dd[(size_t)i * stride + k] = v[i];
     const int map_f[NDERF] = {D_C2, D_S2, D_CS, D_CMS, D_Q2, D_CA, D_CS_, D_SA, D_SS, D_Q2SA,
                               D_Q2SS, D_SA2, D_SS2, D_K, D_K2, D_DC, D_DS, D_Q2DS, D_PF, D_HF};
     for (int i = 0; i < NDERF; ++i) df[(size_t)i * stride + k] = (float)v[map_f[i]];
+}
+
+__global__ void prologue_kernel(PotSoA in, int n, double *__restrict__ dd, float *__restrict__ df,
+                                int stride, int *status) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) prologue_one(in, k, dd, df, stride, status);
+}
+
+// Two tables in one launch (the fixed and the free potentials of a chi^2
+// batch): threads [0, na) take table a, [na, na + nb) table b.
+__global__ void prologue2_kernel(PotSoA a, int na, double *__restrict__ dda,
+                                 float *__restrict__ dfa, int sa, PotSoA b, int nb,
+                                 double *__restrict__ ddb, float *__restrict__ dfb, int sb,
+                                 int *status) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < na)
+        prologue_one(a, k, dda, dfa, sa, status);
+    else if (k - na < nb)
+        prologue_one(b, k - na, ddb, dfb, sb, status);
+}
+
+hipError_t launch_prologue2(PotSoA a, int na, double *dda, float *dfa, int sa, PotSoA b, int nb,
+                            double *ddb, float *dfb, int sb, int *status, hipStream_t st) {
+    const long long n = (long long)na + nb;
+    if (n <= 0) return hipSuccess;
+    if (n > 0x7fffff00LL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(prologue2_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a,
+                       na, dda, dfa, sa, b, nb, ddb, dfb, sb, status);
+    return hipGetLastError();
 }
 
 hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, int *status,
@@ -161,12 +188,40 @@ struct MapArgs {
     GridArgs g;
     double dlsds;
     void *out[5];
+    void *dout[6];
+    int derived;
     int chunk;
     Series S;
 };
 
+// Derived maps from the summed second derivatives h = (hxx, hxy, hyy) at one
+// point (Sec. 2.4, Eqs. (7)-(9), with Sec. 2.1's inverse magnification matrix
+// [[1 - kappa - gamma1, -gamma2], [-gamma2, 1 - kappa + gamma1]]):
+// kappa, gamma1, gamma2, |gamma|, mu = 1/det, det = (1 - kappa)^2 - |gamma|^2.
+__device__ __forceinline__ void derived_of(double hxx, double hxy, double hyy, double v[6]) {
+    const double k = 0.5 * (hxx + hyy);
+    const double g1 = 0.5 * (hxx - hyy);
+    const double gg = g1 * g1 + hxy * hxy;
+    const double om = 1.0 - k;
+    const double det = om * om - gg;
+    v[0] = k;
+    v[1] = g1;
+    v[2] = hxy;
+    v[3] = sqrt(gg);
+    v[4] = 1.0 / det;
+    v[5] = det;
+}
+
+// Minimum waves per SIMD the register allocation must allow: the FP64 kernel
+// with one pixel per thread fits five without spilling (the compiler's own
+// choice leaves four); the other variants keep the compiler's choice.
+template <int PREC, int PPT>
+constexpr int map_min_waves() {
+    return (PREC == 0 && PPT == 1) ? 5 : 1;
+}
+
 template <int PREC, bool GRAD, bool HESS, bool STAGE, int PPT>
-__global__ void __launch_bounds__(256) map_kernel(MapArgs a) {
+__global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(MapArgs a) {
     extern __shared__ double lds[];
     const int bx = blockDim.x, by = blockDim.y;
     const int i_base = blockIdx.x * bx * PPT + threadIdx.x;
@@ -236,6 +291,30 @@ __global__ void __launch_bounds__(256) map_kernel(MapArgs a) {
     }
 
     if (j >= a.g.ny) return;
+    if (HESS && a.derived) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int i = i_base + p * bx;
+            if (i >= a.g.nx) continue;
+            const size_t idx = (size_t)j * a.g.nx + i;
+            double h[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                h[c] = a.dlsds * (PREC == 2 ? (double)fs[p][2 + c] + (double)fc[p][2 + c]
+                                            : acc[p][2 + c]);
+            double v[6];
+            derived_of(h[0], h[1], h[2], v);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                if (a.dout[c] == nullptr) continue;
+                if (PREC == 0)
+                    static_cast<double *>(a.dout[c])[idx] = v[c];
+                else
+                    static_cast<float *>(a.dout[c])[idx] = (float)v[c];
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int i = i_base + p * bx;
@@ -300,6 +379,9 @@ hipError_t launch_map(const MapLaunch &m, hipStream_t st) {
     a.g = m.grid;
     a.dlsds = m.dlsds;
     for (int c = 0; c < 5; ++c) a.out[c] = m.out[c];
+    for (int c = 0; c < 6; ++c) a.dout[c] = m.derived ? m.dout[c] : nullptr;
+    a.derived = m.derived ? 1 : 0;
+    if (m.derived && !m.hess) return hipErrorInvalidValue;
     a.chunk = t.lds_chunk;
     a.S = make_series();
     const long long span_x = (long long)t.block_x * t.pix_per_thread;

@@ -54,3 +54,38 @@ def chi2_source_bound(bx, by, sabs, cat, rtol):
         d = np.hypot(bx[s] - mx, by[s] - my)
         total += np.sum((2 * d * D + D * D) / cat["sig"][s] ** 2)
     return total
+
+
+def derived_bounds(h, mag, rtol, stored_f32=False):
+    """Per-element error bounds of the derived maps given second derivatives
+    h = (hxx, hxy, hyy) that each err by at most rtol * mag (the map
+    tolerance): first-order propagation through kappa, gamma1, gamma2,
+    gamma, det = (1-kappa)^2 - gamma^2 plus the second-order terms, a few
+    units of rounding of the formulas themselves, and one FP32 rounding of
+    the stored value when the outputs are single precision.  mu is bounded
+    only where |det| exceeds twice its bound (elsewhere it is NaN: not
+    compared)."""
+    e = 2.0 ** -52
+    hxx, hxy, hyy = (np.asarray(v, dtype=np.float64) for v in h)
+    dxx, dxy, dyy = (rtol * np.asarray(m, dtype=np.float64) for m in mag)
+    k = 0.5 * (hxx + hyy)
+    g1 = 0.5 * (hxx - hyy)
+    g2 = hxy
+    gg = g1 * g1 + g2 * g2
+    om = 1.0 - k
+    det = om * om - gg
+    dk = 0.5 * (dxx + dyy) + 2 * e * np.abs(k)
+    dg1 = 0.5 * (dxx + dyy) + 2 * e * np.abs(g1)
+    dg2 = dxy
+    dg = dg1 + dg2 + 4 * e * np.sqrt(gg)
+    ddet = (2 * np.abs(om) * dk + dk * dk + 2 * np.abs(g1) * dg1 + dg1 * dg1
+            + 2 * np.abs(g2) * dg2 + dg2 * dg2 + 8 * e * (om * om + gg))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ok = np.abs(det) > 2 * ddet
+        mu = 1.0 / det
+        dmu = np.where(ok, ddet / (np.abs(det) * (np.abs(det) - ddet)) + 4 * e * np.abs(mu), np.nan)
+    out = dict(kappa=dk, gamma1=dg1, gamma2=dg2, gamma=dg, det=ddet, mu=dmu)
+    if stored_f32:
+        vals = dict(kappa=k, gamma1=g1, gamma2=g2, gamma=np.sqrt(gg), det=det, mu=mu)
+        out = {n: b + np.abs(vals[n]) * 2.0 ** -24 for n, b in out.items()}
+    return out

@@ -130,6 +130,52 @@ def test_captured_graph_replays_equal_eager(B, ctx):
     plan.close()
 
 
+def test_resident_plan_keeps_fixed_part_and_matches_batched(B, ctx):
+    """LENS_PLAN_FIXED_RESIDENT: the fixed potentials and catalogue are read at
+    creation; launches follow the free parameters and are bit-identical to the
+    batched path on the same inputs."""
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=300, uneven=True)
+    fixed, free, off = device_model(B, ctx, c)
+    cat = gpu_catalog(B, c)
+    plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, resident=True)
+    for r in range(3):
+        plan.chi2.fill_(-1.0)
+        out = plan.launch()
+        eager = B.chi2_batch(fixed, free, off, cat, ctx=ctx)["chi2"]
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"launch {r}"
+        free["y0"].add_(0.125)  # the next launch sees new free parameters
+    before = B.chi2_batch(fixed, free, off, cat, ctx=ctx)["chi2"].clone()
+    fixed["x0"].add_(0.5)  # not seen by the plan: its fixed part was read at creation
+    out = plan.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(out, before)
+    plan.close()
+
+
+def test_plans_survive_context_scratch_growth(B):
+    """A plan owns its scratch: a later call that grows (reallocates) the
+    context's scratch does not disturb it."""
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=200)
+    ctx2 = B.Context(0, check=False)
+    fixed, free, off = device_model(B, ctx2, c)
+    cat = gpu_catalog(B, c)
+    eager = B.chi2_batch(fixed, free, off, cat, ctx=ctx2)["chi2"].clone()
+    plans = [B.Chi2Plan(fixed, free, off, cat, ctx=ctx2, resident=r) for r in (False, True)]
+    # the image-plane mode needs far more scratch (deflection grids of 32 samples)
+    grid = inputs.pixel_centre_grid(600, -75.0, 75.0)
+    B.chi2_batch(fixed, free, off, cat, mode=B.CHI2_IMAGE, grid=grid, kmax=64, ctx=ctx2)
+    for plan in plans:
+        plan.chi2.fill_(-1.0)
+        out = plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager)
+        plan.close()
+    ctx2.close()
+
+
 def test_full_config3_batch_sampled(B, ctx, oracle):
     """All 4096 samples on the GPU in the benchmark's launch configuration
     (unchecked context, batched path); 48 sampled samples against the oracle."""
