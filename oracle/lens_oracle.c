@@ -479,6 +479,51 @@ int or_orient_perturbed(double ax, double ay, double bx, double by, double px,
 /* ------------------------------------------------------------------------- */
 /* Brute-force image search on the triangulated grid (Sec. 2.3, Fig. 4).      */
 /* ------------------------------------------------------------------------- */
+/* Refinement of one found image (Sec. 2.3: a found image is refined until a  */
+/* set precision is reached; the paper subdivides the containing triangle     */
+/* recursively).  This oracle solves the lens equation beta = theta - f alpha */
+/* (Sec. 2.1, Eq. (1)) for theta near the grid estimate by Newton's method    */
+/* with the analytic second derivatives (Sec. 2.4):                           */
+/*   r = beta - (theta - f alpha(theta)),  A = I - f H(theta),               */
+/*   theta <- theta + A^-1 r,                                                 */
+/* stopping when the step is shorter than tol.  alpha and H sum the fixed     */
+/* potentials then the sample's free ones (index order).  Returns the number  */
+/* of iterations, or -1 when the iteration does not converge within max_iter  */
+/* or leaves the box |theta - theta0| <= max_shift (each coordinate); the     */
+/* input position is then kept.                                               */
+/* ------------------------------------------------------------------------- */
+int or_refine_image(const or_pots_t *fixed, const or_pots_t *freep, int k0, int k1,
+                    double f, double bx, double by, double *x, double *y,
+                    int max_iter, double tol, double max_shift)
+{
+    double x0 = *x, y0 = *y, cx = *x, cy = *y;
+    int it;
+    for (it = 0; it < max_iter; it++) {
+        double acc[5] = {0, 0, 0, 0, 0};
+        double rx, ry, a11, a12, a22, det, sx, sy;
+        pots_sum(fixed, 0, fixed->n, cx, cy, acc, NULL);
+        pots_sum(freep, k0, k1, cx, cy, acc, NULL);
+        rx = bx - (cx - f * acc[0]);
+        ry = by - (cy - f * acc[1]);
+        a11 = 1.0 - f * acc[2];
+        a12 = -(f * acc[3]);
+        a22 = 1.0 - f * acc[4];
+        det = a11 * a22 - a12 * a12;
+        sx = (a22 * rx - a12 * ry) / det;
+        sy = (a11 * ry - a12 * rx) / det;
+        cx = cx + sx;
+        cy = cy + sy;
+        if (!(fabs(cx - x0) <= max_shift && fabs(cy - y0) <= max_shift)) return -1;
+        if (sx * sx + sy * sy < tol * tol) {
+            *x = cx;
+            *y = cy;
+            return it + 1;
+        }
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Cell (i, j), 0 <= i < nx-1, 0 <= j < ny-1, is split into
  *   T0 = (v[i,j], v[i+1,j], v[i,j+1])  and  T1 = (v[i+1,j+1], v[i,j+1], v[i+1,j]),
  * with triangle ids 2 (j (nx-1) + i) and that + 1.  Each vertex maps to the
@@ -611,7 +656,8 @@ int or_chi2_image(const or_pots_t *fixed, const or_pots_t *freep,
                   int ny, double gx0, double gy0, double dx, double dy,
                   int kmax, double penalty, double *chi2, int *nimg,
                   int *nmiss, double *img_x, double *img_y,
-                  long long *img_tri)
+                  long long *img_tri, int refine_max_iter, double refine_tol,
+                  double refine_max_shift, int *nfail)
 {
     size_t nv = (size_t)nx * ny;
     double *gax = malloc(sizeof(double) * nv), *gay = malloc(sizeof(double) * nv);
@@ -633,7 +679,8 @@ int or_chi2_image(const or_pots_t *fixed, const or_pots_t *freep,
             gay[v] = acc[1];
         }
         or_sources(fixed, freep, free_off, m, C, sx, sy);
-#pragma omp parallel for schedule(dynamic) reduction(+ : over)
+        int fails = 0;
+#pragma omp parallel for schedule(dynamic) reduction(+ : over, fails)
         for (i = 0; i < C->nsys; i++) {
             int cap = kmax > 0 ? kmax : 0;
             long long *tri = malloc(sizeof(long long) * (cap + 1));
@@ -643,6 +690,12 @@ int or_chi2_image(const or_pots_t *fixed, const or_pots_t *freep,
                                    sx[i], sy[i], cap, tri, ix, iy);
             int stored = n < cap ? n : cap, k;
             if (n > cap) over++;
+            if (refine_max_iter > 0)
+                for (k = 0; k < stored; k++)
+                    if (or_refine_image(fixed, freep, free_off[m], free_off[m + 1], C->f[i],
+                                        sx[i], sy[i], &ix[k], &iy[k], refine_max_iter,
+                                        refine_tol, refine_max_shift) < 0)
+                        fails++;
             int o = C->off[i], M = C->off[i + 1] - C->off[i];
             part[i] = or_assign_system(stored, ix, iy, M, C->x + o, C->y + o,
                                        C->sig + o, penalty, &miss[i]);
@@ -665,6 +718,7 @@ int or_chi2_image(const or_pots_t *fixed, const or_pots_t *freep,
         }
         chi2[s] = total;
         if (nmiss) nmiss[s] = nm;
+        if (nfail) nfail[s] = fails;
     }
     free(gax);
     free(gay);

@@ -83,7 +83,12 @@ def lib():
                                     C.POINTER(_Cat), dp, dp, C.c_int, C.c_int,
                                     C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.c_int, C.c_double, dp, ip, ip, dp, dp,
-                                    C.POINTER(C.c_longlong)]
+                                    C.POINTER(C.c_longlong), C.c_int, C.c_double, C.c_double,
+                                    ip]
+        L.or_refine_image.argtypes = [C.POINTER(_Pots), C.POINTER(_Pots), C.c_int, C.c_int,
+                                      C.c_double, C.c_double, C.c_double, dp, dp, C.c_int,
+                                      C.c_double, C.c_double]
+        L.or_refine_image.restype = C.c_int
         L.or_chi2_image.restype = C.c_int
         L.or_edge_margin.argtypes = [dp, dp, C.c_int, C.c_int] + [C.c_double] * 7
         L.or_edge_margin.restype = C.c_double
@@ -256,8 +261,11 @@ def alpha_grid(pots, grid):
 
 
 def chi2_image(fixed, free, free_off, cat, grid, m0=0, m1=None, kmax=16,
-               penalty=0.0, alpha_fix=None):
-    """Image-plane chi^2 of samples [m0, m1) -> dict of arrays (see lens_oracle.c)."""
+               penalty=0.0, alpha_fix=None, refine=None):
+    """Image-plane chi^2 of samples [m0, m1) -> dict of arrays (see lens_oracle.c).
+    refine = (max_iter, tol, max_shift) refines every stored image by Newton's
+    method before the assignment; `nfail` counts images left at the grid
+    estimate."""
     nx, ny, gx0, gy0, dx, dy = grid
     if m1 is None:
         m1 = len(free_off) - 1
@@ -274,12 +282,30 @@ def chi2_image(fixed, free, free_off, cat, grid, m0=0, m1=None, kmax=16,
     ix = np.zeros((S, ns, kmax))
     iy = np.zeros((S, ns, kmax))
     itri = np.full((S, ns, kmax), -1, dtype=np.int64)
+    nfail = np.zeros(S, dtype=np.int32)
+    it, tol, shift = refine if refine is not None else (0, 0.0, 0.0)
     over = lib().or_chi2_image(C.byref(Pf), C.byref(Pv), _ptr(off, C.c_int), m0, m1,
                                C.byref(Cc), _ptr(afx), _ptr(afy), nx, ny, gx0, gy0, dx, dy,
                                kmax, float(penalty), _ptr(chi2), _ptr(nimg, C.c_int),
                                _ptr(nmiss, C.c_int), _ptr(ix), _ptr(iy),
-                               itri.ctypes.data_as(C.POINTER(C.c_longlong)))
-    return dict(chi2=chi2, nimg=nimg, nmiss=nmiss, x=ix, y=iy, tri=itri, overflow=over)
+                               itri.ctypes.data_as(C.POINTER(C.c_longlong)), int(it),
+                               float(tol), float(shift), _ptr(nfail, C.c_int))
+    return dict(chi2=chi2, nimg=nimg, nmiss=nmiss, x=ix, y=iy, tri=itri, overflow=over,
+                nfail=nfail)
+
+
+def refine_image(fixed, free, f, beta, theta, max_iter=20, tol=1e-10, max_shift=1.0):
+    """Newton refinement of one image position theta for the source beta with
+    Dls/Ds f; the model is the fixed potentials plus `free` (all of it).
+    Returns (x, y, iterations or -1)."""
+    keep = _Keep()
+    Pf, Pv = _pots(fixed, keep), _pots(free, keep)
+    x, y = C.c_double(float(theta[0])), C.c_double(float(theta[1]))
+    n = len(np.atleast_1d(free["x0"]))
+    it = lib().or_refine_image(C.byref(Pf), C.byref(Pv), 0, n, float(f), float(beta[0]),
+                               float(beta[1]), C.byref(x), C.byref(y), int(max_iter), float(tol),
+                               float(max_shift))
+    return x.value, y.value, it
 
 
 def edge_margin(ax, ay, grid, f, px, py):

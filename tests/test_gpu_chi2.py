@@ -52,10 +52,15 @@ def check_samples(O, c, got, samples, rtol):
     sizes = [off[m + 1] - off[m] for m in samples]
     sub_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
     ref = O.chi2_source(fixed, sub_free, sub_off, cat)
+    worst_b = worst_r = 0.0
     for r, m in enumerate(samples):
         bx, by, sabs = O.unlens(fixed, sub_free, sub_off, r, cat)
         bound = chi2_source_bound(bx, by, sabs, cat, rtol)
-        assert abs(got[m] - ref[r]) <= bound, (m, got[m], ref[r], bound)
+        err = abs(got[m] - ref[r])
+        assert err <= bound, (m, got[m], ref[r], bound)
+        worst_b = max(worst_b, err / bound if bound > 0 else 0.0)
+        worst_r = max(worst_r, err / abs(ref[r]) if ref[r] != 0 else 0.0)
+    check_samples.last = (worst_r, worst_b)
     return ref
 
 
@@ -68,6 +73,8 @@ def test_source_chi2_matches_oracle(B, ctx, oracle, prec):
     torch.cuda.synchronize()
     got = res["chi2"].cpu().numpy()
     check_samples(oracle, c, got, list(range(192)), RTOL[prec])
+    rel, frac = check_samples.last
+    print(f"source chi2 prec={prec}: max |err|/chi2 {rel:.3g}, max |err|/bound {frac:.3g}")
 
 
 def test_paths_agree_bit_for_bit_on_uneven_samples(B, ctx, oracle):

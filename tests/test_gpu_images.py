@@ -134,6 +134,7 @@ def compare_image_results(O, c, grid, got, ref, cat, samples, m0):
     position tolerance allows."""
     fixed, free = O.phys_to_pots(c["fixed"]), O.phys_to_pots(c["free"])
     flagged = 0
+    worst_pos = worst_chi2 = 0.0
     for r, m in enumerate(samples):
         s = m - m0
         mism = np.nonzero(got["nimg"][m] != ref["nimg"][s])[0]
@@ -153,9 +154,12 @@ def compare_image_results(O, c, grid, got, ref, cat, samples, m0):
             d = np.hypot(got["img_xy"][m, i, :k, 0] - ref["x"][s, i, :k],
                          got["img_xy"][m, i, :k, 1] - ref["y"][s, i, :k])
             assert np.all(d < 1e-7), (m, i, d)
+            worst_pos = max(worst_pos, float(d.max()) if d.size else 0.0)
         assert got["nmissing"][m] == ref["nmiss"][s]
         assert abs(got["chi2"][m] - ref["chi2"][s]) <= 1e-6 * max(1.0, ref["chi2"][s]), (
             m, got["chi2"][m], ref["chi2"][s])
+        worst_chi2 = max(worst_chi2, abs(got["chi2"][m] - ref["chi2"][s]) / max(1.0, ref["chi2"][s]))
+    compare_image_results.last = (worst_pos, worst_chi2)
     return flagged
 
 
@@ -167,7 +171,9 @@ def test_image_chi2_end_to_end_small_grid(B, ctx, oracle):
     assert not got["overflow"]
     ref, cat = oracle_image_chi2(oracle, c, grid, 0, 8, 16, 100.0)
     flagged = compare_image_results(oracle, c, grid, got, ref, cat, range(8), 0)
-    print("flagged near-edge systems:", flagged)
+    pos, rel = compare_image_results.last
+    print(f"image chi2 FP64 end to end: flagged near-edge systems {flagged}, max image position "
+          f"error {pos:.3g} arcsec, max chi2 error {rel:.3g} (relative, floor 1)")
     # the per-sample path gives identical results
     per = run_gpu_image_chi2(B, ctx, c, grid, 16, 100.0, path=B.PATH_PER_SAMPLE)
     assert np.array_equal(per["chi2"], got["chi2"]) and np.array_equal(per["nimg"], got["nimg"])

@@ -36,6 +36,9 @@ MUTANTS = [
      "double d = (1.0 - k) * (1.0 - k) + gg;"),
     ("convergence not halved", "double k = 0.5 * (hxx[i] + hyy[i]);", "double k = hxx[i] + hyy[i];"),
     ("shear component halved", "double g2 = hxy[i];", "double g2 = 0.5 * hxy[i];"),
+    ("Newton update sign", "        cx = cx + sx;", "        cx = cx - sx;"),
+    ("lens equation residual sign", "rx = bx - (cx - f * acc[0]);", "rx = bx - (cx + f * acc[0]);"),
+    ("refinement skipped", "if (refine_max_iter > 0)", "if (refine_max_iter > 1000)"),
     ("ellipticity conversion", "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 - e * e)); }",
      "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 + e * e)); }"),
 ]
@@ -60,6 +63,9 @@ PINS = [
     (pins.test_derived_sis_closed_form, {}),
     (pins.test_derived_circular_dpie_shear_is_mean_minus_local_convergence, {"a": 0.5, "s": 30.0}),
     (pins.test_derived_det_is_jacobian_of_lens_mapping, {}),
+    (pins.test_refine_sis_images_are_exact, {}),
+    (pins.test_refine_cored_lens_matches_radial_roots, {}),
+    (pins.test_refined_image_chi2_vanishes_for_noise_free_constraints, {}),
 ]
 
 
