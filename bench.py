@@ -289,6 +289,12 @@ def main():
                                                     penalty=100.0, ctx=ctx), 3, 1, torch,
                                per_step=False)
             secondary[f"chi2_image_{name}_samples_per_s"] = S4 * 3 / w
+        # the same with every found image refined by Newton's method to 1e-10"
+        w, e = timed_steps(lambda: B.chi2_batch(fixed, free4, off4, cat, mode=B.CHI2_IMAGE,
+                                                grid=c4["grid"], kmax=64, penalty=100.0,
+                                                refine=(20, 1e-10), ctx=ctx), 3, 1, torch,
+                           per_step=False)
+        secondary["chi2_image_fp64_refined_samples_per_s"] = S4 * 3 / w
         secondary["chi2_image_workload"] = c4["name"]
     if not args.no_chi2 and not args.only_map and not args.no_serve:
         log("serving stream")

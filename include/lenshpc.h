@@ -73,7 +73,7 @@
 extern "C" {
 #endif
 
-#define LENSHPC_ABI_VERSION 1
+#define LENSHPC_ABI_VERSION 2
 
 typedef int32_t lens_status_t;
 #define LENS_OK 0
@@ -170,6 +170,10 @@ typedef struct {
     lens_grid_t grid;          /* image mode: the triangulated grid */
     int32_t max_img_per_sys;   /* image mode: stored images per (sample, system), 1..64 */
     double missing_penalty;    /* image mode: added per constraint left without an image */
+    int32_t refine_max_iter;   /* image mode: Newton iterations per found image, 0..64
+                                  (0: positions stay the grid estimates) */
+    double refine_tol;         /* image mode, refine_max_iter > 0: stop when a Newton step
+                                  is shorter than this [arcsec], > 0 */
 } lens_chi2_opts_t;
 
 /* Launch configuration of the map kernel (chosen by the autotuner).

@@ -74,7 +74,8 @@ class _Cat(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("prec", C.c_int32), ("path", C.c_int32), ("grid", _Grid),
-                ("max_img_per_sys", C.c_int32), ("missing_penalty", C.c_double)]
+                ("max_img_per_sys", C.c_int32), ("missing_penalty", C.c_double),
+                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double)]
 
 
 class MapTuning(C.Structure):
@@ -311,15 +312,17 @@ def catalog_to_device(cat, device="cuda"):
                 f=_dev(cat["f"], device))
 
 
-def _opts(mode, prec, path, grid, kmax, penalty):
+def _opts(mode, prec, path, grid, kmax, penalty, refine=None):
     g = _grid(grid) if grid is not None else _Grid(0, 0, 0, 0, 0, 0)
-    return _Opts(mode, prec, path, g, int(kmax), float(penalty))
+    it, tol = refine if refine is not None else (0, 0.0)
+    return _Opts(mode, prec, path, g, int(kmax), float(penalty), int(it), float(tol))
 
 
 def chi2_batch(fixed, free, free_off, cat, mode=CHI2_SOURCE, prec=FP64, path=PATH_BATCHED,
-               grid=None, kmax=16, penalty=0.0, want_images=False, ctx=None):
+               grid=None, kmax=16, penalty=0.0, want_images=False, refine=None, ctx=None):
     """chi^2 of every sample; image mode also returns nimg, nmissing (and
-    img_xy (S, nsys, kmax, 2) when want_images)."""
+    img_xy (S, nsys, kmax, 2) when want_images).  refine = (max_iter, tol)
+    refines every found image by Newton's method on the lens equation."""
     ctx = _ctx(ctx)
     dev = free_off.device
     S = int(free_off.numel()) - 1
@@ -335,7 +338,7 @@ def chi2_batch(fixed, free, free_off, cat, mode=CHI2_SOURCE, prec=FP64, path=PAT
             img = torch.empty((S, nsys, kmax, 2), dtype=torch.float64, device=dev)
             res["img_xy"] = img
     B, K = _batch(fixed, free, free_off), _catalog(cat)
-    O = _opts(mode, prec, path, grid, kmax, penalty)
+    O = _opts(mode, prec, path, grid, kmax, penalty, refine)
     st = lib().lens_chi2_batch(ctx.handle, C.byref(B), C.byref(K), C.byref(O), _ptr(chi2),
                                _ptr(nimg), _ptr(nmiss), _ptr(img), _stream(dev))
     if st == -4:

@@ -403,6 +403,10 @@ lens_status_t check_chi2_args(lens_ctx_t *ctx, const lens_model_batch_t *b,
             return fail(LENS_EINVAL, "max_img_per_sys = %d (1..64)", o->max_img_per_sys);
         if (!is_fin(o->missing_penalty))
             return fail(LENS_EINVAL, "missing_penalty is not finite");
+        if (o->refine_max_iter < 0 || o->refine_max_iter > 64)
+            return fail(LENS_EINVAL, "refine_max_iter = %d (0..64)", o->refine_max_iter);
+        if (o->refine_max_iter > 0 && !(o->refine_tol > 0.0 && is_fin(o->refine_tol)))
+            return fail(LENS_EINVAL, "refine_tol = %g (> 0)", o->refine_tol);
     }
     return LENS_OK;
 }
@@ -599,7 +603,7 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
                               (size_t)c->n_sys * (sizeof(int) + 2 * sizeof(double) + sizeof(int) +
                                                   (size_t)kmax * (sizeof(long long) + 2 * sizeof(double))) +
                               4096;
-    int chunk = o->path == LENS_CHI2_PATH_PER_SAMPLE ? 1 : 32;
+    int chunk = o->path == LENS_CHI2_PATH_PER_SAMPLE ? 1 : 128;
     if (ctx->scratch_max > fixed_bytes) {
         const size_t fit = (ctx->scratch_max - fixed_bytes) / per_sample;
         chunk = (int)std::min<size_t>(chunk, std::max<size_t>(fit, 1));
@@ -670,6 +674,26 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
         I.tb = (double *)sc(ctx, o_tb);
         HIP_TRY(launch_find_images(I, st));
         HIP_TRY(launch_sort_images(ns * c->n_sys, kmax, count, tri, ix, iy, st));
+        if (o->refine_max_iter > 0) {
+            RefineLaunch F;
+            F.fixedt = DF;
+            F.freet = DV;
+            F.free_off = b->free_offset;
+            F.m0 = m0;
+            F.nsamp = ns;
+            F.nsys = c->n_sys;
+            F.kmax = kmax;
+            F.count = count;
+            F.ix = ix;
+            F.iy = iy;
+            F.sx = I.sx;
+            F.sy = I.sy;
+            F.f = c->dlsds;
+            F.max_iter = o->refine_max_iter;
+            F.tol = o->refine_tol;
+            F.max_shift = 2.0 * std::max(G.dx, G.dy);
+            HIP_TRY(launch_refine_images(F, st));
+        }
         AssignLaunch Q;
         Q.nsamp = ns;
         Q.nsys = c->n_sys;

@@ -307,4 +307,147 @@ hipError_t launch_alpha_grid(const AlphaGridLaunch &L0, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Newton refinement of found images (the refinement of a found image, Sec.
+// 2.3, done by Newton's method on the lens equation of Sec. 2.1, Eq. (1),
+// with the analytic second derivatives of Sec. 2.4):
+//   r = beta - (theta - f alpha(theta)),  A = I - f H(theta),
+//   theta <- theta + A^-1 r  until |step| < tol;
+// an image whose iterate leaves the box |theta - theta0| <= max_shift or
+// does not converge within max_iter keeps its grid estimate.
+//
+// Design: a block of RF_WAVES waves takes 64 images of one sample (lane l of
+// every wave holds image l); the potentials (fixed then the sample's free
+// ones) are staged in LDS in chunks and wave w evaluates every RF_WAVES-th of
+// them, so one image's 300-odd potentials are spread over the block.  The
+// wave partial sums are combined in wave order by every wave, which then
+// takes the same Newton step.
+constexpr int RF_WAVES = 8;
+constexpr int RF_THREADS = 64 * RF_WAVES;
+constexpr int RF_CHUNK = 64;
+
+__global__ void __launch_bounds__(RF_THREADS) refine_images_kernel(RefineLaunch a) {
+    __shared__ double pd[RF_CHUNK * NDER];
+    __shared__ double red[RF_WAVES][5][64];
+    __shared__ int s_pre[RF_THREADS + 1];
+    __shared__ int s_sys[64], s_k[64];
+    __shared__ int s_total;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int s = blockIdx.x, g = blockIdx.y, m = a.m0 + s;
+    // locate image t = 64 g + lane of this sample: scan the systems' stored
+    // counts in windows of RF_THREADS systems
+    if (tid < 64) s_sys[tid] = -1;
+    int base = 0;
+    for (int sys0 = 0; sys0 < a.nsys; sys0 += RF_THREADS) {
+        const int i = sys0 + tid;
+        const int n = i < a.nsys ? min(max(a.count[(size_t)s * a.nsys + i], 0), a.kmax) : 0;
+        __syncthreads();
+        if (tid == 0) s_pre[0] = 0;
+        s_pre[tid + 1] = n;
+        __syncthreads();
+        for (int d = 1; d < RF_THREADS; d <<= 1) {
+            const int v = tid >= d ? s_pre[tid + 1 - d] : 0;
+            __syncthreads();
+            s_pre[tid + 1] += v;
+            __syncthreads();
+        }
+        const int wtot = s_pre[RF_THREADS];
+        if (tid < 64) {
+            const int t = g * 64 + tid - base;
+            if (t >= 0 && t < wtot) {
+                int lo = 0, hi = RF_THREADS;  // largest c with s_pre[c] <= t
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pre[mid] <= t)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                s_sys[tid] = sys0 + lo;
+                s_k[tid] = t - s_pre[lo];
+            }
+        }
+        base += wtot;
+    }
+    if (tid == 0) s_total = base;
+    __syncthreads();
+    if (g * 64 >= s_total) return;  // whole block: no image here
+    const int sys = s_sys[lane];
+    const bool act = sys >= 0;
+    size_t slot = 0;
+    double x = 0.0, y = 0.0, f = 1.0, bx = 0.0, by = 0.0;
+    if (act) {
+        slot = ((size_t)s * a.nsys + sys) * a.kmax + s_k[lane];
+        x = a.ix[slot];
+        y = a.iy[slot];
+        f = a.f[sys];
+        bx = a.sx[(size_t)s * a.nsys + sys];
+        by = a.sy[(size_t)s * a.nsys + sys];
+    }
+    const double x0 = x, y0 = y, tol2 = a.tol * a.tol;
+    int state = act ? 0 : 1;  // 0 iterating, 1 converged (or no image), -1 failed
+    const int nfix = a.fixedt.n, nf = a.freet.n;
+    const int k0 = min(max(a.free_off[m], 0), nf), k1 = min(max(a.free_off[m + 1], k0), nf);
+    for (int it = 0; it < a.max_iter; ++it) {
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int pass = 0; pass < 2; ++pass) {
+            const Derived T = pass == 0 ? a.fixedt : a.freet;
+            const int lo_k = pass == 0 ? 0 : k0, hi_k = pass == 0 ? nfix : k1;
+            for (int kc = lo_k; kc < hi_k; kc += RF_CHUNK) {
+                const int cnt = min(RF_CHUNK, hi_k - kc);
+                __syncthreads();
+                for (int e = tid; e < cnt * NDER; e += RF_THREADS) {
+                    const int ci = e / cnt, kk = e - ci * cnt;
+                    pd[kk * NDER + ci] = T.d[(size_t)ci * T.stride + kc + kk];
+                }
+                __syncthreads();
+                for (int kk = wave; kk < cnt; kk += RF_WAVES)
+                    eval_pot_f64<true, true>(ConstD{pd + kk * NDER, 1}, x, y, acc, a.S);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) red[wave][c][lane] = acc[c];
+        __syncthreads();
+        double h[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            double v = red[0][c][lane];
+            for (int w = 1; w < RF_WAVES; ++w) v += red[w][c][lane];
+            h[c] = v;
+        }
+        if (state == 0) {
+            const double rx = bx - (x - f * h[0]);
+            const double ry = by - (y - f * h[1]);
+            const double a11 = 1.0 - f * h[2];
+            const double a12 = -(f * h[3]);
+            const double a22 = 1.0 - f * h[4];
+            const double det = a11 * a22 - a12 * a12;
+            const double sx = (a22 * rx - a12 * ry) / det;
+            const double sy = (a11 * ry - a12 * rx) / det;
+            x = x + sx;
+            y = y + sy;
+            if (!(fabs(x - x0) <= a.max_shift && fabs(y - y0) <= a.max_shift))
+                state = -1;
+            else if (sx * sx + sy * sy < tol2)
+                state = 1;
+        }
+        if (!__syncthreads_or(state == 0)) break;
+    }
+    if (wave == 0 && act && state == 1) {
+        a.ix[slot] = x;
+        a.iy[slot] = y;
+    }
+}
+
+hipError_t launch_refine_images(const RefineLaunch &L0, hipStream_t st) {
+    if (L0.nsamp <= 0 || L0.max_iter <= 0 || L0.nsys <= 0) return hipSuccess;
+    RefineLaunch L = L0;
+    L.S = make_series();
+    const long long groups = ((long long)L.nsys * L.kmax + 63) / 64;
+    if (groups > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(refine_images_kernel, dim3(L.nsamp, (unsigned)groups), dim3(RF_THREADS), 0,
+                       st, L);
+    return hipGetLastError();
+}
+
 }  // namespace lens

@@ -194,6 +194,21 @@ struct AlphaGridLaunch {
 };
 hipError_t launch_alpha_grid(const AlphaGridLaunch &L, hipStream_t st);
 
+// Newton refinement of the stored images of samples m0 .. m0+nsamp-1 (in place).
+struct RefineLaunch {
+    Derived fixedt, freet;
+    const int *free_off;
+    int m0, nsamp, nsys, kmax;
+    const int *count;          // [nsamp*nsys] image counts (may exceed kmax)
+    double *ix, *iy;           // [nsamp*nsys*kmax] positions, refined in place
+    const double *sx, *sy;     // [nsamp*nsys] the chunk's sources
+    const double *f;           // [nsys] Dls/Ds
+    int max_iter;
+    double tol, max_shift;
+    Series S;                  // filled by the launch wrapper
+};
+hipError_t launch_refine_images(const RefineLaunch &L, hipStream_t st);
+
 struct AssignLaunch {
     int nsamp, nsys, kmax;     // samples m0 .. m0+nsamp-1 of this chunk
     const int *count;          // [nsamp*nsys]
