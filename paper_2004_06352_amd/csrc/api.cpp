@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "lens_internal.h"
+#include "chi2_launch.h"
 
 using namespace lens;
 

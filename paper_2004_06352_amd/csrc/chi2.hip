@@ -19,6 +19,7 @@
 
 #include <algorithm>
 
+#include "chi2_launch.h"
 #include "eval.h"
 
 namespace lens {

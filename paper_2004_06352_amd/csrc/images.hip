@@ -19,7 +19,7 @@
 // with one atomic each; a second pass orders each slot list by triangle id.
 #include <math.h>
 
-#include "lens_internal.h"
+#include "chi2_launch.h"
 
 namespace lens {
 
