@@ -204,6 +204,113 @@ void or_map(const or_pots_t *P, int nx, int ny, double gx0, double gy0,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Lensing potential (Sec. 2.1: alpha = grad psi; one of the lensing maps of  */
+/* Sec. 2.4) of one cored isothermal ellipsoid, in its own frame: the Keeton  */
+/* (2001) softened-isothermal-ellipsoid form under the same mapping as the    */
+/* deflection,                                                                */
+/*   P_w = x' a'x + y' a'y - b0 (1 - eps^2) w ln sqrt((psi_w + S_w)^2 + k^2 x'^2) */
+/* (circular: P_w = b0 [psi_w - w - w ln(psi_w + w)]), defined up to an       */
+/* additive constant, which is fixed by this form.  mag receives the sum of   */
+/* the magnitudes of its three terms.                                         */
+/* ------------------------------------------------------------------------- */
+static double cie_potential(double b0, double eps, double w, double xp, double yp,
+                            double *mag)
+{
+    double q = (1.0 - eps) / (1.0 + eps);
+    double q2 = q * q;
+    double S = (1.0 + eps) * w;
+    double pw = sqrt(q2 * (S * S + xp * xp) + yp * yp);  /* psi_w */
+    double tx, ty, tl;
+    if (eps > 0.0) {
+        double k = 2.0 * sqrt(eps) / (1.0 + eps);
+        double pref = b0 * (1.0 - eps * eps) / (2.0 * sqrt(eps));
+        tx = xp * (pref * atan(k * xp / (pw + S)));
+        ty = yp * (pref * atanh(k * yp / (pw + q2 * S)));
+        tl = w > 0.0 ? b0 * (1.0 - eps * eps) * w * 0.5 *
+                           log((pw + S) * (pw + S) + k * k * xp * xp)
+                     : 0.0;
+    } else {
+        tx = xp * (b0 * xp / (pw + w));
+        ty = yp * (b0 * yp / (pw + w));
+        tl = w > 0.0 ? b0 * w * log(pw + w) : 0.0;
+    }
+    if (mag) *mag = fabs(tx) + fabs(ty) + fabs(tl);
+    return tx + ty - tl;
+}
+
+/* dPIE potential p at (x, y), Dls/Ds = 1: F (P_a - P_s) (rcut = inf: F = 1,
+ * no P_s); zero at the centre of a potential with rcore = 0 (its limit).
+ * mag (may be NULL) receives F (mag_a + mag_s). */
+double or_potential(const double p[7], double x, double y, double *mag)
+{
+    double x0 = p[0], y0 = p[1], b0 = p[2], eps = p[3], phi = p[4];
+    double a = p[5], s = p[6];
+    double dx = x - x0, dy = y - y0;
+    if (a == 0.0 && dx == 0.0 && dy == 0.0) {
+        if (mag) *mag = 0.0;
+        return 0.0;
+    }
+    double c = cos(phi), sn = sin(phi);
+    double xp = dx * c + dy * sn;
+    double yp = -dx * sn + dy * c;
+    double ma = 0.0, ms = 0.0, Ps = 0.0, F = 1.0;
+    double Pa = cie_potential(b0, eps, a, xp, yp, &ma);
+    if (isfinite(s)) {
+        Ps = cie_potential(b0, eps, s, xp, yp, &ms);
+        F = s / (s - a);
+    }
+    if (mag) *mag = F * (ma + ms);
+    return F * (Pa - Ps);
+}
+
+/* Potential map (Dls/Ds scaling as for the deflection) and, with scale != 0,
+ * the time-delay surface t = scale (|theta - beta|^2 / 2 - psi) of a source
+ * at beta (Fermat potential; its stationary points are the images).
+ * out, mag: ny*nx row-major (mag may be NULL; for t it bounds scale*psi). */
+void or_potential_map(const or_pots_t *P, int nx, int ny, double gx0, double gy0,
+                      double dx, double dy, double dlsds, double bx, double by,
+                      double scale, double *out, double *mag)
+{
+    int j;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < ny; j++) {
+        int i, k;
+        for (i = 0; i < nx; i++) {
+            double x = grid_coord(gx0, i, dx), y = grid_coord(gy0, j, dy);
+            double acc = 0.0, macc = 0.0, m;
+            for (k = 0; k < P->n; k++) {
+                double p[7] = {P->x0[k], P->y0[k], P->b0[k], P->eps[k], P->phi[k],
+                               P->rcore[k], P->rcut[k]};
+                acc += or_potential(p, x, y, &m);
+                macc += m;
+            }
+            size_t at = (size_t)j * nx + i;
+            if (scale != 0.0) {
+                double ex = x - bx, ey = y - by;
+                out[at] = scale * (0.5 * (ex * ex + ey * ey) - dlsds * acc);
+                if (mag) mag[at] = fabs(scale) * (0.5 * (ex * ex + ey * ey) + dlsds * macc);
+            } else {
+                out[at] = dlsds * acc;
+                if (mag) mag[at] = dlsds * macc;
+            }
+        }
+    }
+}
+
+/* Time-delay scale (1 + zl) Dl Ds / (c Dls) in days per arcsec^2 for a flat
+ * cosmology with H0 [km/s/Mpc]: the angular-diameter distances are
+ * (c/H0) chi/(1+z) (Dls = (c/H0)(chi_s - chi_l)/(1+zs)), so the scale is
+ * chi_l chi_s / ((chi_s - chi_l) H0) seconds per rad^2. */
+static double comoving(double z, double om, double ol);
+double or_time_delay_scale(double zl, double zs, double h0, double om, double ol)
+{
+    double cl = comoving(zl, om, ol), cs = comoving(zs, om, ol);
+    double h0_si = h0 * 1000.0 / 3.0856775814913673e22;
+    double rad = M_PI / 648000.0;
+    return cl * cs / ((cs - cl) * h0_si) * rad * rad / 86400.0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Derived maps from the summed second derivatives H (already scaled by      */
 /* Dls/Ds).  Sec. 2.4, Eqs. (7)-(9) with Sec. 2.1's magnification matrix     */
 /* A^-1 = [[1 - kappa - gamma1, -gamma2], [-gamma2, 1 - kappa + gamma1]]:    */

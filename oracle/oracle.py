@@ -160,6 +160,44 @@ def lens_map(pots, grid, dlsds=1.0, want_mag=True):
     return out, mag
 
 
+def potential_eval(p7, x, y):
+    """Lensing potential of one potential {x0, y0, b0, eps, phi, rcore, rcut}
+    at (x, y), Dls/Ds = 1 -> (value, magnitude scale)."""
+    L = lib()
+    L.or_potential.argtypes = [C.POINTER(C.c_double), C.c_double, C.c_double,
+                               C.POINTER(C.c_double)]
+    L.or_potential.restype = C.c_double
+    p = _d(np.asarray(p7, dtype=np.float64))
+    m = C.c_double()
+    v = L.or_potential(_ptr(p), float(x), float(y), C.byref(m))
+    return v, m.value
+
+
+def potential_map(pots, grid, dlsds=1.0, beta=(0.0, 0.0), scale=0.0):
+    """Potential map (scale == 0) or time-delay surface scale (|theta-beta|^2/2
+    - psi) of shape (ny, nx), plus its magnitude scale."""
+    nx, ny, gx0, gy0, dx, dy = grid
+    keep = _Keep()
+    P = _pots(pots, keep)
+    out = np.zeros((ny, nx))
+    mag = np.zeros((ny, nx))
+    L = lib()
+    L.or_potential_map.argtypes = [C.POINTER(_Pots), C.c_int, C.c_int] + [C.c_double] * 8 + \
+        [C.POINTER(C.c_double)] * 2
+    L.or_potential_map.restype = None
+    L.or_potential_map(C.byref(P), nx, ny, gx0, gy0, dx, dy, float(dlsds), float(beta[0]),
+                       float(beta[1]), float(scale), _ptr(out), _ptr(mag))
+    return out, mag
+
+
+def time_delay_scale(zl, zs, h0=70.0, om=0.3, ol=0.7):
+    """(1 + zl) Dl Ds / (c Dls) in days per arcsec^2 (flat cosmology)."""
+    L = lib()
+    L.or_time_delay_scale.argtypes = [C.c_double] * 5
+    L.or_time_delay_scale.restype = C.c_double
+    return L.or_time_delay_scale(float(zl), float(zs), float(h0), float(om), float(ol))
+
+
 def derived(hxx, hxy, hyy):
     """kappa, gamma1, gamma2, gamma, det (of the inverse magnification matrix)
     and mu from a summed second-derivative map (see lens_oracle.c)."""

@@ -21,7 +21,7 @@ MUTANTS = [
      "double psi = sqrt(q * (S * S + xp * xp) + yp * yp);"),
     ("Hessian xx/yy transposed", "out[2] = h * (q2 * S * S + yp * yp + S * psi) / D;  /* xx */",
      "out[2] = h * (S * S + xp * xp + S * psi) / D;  /* xx */"),
-    ("F missing", "F = s / (s - a);", "F = 1.0;"),
+    ("F missing", "F = s / (s - a);\n    }\n    double d[5]", "F = 1.0;\n    }\n    double d[5]"),
     ("distance ratio", "*out = 1.0 - comoving(zl, om, ol) / comoving(zs, om, ol);",
      "*out = comoving(zl, om, ol) / comoving(zs, om, ol);"),
     ("exact orientation term sign", "acc_product(L, by, ax, +1);", "acc_product(L, by, ax, -1);"),
@@ -39,6 +39,13 @@ MUTANTS = [
     ("Newton update sign", "        cx = cx + sx;", "        cx = cx - sx;"),
     ("lens equation residual sign", "rx = bx - (cx - f * acc[0]);", "rx = bx - (cx + f * acc[0]);"),
     ("refinement skipped", "if (refine_max_iter > 0)", "if (refine_max_iter > 1000)"),
+    ("potential log term without the core radius", "tl = w > 0.0 ? b0 * (1.0 - eps * eps) * w * 0.5 *",
+     "tl = w > 0.0 ? b0 * (1.0 - eps * eps) * 0.5 *"),
+    ("potential log term sign", "    return tx + ty - tl;", "    return tx + ty + tl;"),
+    ("time delay geometric term", "out[at] = scale * (0.5 * (ex * ex + ey * ey) - dlsds * acc);",
+     "out[at] = scale * ((ex * ex + ey * ey) - dlsds * acc);"),
+    ("time-delay scale distances", "return cl * cs / ((cs - cl) * h0_si) * rad * rad / 86400.0;",
+     "return cl * cs / (cs * h0_si) * rad * rad / 86400.0;"),
     ("ellipticity conversion", "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 - e * e)); }",
      "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 + e * e)); }"),
 ]
@@ -66,6 +73,11 @@ PINS = [
     (pins.test_refine_sis_images_are_exact, {}),
     (pins.test_refine_cored_lens_matches_radial_roots, {}),
     (pins.test_refined_image_chi2_vanishes_for_noise_free_constraints, {}),
+    (pins.test_potential_sis_is_b0_r, {}),
+    (pins.test_potential_circular_dpie_closed_form, {"a": 0.5, "s": 30.0}),
+    (pins.test_potential_gradient_is_deflection, {}),
+    (pins.test_time_delay_sis_images, {}),
+    (pins.test_time_delay_scale_einstein_de_sitter, {}),
 ]
 
 

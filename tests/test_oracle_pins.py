@@ -702,3 +702,99 @@ def test_refined_image_chi2_vanishes_for_noise_free_constraints(oracle):
     assert plain["nmiss"][0] == ref["nmiss"][0] == 0 and ref["nfail"][0] == 0
     assert ref["chi2"][0] < 1e-10
     assert plain["chi2"][0] > 1e-4
+
+
+# --------------------------------------------------------------------------
+# Lensing potential and time-delay surface
+# --------------------------------------------------------------------------
+def test_potential_sis_is_b0_r(oracle):
+    for _ in range(40):
+        b0 = RNG.uniform(1, 40)
+        x0, y0 = RNG.uniform(-5, 5, 2)
+        r = 10 ** RNG.uniform(-3, 3)
+        t = RNG.uniform(0, 2 * math.pi)
+        v, m = oracle.potential_eval(pot(x0, y0, b0), x0 + r * math.cos(t), y0 + r * math.sin(t))
+        assert v == pytest.approx(b0 * r, rel=1e-13)
+
+
+@pytest.mark.parametrize("a,s", [(0.5, 30.0), (3.0, 800.0)])
+def test_potential_circular_dpie_closed_form(oracle, a, s):
+    """psi(r) = F b0 [g(a) - g(s)], g(w) = sqrt(w^2+r^2) - w - w ln(w + sqrt(w^2+r^2)):
+    the radial integral of the enclosed-mass deflection."""
+    b0 = 11.0
+    F = s / (s - a)
+    for r in [1e-3, 0.4, 2.0, 17.0, 150.0, 3000.0]:
+        t = RNG.uniform(0, 2 * math.pi)
+        v, m = oracle.potential_eval(pot(0, 0, b0, 0.0, RNG.uniform(0, 3), a, s),
+                                     r * math.cos(t), r * math.sin(t))
+        with mp.workdps(50):
+            R = mp.mpf(r)
+            g = lambda w: mp.sqrt(w * w + R * R) - w - w * mp.log(w + mp.sqrt(w * w + R * R))
+            ref = float(b0 * F * (g(mp.mpf(a)) - g(mp.mpf(s))))
+        assert v == pytest.approx(ref, rel=1e-12, abs=1e-14 * m)
+
+
+def test_potential_gradient_is_deflection(oracle):
+    """Central differences of psi reproduce alpha (elliptical dPIEs)."""
+    for _ in range(40):
+        p = rand_pot()
+        x, y = RNG.uniform(-40, 40, 2)
+        h = 1e-5
+        px = (oracle.potential_eval(p, x + h, y)[0] - oracle.potential_eval(p, x - h, y)[0]) / (2 * h)
+        py = (oracle.potential_eval(p, x, y + h)[0] - oracle.potential_eval(p, x, y - h)[0]) / (2 * h)
+        v, m = oracle.pot_eval(p, x, y)
+        _, mp_ = oracle.potential_eval(p, x, y)
+        tol = 1e-9 * max(m[0], m[1]) + 1e-10 * mp_ / h
+        assert abs(px - v[0]) < tol and abs(py - v[1]) < tol
+
+
+def test_potential_laplacian_is_twice_convergence(oracle):
+    """Second differences of psi: Laplacian = Hxx + Hyy = 2 kappa."""
+    for _ in range(30):
+        p = rand_pot()
+        x, y = RNG.uniform(-30, 30, 2)
+        h = 2e-3
+        c = oracle.potential_eval(p, x, y)[0]
+        lap = (oracle.potential_eval(p, x + h, y)[0] + oracle.potential_eval(p, x - h, y)[0]
+               + oracle.potential_eval(p, x, y + h)[0] + oracle.potential_eval(p, x, y - h)[0]
+               - 4 * c) / (h * h)
+        v, m = oracle.pot_eval(p, x, y)
+        scale = m[2] + m[4] + 1e-13 * abs(c) / (h * h) * 1e3
+        assert abs(lap - (v[2] + v[4])) < 1e-4 * scale
+
+
+def test_time_delay_sis_images(oracle):
+    """SIS scaled by f: the two images differ in arrival time by
+    scale * 2 f b0 |beta|, and the time-delay surface is stationary at both."""
+    b0, f, scale = 8.0, 0.7, 3.5
+    lens = dict(x0=[0.0], y0=[0.0], b0=[b0], eps=[0.0], phi=[0.0], rcore=[0.0], rcut=[math.inf])
+    for _ in range(10):
+        r = RNG.uniform(0.1, 0.9) * f * b0
+        t = RNG.uniform(0, 2 * math.pi)
+        beta = (r * math.cos(t), r * math.sin(t))
+        times = []
+        for rad in (r + f * b0, r - f * b0):
+            x, y = rad * math.cos(t), rad * math.sin(t)
+            h = 1e-4
+            pts = [(x, y), (x + h, y), (x - h, y), (x, y + h), (x, y - h)]
+            xs = np.array([q[0] for q in pts])
+            vals = []
+            for q in pts:
+                g = (1, 1, q[0], q[1], 1.0, 1.0)
+                out, _ = oracle.potential_map(lens, g, f, beta, scale)
+                vals.append(out[0, 0])
+            times.append(vals[0])
+            gx, gy = (vals[1] - vals[2]) / (2 * h), (vals[3] - vals[4]) / (2 * h)
+            assert abs(gx) < 1e-6 * scale * b0 and abs(gy) < 1e-6 * scale * b0
+        assert times[1] - times[0] == pytest.approx(scale * 2 * f * b0 * r, rel=1e-10)
+
+
+def test_time_delay_scale_einstein_de_sitter(oracle):
+    """Omega_m = 1: chi(z) = 2 (1 - 1/sqrt(1+z)) c/H0, so the scale is
+    chi_l chi_s / ((chi_s - chi_l) H0) per rad^2."""
+    h0 = 70.0
+    for zl, zs in [(0.2, 1.0), (0.4, 2.0), (0.5, 5.0)]:
+        cl, cs = (2 * (1 - 1 / math.sqrt(1 + z)) for z in (zl, zs))
+        h0_si = h0 * 1000.0 / 3.0856775814913673e22
+        want = cl * cs / ((cs - cl) * h0_si) * (math.pi / 648000.0) ** 2 / 86400.0
+        assert oracle.time_delay_scale(zl, zs, h0, 1.0, 0.0) == pytest.approx(want, rel=1e-10)
