@@ -256,6 +256,12 @@ def main():
     secondary["derived_map_fp64_evals_per_s"] = evals * nd / wd
     secondary["derived_map_fp64_avg_launch_ms"] = ed * 1e3
     del od
+    # lensing potential (FP64), one plane
+    op = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
+    wp, ep = timed_steps(lambda: B.potential_map(table, grid, f, ctx=ctx, out=op), nd, 1, torch)
+    secondary["potential_map_fp64_evals_per_s"] = evals * nd / wp
+    secondary["potential_map_fp64_avg_launch_ms"] = ep * 1e3
+    del op
     if not args.no_chi2 and not args.only_map:
         c3 = inputs.config3()
         cat = B.catalog_to_device(B.catalog_with_dlsds(c3["catalog"], c3["zl"]))

@@ -229,6 +229,27 @@ lens_status_t lens_hessian_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
                                void *hxx, void *hxy, void *hyy, void *ax, void *ay,
                                void *stream);
 
+/* Lensing potential psi = dlsds * sum_k psi_k (alpha = grad psi, Sec. 2.1;
+ * one of the lensing maps of Sec. 2.4), FP64 only (psi must be nx*ny
+ * doubles; other precisions return LENS_EUNSUPPORTED).  Each cored isothermal
+ * ellipsoid contributes Keeton's (2001) softened-isothermal-ellipsoid
+ * potential under the mapping of the deflection,
+ *   P_w = x' a'x + y' a'y - b0 (1 - eps^2) w ln sqrt((psi_w + S_w)^2 + k^2 x'^2)
+ * (circular: b0 [psi_w - w - w ln(psi_w + w)]), a dPIE F (P_a - P_s): the
+ * potential is defined up to an additive constant, fixed by this form. */
+lens_status_t lens_potential_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                                 const lens_grid_t *grid, double dlsds, lens_precision_t prec,
+                                 double *psi, void *stream);
+
+/* Time-delay (Fermat) surface of a source at (beta_x, beta_y) [arcsec]:
+ *   t = scale (|theta - beta|^2 / 2 - dlsds * sum_k psi_k)
+ * at every grid point (nx*ny doubles); its stationary points are the images
+ * and differences of t between images are their arrival-time differences.
+ * scale converts arcsec^2 to time, e.g. lens_time_delay_scale's days. */
+lens_status_t lens_time_delay_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                                  const lens_grid_t *grid, double dlsds, double beta_x,
+                                  double beta_y, double scale, double *t, void *stream);
+
 /* Derived maps (Sec. 2.4, Eqs. (7)-(9), with the inverse magnification matrix
  * of Sec. 2.1, A^-1 = [[1 - kappa - gamma1, -gamma2], [-gamma2, 1 - kappa +
  * gamma1]]), from H = dlsds * sum_k d^2 psi_k at every grid point:
@@ -319,6 +340,12 @@ lens_status_t lens_chi2_plan_destroy(lens_chi2_plan_t *plan);
 /* Dls/Ds for a flat cosmology (om + ol = 1; the paper's Eq. (3) distances):
  * 1 - chi(zl)/chi(zs), chi the comoving distance.  0 <= zl < zs. */
 lens_status_t lens_dlsds(double zl, double zs, double om, double ol, double *out);
+/* Time-delay scale (1 + zl) Dl Ds / (c Dls) in days per arcsec^2 for a flat
+ * cosmology (om + ol = 1) with H0 in km/s/Mpc: with angular-diameter
+ * distances (c/H0) chi/(1+z) it is chi_l chi_s / ((chi_s - chi_l) H0).
+ * 0 < zl < zs. */
+lens_status_t lens_time_delay_scale(double zl, double zs, double h0, double om, double ol,
+                                    double *out);
 lens_status_t lens_b0_from_sigma(double sigma_kms, int32_t convention, double *out);
 lens_status_t lens_eps_from_e(double e, double *out);
 

@@ -36,7 +36,8 @@ PHYS_KEYS = ("x0", "y0", "sigma", "e", "phi", "rcore", "rcut")
 EXPORTS = ("lens_ctx_create", "lens_ctx_destroy", "lens_ctx_status", "lens_set_map_tuning",
            "lens_get_map_tuning", "lens_set_chi2_tuning", "lens_get_chi2_tuning",
            "lens_table_from_physical", "lens_grad_map",
-           "lens_hessian_map", "lens_derived_map", "lens_chi2_batch", "lens_find_images",
+           "lens_hessian_map", "lens_derived_map", "lens_potential_map", "lens_time_delay_map",
+           "lens_time_delay_scale", "lens_chi2_batch", "lens_find_images",
            "lens_chi2_plan_create", "lens_chi2_plan_create_ex",
            "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_dlsds",
            "lens_b0_from_sigma", "lens_eps_from_e", "lens_last_error", "lens_abi_version")
@@ -111,6 +112,10 @@ def lib():
                                        vp, vp, vp, vp]
         L.lens_derived_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp,
                                        vp, vp, vp, vp, vp]
+        L.lens_potential_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp]
+        L.lens_time_delay_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, dbl, dbl,
+                                          dbl, vp, vp]
+        L.lens_time_delay_scale.argtypes = [dbl, dbl, dbl, dbl, dbl, C.POINTER(dbl)]
         L.lens_chi2_batch.argtypes = [vp, C.POINTER(_Batch), C.POINTER(_Cat), C.POINTER(_Opts),
                                       vp, vp, vp, vp, vp]
         L.lens_find_images.argtypes = [vp, vp, vp, C.POINTER(_Grid), i32, vp, vp, vp, i32, vp,
@@ -293,6 +298,41 @@ def derived_map(table, grid, dlsds=1.0, prec=FP64, names=DERIVED, ctx=None, out=
     _check(lib().lens_derived_map(ctx.handle, C.byref(T), C.byref(G), float(dlsds), prec,
                                   *[_ptr(out.get(k)) for k in DERIVED], _stream(dev)))
     return out
+
+
+def potential_map(table, grid, dlsds=1.0, ctx=None, out=None):
+    """(ny, nx) FP64 lensing potential."""
+    ctx = _ctx(ctx)
+    nx, ny = int(grid[0]), int(grid[1])
+    dev = table["x0"].device
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float64, device=dev)
+    T, G = _pot(table), _grid(grid)
+    _check(lib().lens_potential_map(ctx.handle, C.byref(T), C.byref(G), float(dlsds), FP64,
+                                    _ptr(out), _stream(dev)))
+    return out
+
+
+def time_delay_map(table, grid, dlsds, beta, scale, ctx=None, out=None):
+    """(ny, nx) FP64 time-delay surface scale (|theta - beta|^2 / 2 - psi)."""
+    ctx = _ctx(ctx)
+    nx, ny = int(grid[0]), int(grid[1])
+    dev = table["x0"].device
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float64, device=dev)
+    T, G = _pot(table), _grid(grid)
+    _check(lib().lens_time_delay_map(ctx.handle, C.byref(T), C.byref(G), float(dlsds),
+                                     float(beta[0]), float(beta[1]), float(scale), _ptr(out),
+                                     _stream(dev)))
+    return out
+
+
+def time_delay_scale(zl, zs, h0=70.0, om=0.3, ol=0.7):
+    """Days per arcsec^2 of the time-delay surface (host helper)."""
+    v = C.c_double()
+    _check(lib().lens_time_delay_scale(float(zl), float(zs), float(h0), float(om), float(ol),
+                                       C.byref(v)))
+    return v.value
 
 
 def _batch(fixed, free, free_off):

@@ -33,6 +33,7 @@ SOURCES = {
     "maps.hip": ["-ffp-contract=off"],
     "chi2.hip": ["-ffp-contract=off"],
     "images.hip": ["-ffp-contract=off"],
+    "potential.hip": ["-ffp-contract=off"],
 }
 
 

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "chi2_launch.h"
+#include "potential_launch.h"
 
 using namespace lens;
 
@@ -555,6 +556,45 @@ lens_status_t lens_hessian_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
                       (hipStream_t)stream);
 }
 
+// Potential (td = 0) or time-delay (td = 1) map: validation, prologue, kernel.
+lens_status_t psi_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const lens_grid_t *grid,
+                         double dlsds, int td, double bx, double by, double scale, double *out,
+                         hipStream_t st) {
+    if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
+    TRY(check_table(table, "table"));
+    TRY(check_grid(grid));
+    if (!is_fin(dlsds) || dlsds < 0) return fail(LENS_EINVAL, "dlsds = %g", dlsds);
+    if (td && (!is_fin(bx) || !is_fin(by) || !is_fin(scale)))
+        return fail(LENS_EINVAL, "beta and scale must be finite");
+    TRY(check_range(out, (size_t)grid->nx * grid->ny * sizeof(double), td ? "t" : "psi"));
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
+    Carve cv;
+    const size_t o_tab = cv.take(derived_bytes(table->n));
+    TRY(ensure_scratch(ctx, cv.off));
+    const Derived D = derived_at(ctx, o_tab, table->n);
+    TRY(status_reset(ctx, st));
+    TRY(run_prologue(ctx, table, D, st));
+    TRY(status_check(ctx, st));
+    const GridArgs G{grid->nx, grid->ny, grid->x0, grid->y0, grid->dx, grid->dy};
+    HIP_TRY(launch_potential_map(D, G, dlsds, out, td, bx, by, scale, st));
+    return LENS_OK;
+}
+
+lens_status_t lens_potential_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                                 const lens_grid_t *grid, double dlsds, lens_precision_t prec,
+                                 double *psi, void *stream) {
+    if (prec != LENS_FP64)
+        return fail(LENS_EUNSUPPORTED, "the potential map is computed in FP64 only");
+    return psi_common(ctx, table, grid, dlsds, 0, 0.0, 0.0, 0.0, psi, (hipStream_t)stream);
+}
+
+lens_status_t lens_time_delay_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                                  const lens_grid_t *grid, double dlsds, double beta_x,
+                                  double beta_y, double scale, double *t, void *stream) {
+    return psi_common(ctx, table, grid, dlsds, 1, beta_x, beta_y, scale, t, (hipStream_t)stream);
+}
+
 lens_status_t lens_derived_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
                                const lens_grid_t *grid, double dlsds, lens_precision_t prec,
                                void *kappa, void *gamma1, void *gamma2, void *gamma, void *mu,
@@ -899,6 +939,19 @@ lens_status_t lens_dlsds(double zl, double zs, double om, double ol, double *out
         fabs(om + ol - 1.0) > 1e-9)
         return fail(LENS_EINVAL, "need 0 <= zl < zs and a flat cosmology (om + ol = 1)");
     *out = 1.0 - comoving_gl(zl, om, ol) / comoving_gl(zs, om, ol);
+    return LENS_OK;
+}
+
+lens_status_t lens_time_delay_scale(double zl, double zs, double h0, double om, double ol,
+                                    double *out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    if (!(zl > 0.0) || !(zs > zl) || !is_fin(zs) || !(h0 > 0.0) || !is_fin(h0) ||
+        !(om >= 0.0) || !(ol >= 0.0) || fabs(om + ol - 1.0) > 1e-9)
+        return fail(LENS_EINVAL, "need 0 < zl < zs, H0 > 0 and a flat cosmology");
+    const double cl = comoving_gl(zl, om, ol), cs = comoving_gl(zs, om, ol);
+    const double h0_si = h0 * 1000.0 / 3.0856775814913673e22;  // km/s/Mpc -> 1/s
+    const double rad = M_PI / 648000.0;                          // arcsec -> rad
+    *out = cl * cs / ((cs - cl) * h0_si) * rad * rad / 86400.0;
     return LENS_OK;
 }
 

@@ -69,6 +69,19 @@ def test_host_distance_ratio_matches_oracle(lib, oracle):
     assert _call_d(fn, 0.4, float("nan"), 0.3, 0.7)[0] == -1
 
 
+def test_host_time_delay_scale_matches_oracle(lib, oracle):
+    fn = lib.lens_time_delay_scale
+    fn.argtypes = [C.c_double] * 5 + [C.POINTER(C.c_double)]
+    fn.restype = C.c_int32
+    for zl, zs in [(0.2, 1.0), (0.4, 2.0), (0.5, 6.0)]:
+        for h0, om, ol in [(70.0, 0.3, 0.7), (67.0, 1.0, 0.0)]:
+            v = C.c_double()
+            assert fn(zl, zs, h0, om, ol, C.byref(v)) == 0
+            assert v.value == pytest.approx(oracle.time_delay_scale(zl, zs, h0, om, ol), rel=1e-12)
+    v = C.c_double()
+    assert fn(0.0, 1.0, 70.0, 0.3, 0.7, C.byref(v)) == -1  # zl must be > 0
+
+
 def test_host_parameter_conversions_match_oracle(lib, oracle):
     fb = lib.lens_b0_from_sigma
     fb.argtypes = [C.c_double, C.c_int32, C.POINTER(C.c_double)]
