@@ -836,6 +836,82 @@ int or_chi2_image(const or_pots_t *fixed, const or_pots_t *freep,
     return over;
 }
 
+/* ------------------------------------------------------------------------- */
+/* One step of a Metropolis sampler over the free potentials' physical        */
+/* parameters (Sec. 2.2: the parameter space is explored by a Bayesian MCMC;  */
+/* Sec. 4 names the sampler the third bottleneck).  Walker w holds nfree      */
+/* potentials of 7 parameters (x0, y0, sigma, e, phi, rcore, rcut) in         */
+/* params[w][k][j]; u[w][0 .. 7 nfree] are uniforms in (0, 1] supplied by the */
+/* caller.  Proposal: theta'_i = theta_i + step_i (2 u_i - 1) (symmetric);    */
+/* a proposal outside the prior box [lo, hi] is rejected.  Otherwise it is    */
+/* accepted when chi2' <= chi2 or -2 ln u_last > chi2' - chi2, i.e. with      */
+/* probability min(1, exp(-(chi2' - chi2)/2)) for the likelihood exp(-chi2/2) */
+/* and uniform priors.  chi2' is the source-plane chi^2 (fixed potentials     */
+/* then the walker's, in index order; sigma -> b0 and e -> eps as the         */
+/* parameter conversions below).  Returns the number of accepted moves.       */
+/* ------------------------------------------------------------------------- */
+double or_b0_from_sigma(double sigma_kms, int convention);
+double or_eps_from_e(double e);
+
+int or_mcmc_step(const or_pots_t *fixed, const or_cat_t *C, int W, int nfree,
+                 double *params, double *chi2, int *accepted, const double *lo,
+                 const double *hi, const double *step, const double *u, int convention)
+{
+    int P = 7 * nfree, w, i, k, acc = 0;
+    double *prop = malloc(sizeof(double) * ((size_t)W * P + 1));
+    double *amp = malloc(sizeof(double) * ((size_t)7 * W * nfree + 1));
+    double *chi2p = malloc(sizeof(double) * (W + 1));
+    int *inside = malloc(sizeof(int) * (W + 1));
+    int *off = malloc(sizeof(int) * (W + 1));
+    size_t n = (size_t)W * nfree;
+    for (w = 0; w < W; w++) {
+        const double *th = params + (size_t)w * P;
+        const double *uw = u + (size_t)w * (P + 1);
+        double *pr = prop + (size_t)w * P;
+        int in = 1;
+        for (i = 0; i < P; i++) {
+            pr[i] = th[i] + step[i] * (2.0 * uw[i] - 1.0);
+            if (!(pr[i] >= lo[i] && pr[i] <= hi[i])) in = 0;
+        }
+        inside[w] = in;
+        off[w] = w * nfree;
+        /* an out-of-prior proposal is never evaluated: its slot holds the
+           current (valid) parameters */
+        const double *src = in ? pr : th;
+        for (k = 0; k < nfree; k++) {
+            size_t at = (size_t)w * nfree + k;
+            const double *q = src + 7 * k;
+            amp[0 * n + at] = q[0];
+            amp[1 * n + at] = q[1];
+            amp[2 * n + at] = or_b0_from_sigma(q[2], convention);
+            amp[3 * n + at] = or_eps_from_e(q[3]);
+            amp[4 * n + at] = q[4];
+            amp[5 * n + at] = q[5];
+            amp[6 * n + at] = q[6];
+        }
+    }
+    off[W] = W * nfree;
+    or_pots_t freep = {(int)n, amp, amp + n, amp + 2 * n, amp + 3 * n, amp + 4 * n,
+                       amp + 5 * n, amp + 6 * n};
+    or_chi2_source(fixed, &freep, off, W, C, chi2p);
+    for (w = 0; w < W; w++) {
+        double d = chi2p[w] - chi2[w];
+        double ul = u[(size_t)w * (P + 1) + P];
+        if (inside[w] && (d <= 0.0 || -2.0 * log(ul) > d)) {
+            memcpy(params + (size_t)w * P, prop + (size_t)w * P, sizeof(double) * P);
+            chi2[w] = chi2p[w];
+            accepted[w] += 1;
+            acc++;
+        }
+    }
+    free(prop);
+    free(amp);
+    free(chi2p);
+    free(inside);
+    free(off);
+    return acc;
+}
+
 /* Smallest distance from p to any triangle edge (segment) of the unlensed grid
  * for one system.  A containment decision can only differ between two
  * evaluations whose vertex and source positions differ by less than this. */

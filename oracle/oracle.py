@@ -198,6 +198,37 @@ def time_delay_scale(zl, zs, h0=70.0, om=0.3, ol=0.7):
     return L.or_time_delay_scale(float(zl), float(zs), float(h0), float(om), float(ol))
 
 
+def mcmc_step(fixed, cat, params, chi2, accepted, lo, hi, step, u, convention=0):
+    """One Metropolis step of every walker, in place (see lens_oracle.c).
+    params (W, nfree, 7) physical, chi2 (W,), accepted (W,) int32, lo/hi/step
+    (nfree, 7), u (W, 7 nfree + 1) in (0, 1].  Returns the accepted count."""
+    for a_ in (params, chi2, lo, hi, step, u):
+        assert a_.dtype == np.float64 and a_.flags.c_contiguous
+    assert accepted.dtype == np.int32 and accepted.flags.c_contiguous
+    W, nfree = params.shape[0], params.shape[1]
+    keep = _Keep()
+    Pf, Cc = _pots(fixed, keep), _cat(cat, keep)
+    L = lib()
+    L.or_mcmc_step.argtypes = [C.POINTER(_Pots), C.POINTER(_Cat), C.c_int, C.c_int,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double),
+                               C.POINTER(C.c_int)] + [C.POINTER(C.c_double)] * 4 + [C.c_int]
+    L.or_mcmc_step.restype = C.c_int
+    return L.or_mcmc_step(C.byref(Pf), C.byref(Cc), W, nfree, _ptr(params), _ptr(chi2),
+                          _ptr(accepted, C.c_int), _ptr(lo), _ptr(hi), _ptr(step), _ptr(u),
+                          int(convention))
+
+
+def chi2_of_physical(fixed, cat, params, convention=0):
+    """Source-plane chi^2 of walkers given as physical parameters (W, nfree, 7)."""
+    W, nfree = params.shape[0], params.shape[1]
+    flat = params.reshape(W * nfree, 7)
+    phys = {k: np.ascontiguousarray(flat[:, i]) for i, k in
+            enumerate(("x0", "y0", "sigma", "e", "phi", "rcore", "rcut"))}
+    free = phys_to_pots(phys, convention)
+    off = (np.arange(W + 1) * nfree).astype(np.int32)
+    return chi2_source(fixed, free, off, cat)
+
+
 def derived(hxx, hxy, hyy):
     """kappa, gamma1, gamma2, gamma, det (of the inverse magnification matrix)
     and mu from a summed second-derivative map (see lens_oracle.c)."""

@@ -46,6 +46,11 @@ MUTANTS = [
      "out[at] = scale * ((ex * ex + ey * ey) - dlsds * acc);"),
     ("time-delay scale distances", "return cl * cs / ((cs - cl) * h0_si) * rad * rad / 86400.0;",
      "return cl * cs / (cs * h0_si) * rad * rad / 86400.0;"),
+    ("Metropolis acceptance without the half", "d <= 0.0 || -2.0 * log(ul) > d",
+     "d <= 0.0 || -log(ul) > d"),
+    ("prior box ignored", "if (!(pr[i] >= lo[i] && pr[i] <= hi[i])) in = 0;", "(void)0;"),
+    ("asymmetric proposal", "pr[i] = th[i] + step[i] * (2.0 * uw[i] - 1.0);",
+     "pr[i] = th[i] + step[i] * (2.0 * uw[i] - 0.9);"),
     ("ellipticity conversion", "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 - e * e)); }",
      "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 + e * e)); }"),
 ]
@@ -78,6 +83,9 @@ PINS = [
     (pins.test_potential_gradient_is_deflection, {}),
     (pins.test_time_delay_sis_images, {}),
     (pins.test_time_delay_scale_einstein_de_sitter, {}),
+    (pins.test_mcmc_zero_step_and_prior_rules, {}),
+    (pins.test_mcmc_acceptance_threshold, {}),
+    (pins.test_mcmc_samples_the_posterior, {}),
 ]
 
 

@@ -798,3 +798,120 @@ def test_time_delay_scale_einstein_de_sitter(oracle):
         h0_si = h0 * 1000.0 / 3.0856775814913673e22
         want = cl * cs / ((cs - cl) * h0_si) * (math.pi / 648000.0) ** 2 / 86400.0
         assert oracle.time_delay_scale(zl, zs, h0, 1.0, 0.0) == pytest.approx(want, rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Metropolis sampler
+# --------------------------------------------------------------------------
+def _sis_sampler_problem():
+    """One SIS at the origin whose velocity dispersion is the only free
+    parameter (the other six have zero step and a point prior), one system of
+    three images: chi^2 is a smooth function of sigma with one minimum."""
+    cat = dict(off=np.array([0, 3], np.int32), x=np.array([10.0, -6.0, 2.0]),
+               y=np.array([1.0, 7.0, -9.0]), sig=np.array([0.5, 0.5, 0.5]), f=np.array([0.7]))
+    base = np.array([0.0, 0.0, 700.0, 0.0, 0.0, 0.0, math.inf])
+    return cat, base
+
+
+def test_mcmc_zero_step_and_prior_rules(oracle):
+    cat, base = _sis_sampler_problem()
+    W = 6
+    params = np.tile(base, (W, 1, 1)).astype(np.float64)
+    params[:, 0, 2] = np.linspace(650.0, 750.0, W)
+    chi2 = oracle.chi2_of_physical(empty_pots(), cat, params)
+    acc = np.zeros(W, np.int32)
+    lo = base.reshape(1, 7).copy()
+    hi = base.reshape(1, 7).copy()
+    lo[0, 2], hi[0, 2] = 600.0, 800.0
+    step = np.zeros((1, 7))
+    u = np.full((W, 8), 0.5)
+    # zero step: the proposal is the current state, always accepted, nothing moves
+    p0 = params.copy()
+    assert oracle.mcmc_step(empty_pots(), cat, params, chi2, acc, lo, hi, step, u) == W
+    assert np.array_equal(params, p0) and np.all(acc == 1)
+    # a proposal beyond the prior box is rejected even when it lowers chi^2:
+    # a box below the chi^2 minimum, walkers at its upper edge, moves upward
+    g = np.tile(base, (301, 1, 1))
+    g[:, 0, 2] = np.linspace(300.0, 1500.0, 301)
+    smin = g[int(np.argmin(oracle.chi2_of_physical(empty_pots(), cat, g))), 0, 2]
+    lo[0, 2], hi[0, 2] = smin - 300.0, smin - 100.0
+    params[:, 0, 2] = smin - 110.0
+    chi2 = oracle.chi2_of_physical(empty_pots(), cat, params)
+    p0 = params.copy()
+    step[0, 2] = 60.0
+    u[:, 2] = 1.0  # sigma + 60: outside the box, closer to the minimum
+    moved = params.copy()
+    moved[:, 0, 2] += 60.0
+    assert np.all(oracle.chi2_of_physical(empty_pots(), cat, moved) < chi2)
+    assert oracle.mcmc_step(empty_pots(), cat, params, chi2, acc, lo, hi, step, u) == 0
+    assert np.array_equal(params, p0)
+
+
+def test_mcmc_acceptance_threshold(oracle):
+    """A move that raises chi^2 by d is accepted exactly when -2 ln u > d."""
+    cat, base = _sis_sampler_problem()
+    lo, hi = base.reshape(1, 7).copy(), base.reshape(1, 7).copy()
+    lo[0, 2], hi[0, 2] = 100.0, 2000.0
+    sig_grid = np.linspace(300.0, 1500.0, 601)
+    g = np.tile(base, (len(sig_grid), 1, 1))
+    g[:, 0, 2] = sig_grid
+    c = oracle.chi2_of_physical(empty_pots(), cat, g)
+    i0 = int(np.argmin(c))
+    start = sig_grid[i0]
+    target = start + 40.0  # uphill move
+    params = np.tile(base, (2, 1, 1))
+    params[:, 0, 2] = start
+    chi2 = oracle.chi2_of_physical(empty_pots(), cat, params)
+    moved = params.copy()
+    moved[:, 0, 2] = target
+    d = float(oracle.chi2_of_physical(empty_pots(), cat, moved)[0] - chi2[0])
+    assert d > 0.1
+    step = np.zeros((1, 7))
+    step[0, 2] = 40.0
+    u = np.full((2, 8), 0.5)
+    u[:, 2] = 1.0  # proposal = start + 40 exactly
+    u[0, 7] = math.exp(-d / 2) * (1 - 1e-9)  # -2 ln u just above d: accept
+    u[1, 7] = math.exp(-d / 2) * (1 + 1e-9)  # just below: reject
+    acc = np.zeros(2, np.int32)
+    oracle.mcmc_step(empty_pots(), cat, params, chi2, acc, lo, hi, step, u)
+    assert list(acc) == [1, 0]
+    assert params[0, 0, 2] == target and params[1, 0, 2] == start
+
+
+def test_mcmc_samples_the_posterior(oracle):
+    """Stationary distribution: after burn-in the walkers' sigma follows
+    exp(-chi^2/2) on the prior box (chi^2 from the oracle on a fine grid,
+    integrated by the trapezoid rule): mean within 5 standard errors of the
+    4096 walkers, standard deviation within 12%."""
+    cat, base = _sis_sampler_problem()
+    sig_grid = np.linspace(300.0, 1500.0, 2401)
+    g = np.tile(base, (len(sig_grid), 1, 1))
+    g[:, 0, 2] = sig_grid
+    c = oracle.chi2_of_physical(empty_pots(), cat, g)
+    imin = int(np.argmin(c))
+    wgt = np.exp(-(c - c[imin]) / 2)
+    # prior box: +-6 posterior widths around the minimum
+    mean0 = np.trapezoid(wgt * sig_grid, sig_grid) / np.trapezoid(wgt, sig_grid)
+    sd0 = math.sqrt(np.trapezoid(wgt * (sig_grid - mean0) ** 2, sig_grid) / np.trapezoid(wgt, sig_grid))
+    lo_s, hi_s = mean0 - 6 * sd0, mean0 + 6 * sd0
+    inside = (sig_grid >= lo_s) & (sig_grid <= hi_s)
+    sg, wg = sig_grid[inside], wgt[inside]
+    mean = np.trapezoid(wg * sg, sg) / np.trapezoid(wg, sg)
+    sd = math.sqrt(np.trapezoid(wg * (sg - mean) ** 2, sg) / np.trapezoid(wg, sg))
+    W, steps = 4096, 250
+    rng = np.random.default_rng(11)
+    params = np.tile(base, (W, 1, 1))
+    params[:, 0, 2] = rng.uniform(lo_s, hi_s, W)
+    chi2 = oracle.chi2_of_physical(empty_pots(), cat, params)
+    acc = np.zeros(W, np.int32)
+    lo, hi = base.reshape(1, 7).copy(), base.reshape(1, 7).copy()
+    lo[0, 2], hi[0, 2] = lo_s, hi_s
+    step = np.zeros((1, 7))
+    step[0, 2] = 2.5 * sd
+    for _ in range(steps):
+        u = 1.0 - rng.random((W, 8))  # (0, 1]
+        oracle.mcmc_step(empty_pots(), cat, params, chi2, acc, lo, hi, step, u)
+    s = params[:, 0, 2]
+    assert abs(s.mean() - mean) < 5 * sd / math.sqrt(W)
+    assert abs(s.std() / sd - 1) < 0.12
+    assert 0.1 < acc.mean() / steps < 0.9
