@@ -284,6 +284,19 @@ def main():
             secondary[f"chi2_source_{name}_samples_per_s"] = S * 50 / w
             plan.close()
         secondary["chi2_source_workload"] = c3["name"]
+        # Metropolis sampler: 4096 walkers of the same model, one graph launch
+        # per step (proposal, batched chi^2, acceptance); uniforms supplied
+        # once and reused (filling them is the caller's generator's cost)
+        sm = inputs.sampler_start(n_walkers=4096)
+        Wn = sm["params"].shape[0]
+        dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+        um = dev(inputs.sampler_uniforms(np.random.default_rng(9), Wn, 6))
+        mc = B.Mcmc(fixed, cat, dev(sm["params"]), dev(sm["lo"]), dev(sm["hi"]),
+                    dev(sm["step"]), um, ctx=ctx)
+        w, e = timed_steps(mc.step, 100, 3, torch, per_step=False)
+        secondary["mcmc_walker_steps_per_s"] = Wn * 100 / w
+        secondary["mcmc_ms_per_step"] = w / 100 * 1e3
+        mc.close()
         # image-plane chi^2: 1000^2 grid, 512 samples of the same model
         c4 = inputs.config4()
         off4 = torch.as_tensor(c4["free_off"], dtype=torch.int32, device="cuda")

@@ -112,6 +112,7 @@ typedef int32_t lens_chi2_path_t;
 
 typedef struct lens_ctx lens_ctx_t;        /* opaque */
 typedef struct lens_chi2_plan lens_chi2_plan_t; /* opaque */
+typedef struct lens_mcmc lens_mcmc_t;           /* opaque */
 
 /* Potential table in amplitude form; n entries; device arrays. */
 typedef struct {
@@ -335,6 +336,43 @@ lens_status_t lens_chi2_plan_create_ex(lens_ctx_t *ctx, const lens_model_batch_t
                                        lens_chi2_plan_t **out);
 lens_status_t lens_chi2_plan_launch(lens_chi2_plan_t *plan, void *stream);
 lens_status_t lens_chi2_plan_destroy(lens_chi2_plan_t *plan);
+
+/* ---- sampler (the MCMC of Sec. 2.2; Sec. 4's third bottleneck) ----------- */
+/* Metropolis sampling of the free potentials' physical parameters with many
+ * independent walkers.  Walker w holds n_free potentials of 7 parameters
+ * (x0, y0, sigma, e, phi, rcore, rcut) in params[w][k][0..6].  A step, for
+ * every walker at once: propose theta'_i = theta_i + step_i (2 u_i - 1)
+ * (symmetric); reject a proposal outside the uniform prior box [lo, hi];
+ * otherwise evaluate its source-plane chi^2 (fixed potentials then the
+ * walker's, FP64) and accept it when chi2' <= chi2 or -2 ln u_last >
+ * chi2' - chi2 (probability min(1, exp(-(chi2' - chi2)/2)), likelihood
+ * exp(-chi2/2)).  The uniforms u[w][0 .. 7 n_free] in (0, 1] are written by
+ * the caller before each step (any generator; they are inputs so that a run
+ * can be reproduced elsewhere). */
+typedef struct {
+    int32_t n_walkers, n_free;  /* >= 1 each */
+    double *params;             /* device [n_walkers][n_free][7], updated in place */
+    double *chi2;               /* device [n_walkers]: written by create, updated by step */
+    int32_t *accepted;          /* device [n_walkers]: accepted moves, incremented */
+    const double *lo, *hi;      /* device [n_free][7]: uniform prior box */
+    const double *step;         /* device [n_free][7]: proposal half-widths, >= 0 */
+    const double *u;            /* device [n_walkers][7 n_free + 1] uniforms, per step */
+    int32_t convention;         /* sigma -> b0: 0 Lenstool dPIE (6 pi), 1 SIS (4 pi) */
+} lens_mcmc_desc_t;
+
+/* Create a sampler bound to these buffers.  The fixed potentials and the
+ * catalogue are read once here (their per-image constants are kept; they
+ * must not change while the sampler is used); chi2 receives the chi^2 of the
+ * initial parameters.  The prior box must lie in the valid domain (sigma >=
+ * 0, 0 <= e < 1, 0 <= rcore, rcore's upper bound below rcut's lower bound)
+ * and every walker inside it (LENS_EINVAL otherwise).  The sampler owns its
+ * scratch; destroy it before its context.  Synchronises `stream`. */
+lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
+                               const lens_catalog_t *cat, const lens_mcmc_desc_t *desc,
+                               void *stream, lens_mcmc_t **out);
+/* One step of every walker (one graph launch, asynchronous on stream). */
+lens_status_t lens_mcmc_step(lens_mcmc_t *sampler, void *stream);
+lens_status_t lens_mcmc_destroy(lens_mcmc_t *sampler);
 
 /* ---- host helpers (synchronous, no device) -------------------------------- */
 /* Dls/Ds for a flat cosmology (om + ol = 1; the paper's Eq. (3) distances):

@@ -39,7 +39,8 @@ EXPORTS = ("lens_ctx_create", "lens_ctx_destroy", "lens_ctx_status", "lens_set_m
            "lens_hessian_map", "lens_derived_map", "lens_potential_map", "lens_time_delay_map",
            "lens_time_delay_scale", "lens_chi2_batch", "lens_find_images",
            "lens_chi2_plan_create", "lens_chi2_plan_create_ex",
-           "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_dlsds",
+           "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_mcmc_create",
+           "lens_mcmc_step", "lens_mcmc_destroy", "lens_dlsds",
            "lens_b0_from_sigma", "lens_eps_from_e", "lens_last_error", "lens_abi_version")
 
 
@@ -71,6 +72,13 @@ class _Cat(C.Structure):
     _fields_ = [("n_sys", C.c_int32), ("n_img", C.c_int32), ("img_offset", C.c_void_p),
                 ("x", C.c_void_p), ("y", C.c_void_p), ("sigma", C.c_void_p),
                 ("dlsds", C.c_void_p)]
+
+
+class _McmcDesc(C.Structure):
+    _fields_ = [("n_walkers", C.c_int32), ("n_free", C.c_int32), ("params", C.c_void_p),
+                ("chi2", C.c_void_p), ("accepted", C.c_void_p), ("lo", C.c_void_p),
+                ("hi", C.c_void_p), ("step", C.c_void_p), ("u", C.c_void_p),
+                ("convention", C.c_int32)]
 
 
 class _Opts(C.Structure):
@@ -443,6 +451,50 @@ class Chi2Plan:
     def close(self):
         if getattr(self, "handle", None):
             lib().lens_chi2_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mcmc:
+    """Metropolis sampler over the free potentials' physical parameters.
+    params (W, nfree, 7) FP64, updated in place; lo/hi/step (nfree, 7); u
+    (W, 7 nfree + 1) uniforms in (0, 1], refilled by the caller before each
+    step().  chi2 (W,) and accepted (W,) int32 are owned here."""
+
+    def __init__(self, fixed, cat, params, lo, hi, step, u, convention=0, ctx=None):
+        self.ctx = _ctx(ctx)
+        dev = params.device
+        W, nf = int(params.shape[0]), int(params.shape[1])
+        for t in (params, lo, hi, step, u):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.device == dev
+        assert params.shape[2] == 7 and lo.shape == hi.shape == step.shape == (nf, 7)
+        assert u.shape == (W, 7 * nf + 1)
+        self.params, self.u = params, u
+        self.chi2 = torch.empty(W, dtype=torch.float64, device=dev)
+        self.accepted = torch.zeros(W, dtype=torch.int32, device=dev)
+        self._keep = (fixed, cat, lo, hi, step)
+        D = _McmcDesc(W, nf, params.data_ptr(), self.chi2.data_ptr(), self.accepted.data_ptr(),
+                      lo.data_ptr(), hi.data_ptr(), step.data_ptr(), u.data_ptr(),
+                      int(convention))
+        T, K = _pot(fixed), _catalog(cat)
+        h = C.c_void_p()
+        self.stream = torch.cuda.Stream(device=dev)
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        _check(lib().lens_mcmc_create(self.ctx.handle, C.byref(T), C.byref(K), C.byref(D),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def step(self):
+        _check(lib().lens_mcmc_step(self.handle, _stream(self.params.device)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lens_mcmc_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -15,6 +15,7 @@
 
 #include "chi2_launch.h"
 #include "potential_launch.h"
+#include "sampler_launch.h"
 
 using namespace lens;
 
@@ -55,6 +56,13 @@ struct lens_ctx {
     int num_cu = 256;
     lens_map_tuning_t tune[3];
     int chi2_blocks_per_cu = 16;  // persistent chi^2 waves (one-wave blocks) per CU
+};
+
+struct lens_mcmc {
+    lens_ctx_t *ctx = nullptr;
+    void *mem = nullptr;  // derived tables, per-image constants, proposals, amplitudes
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 struct lens_chi2_plan {
@@ -891,6 +899,169 @@ lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *b
                                     const lens_catalog_t *c, const lens_chi2_opts_t *o,
                                     double *chi2, void *stream, lens_chi2_plan_t **out) {
     return lens_chi2_plan_create_ex(ctx, b, c, o, chi2, 0u, stream, out);
+}
+
+// ---------------------------------------------------------------------------
+// Metropolis sampler: proposal kernel, batched chi^2 of the proposals (fixed
+// part resident), acceptance kernel; one step is one graph launch.
+lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
+                               const lens_catalog_t *c, const lens_mcmc_desc_t *d, void *stream,
+                               lens_mcmc_t **out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx || !d) return fail(LENS_EINVAL, "ctx or desc is NULL");
+    TRY(check_table(fixed, "fixed"));
+    TRY(check_catalog(c));
+    const int W = d->n_walkers, nf = d->n_free;
+    if (W < 1 || nf < 1 || (long long)W * nf > (1LL << 28))
+        return fail(LENS_EINVAL, "n_walkers = %d, n_free = %d", W, nf);
+    if (d->convention != 0 && d->convention != 1)
+        return fail(LENS_EINVAL, "convention = %d", d->convention);
+    const int P = 7 * nf;
+    TRY(check_range(d->params, (size_t)W * P * sizeof(double), "params"));
+    TRY(check_range(d->chi2, (size_t)W * sizeof(double), "chi2"));
+    TRY(check_range(d->accepted, (size_t)W * sizeof(int32_t), "accepted"));
+    TRY(check_range(d->lo, (size_t)P * sizeof(double), "lo"));
+    TRY(check_range(d->hi, (size_t)P * sizeof(double), "hi"));
+    TRY(check_range(d->step, (size_t)P * sizeof(double), "step"));
+    TRY(check_range(d->u, (size_t)W * (P + 1) * sizeof(double), "u"));
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    // the prior box must lie inside the valid parameter domain, and the
+    // walkers inside the box (read back once)
+    std::vector<double> lo(P), hi(P), step(P), th((size_t)W * P);
+    HIP_TRY(hipMemcpyAsync(lo.data(), d->lo, P * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hi.data(), d->hi, P * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(step.data(), d->step, P * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(th.data(), d->params, th.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int k = 0; k < nf; ++k) {
+        const double *l = &lo[7 * k], *h = &hi[7 * k];
+        for (int j = 0; j < 7; ++j)
+            if (!(l[j] <= h[j]) || !is_fin(l[j]) || (j != 6 && !is_fin(h[j])) ||
+                !(step[7 * k + j] >= 0.0) || !is_fin(step[7 * k + j]))
+                return fail(LENS_EINVAL, "prior box or step of potential %d, parameter %d", k, j);
+        if (!(l[2] >= 0.0) || !(l[3] >= 0.0) || !(h[3] < 1.0) || !(l[5] >= 0.0) || !(h[5] < l[6]))
+            return fail(LENS_EINVAL,
+                        "prior box of potential %d leaves the valid domain (sigma >= 0, "
+                        "0 <= e < 1, 0 <= rcore < rcut)", k);
+    }
+    for (int w = 0; w < W; ++w)
+        for (int i = 0; i < P; ++i) {
+            const double v = th[(size_t)w * P + i];
+            if (!(v >= lo[i] && v <= hi[i]))
+                return fail(LENS_EINVAL, "walker %d parameter %d = %g outside the prior box", w,
+                            i, v);
+        }
+    // own memory: derived tables, per-image constants, amplitudes, proposals
+    const size_t n = (size_t)W * nf;
+    Carve cv;
+    SrcPlan sp;
+    sp.nimg_pad = (c->n_img + 63) / 64 * 64;
+    sp.o_fix = cv.take(derived_bytes(fixed->n));
+    sp.o_free = cv.take(derived_bytes((int)n));
+    sp.o_rec = cv.take((size_t)3 * sp.nimg_pad * sizeof(double));
+    sp.o_src = 0;
+    const size_t o_amp = cv.take(7 * n * sizeof(double));
+    const size_t o_prop = cv.take((size_t)W * P * sizeof(double));
+    const size_t o_in = cv.take((size_t)W * sizeof(int));
+    const size_t o_chi2p = cv.take((size_t)W * sizeof(double));
+    const size_t o_off = cv.take(((size_t)W + 1) * sizeof(int));
+    lens_mcmc_t *m = new lens_mcmc_t();
+    m->ctx = ctx;
+    hipError_t e = hipMalloc(&m->mem, cv.off);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete m;
+        return fail(LENS_ENOMEM, "hipMalloc(%zu) for the sampler failed", cv.off);
+    }
+    char *base = (char *)m->mem;
+    sp.base = base;
+    auto bail = [&](lens_status_t s) {
+        (void)hipStreamSynchronize(st);
+        if (m->graph) (void)hipGraphDestroy(m->graph);
+        (void)hipFree(m->mem);
+        delete m;
+        return s;
+    };
+    std::vector<int32_t> off(W + 1);
+    for (int w = 0; w <= W; ++w) off[w] = w * nf;
+    int32_t *doff = (int32_t *)(base + o_off);
+    e = hipMemcpyAsync(doff, off.data(), off.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
+    double *amp = (double *)(base + o_amp);
+    lens_model_batch_t b;
+    b.n_samples = W;
+    b.free_offset = doff;
+    b.free = lens_pot_table_t{(int32_t)n, amp, amp + n, amp + 2 * n, amp + 3 * n, amp + 4 * n,
+                              amp + 5 * n, amp + 6 * n};
+    b.fixed = *fixed;
+    lens_status_t s = check_contents(ctx, &b, c, st);
+    if (s != LENS_OK) return bail(s);
+    McmcArgs A;
+    A.W = W;
+    A.nfree = nf;
+    A.params = d->params;
+    A.chi2 = d->chi2;
+    A.accepted = d->accepted;
+    A.lo = d->lo;
+    A.hi = d->hi;
+    A.step = d->step;
+    A.u = d->u;
+    A.prop = (double *)(base + o_prop);
+    A.amp = amp;
+    A.inside = (int *)(base + o_in);
+    A.chi2p = (const double *)(base + o_chi2p);
+    A.bK = d->convention == 1 ? 4.0 : 6.0;
+    // the fixed part once; the chi^2 of the initial state into chi2
+    e = launch_mcmc_load(A, st);
+    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
+    s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp, nullptr, false, st,
+                     checked(ctx), SRC_FIXED_ONLY);
+    if (s == LENS_OK)
+        s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp, d->chi2, false, st,
+                         checked(ctx), SRC_FREE_ONLY);
+    if (s != LENS_OK) return bail(s);
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
+    // one step: propose, chi^2 of the proposals, accept
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e)));
+    hipError_t le = launch_mcmc_propose(A, st);
+    if (le == hipSuccess)
+        s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp,
+                         (double *)(base + o_chi2p), false, st, false, SRC_FREE_ONLY);
+    if (le == hipSuccess && s == LENS_OK) le = launch_mcmc_accept(A, st);
+    e = hipStreamEndCapture(st, &m->graph);
+    if (le != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(le)));
+    if (s != LENS_OK) return bail(s);
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e)));
+    e = hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)));
+    *out = m;
+    return LENS_OK;
+}
+
+lens_status_t lens_mcmc_step(lens_mcmc_t *m, void *stream) {
+    if (!m) return fail(LENS_EINVAL, "sampler is NULL");
+    DeviceGuard dg(m->ctx->device);
+    HIP_TRY(hipGraphLaunch(m->exec, (hipStream_t)stream));
+    return LENS_OK;
+}
+
+lens_status_t lens_mcmc_destroy(lens_mcmc_t *m) {
+    if (!m) return LENS_OK;
+    DeviceGuard dg(m->ctx->device);
+    if (m->exec) (void)hipGraphExecDestroy(m->exec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    if (m->mem) (void)hipFree(m->mem);
+    delete m;
+    return LENS_OK;
 }
 
 lens_status_t lens_chi2_plan_launch(lens_chi2_plan_t *p, void *stream) {

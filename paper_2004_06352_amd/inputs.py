@@ -196,6 +196,26 @@ def config3(seed=3, n_samples=4096, uneven=False):
                 free_off=off, catalog=load_catalog(), zl=ZL)
 
 
+def sampler_start(seed=3, n_walkers=4096, step_frac=0.02):
+    """Walkers for the Metropolis sampler on the config-3 model: starting
+    points drawn from the uniform priors of the 6 free dPIEs, the prior box,
+    and proposal half-widths step_frac of each prior's width.  Returns a dict:
+    params (W, 6, 7), lo, hi, step (6, 7), fixed, catalog, zl."""
+    rng = np.random.default_rng(7000 + seed)
+    lo = np.array([[p[0] for p in pr] for pr in _FREE_PRIORS], dtype=np.float64)
+    hi = np.array([[p[1] for p in pr] for pr in _FREE_PRIORS], dtype=np.float64)
+    params = lo + rng.random((n_walkers, N_FREE, 7)) * (hi - lo)
+    return dict(name=f"cfg3_{n_walkers}walkers", params=np.ascontiguousarray(params), lo=lo,
+                hi=hi, step=step_frac * (hi - lo), fixed=fixed_galaxies(seed),
+                catalog=load_catalog(), zl=ZL)
+
+
+def sampler_uniforms(rng, n_walkers, n_free):
+    """One step's uniforms in (0, 1]: 7 n_free for the proposal, 1 for the
+    acceptance test, per walker."""
+    return np.ascontiguousarray(1.0 - rng.random((n_walkers, 7 * n_free + 1)))
+
+
 def config4(seed=3, n_samples=512, n=1000):
     """1000^2 pixel-centre vertices over [-75, 75]^2; the first 512 samples of
     the config-3 model and catalogue."""

@@ -1,0 +1,172 @@
+"""GPU parity of the Metropolis sampler against the oracle's step, through the
+C ABI: the same walkers, prior box, proposal widths and uniforms on both
+sides.  Proposals are the same rounded operations on both sides, so walker
+parameters agree bit for bit; chi^2 agrees within the source-plane bound;
+accept/reject decisions agree except where -2 ln u lies within that bound of
+chi2' - chi2 (a near tie: then both walkers are reset to the oracle's state
+and the count is reported)."""
+import math
+
+import numpy as np
+import pytest
+
+from lensutil import RTOL, chi2_source_bound
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_06352_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context(0, check=True)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _setup(B, ctx, s):
+    fixed = B.table_from_physical(B.to_device(s["fixed"], B.PHYS_KEYS), 0, ctx)
+    cat = B.catalog_to_device(B.catalog_with_dlsds(s["catalog"], s["zl"]))
+    return fixed, cat
+
+
+def _bounds(O, fixed_o, cat_o, params):
+    """Per-walker chi^2 error bounds at FP64 (oracle unlensing)."""
+    W, nf = params.shape[:2]
+    flat = params.reshape(W * nf, 7)
+    phys = {k: np.ascontiguousarray(flat[:, i]) for i, k in
+            enumerate(("x0", "y0", "sigma", "e", "phi", "rcore", "rcut"))}
+    free = O.phys_to_pots(phys)
+    off = (np.arange(W + 1) * nf).astype(np.int32)
+    out = np.zeros(W)
+    for w in range(W):
+        bx, by, sabs = O.unlens(fixed_o, free, off, w, cat_o)
+        out[w] = chi2_source_bound(bx, by, sabs, cat_o, RTOL[0])
+    return out
+
+
+def test_initial_chi2_and_zero_step(B, ctx, oracle):
+    """chi2 at creation matches the oracle; a zero-width step proposes the
+    current state, which is accepted with chi^2 unchanged bit for bit."""
+    from paper_2004_06352_amd import inputs
+    s = inputs.sampler_start(seed=3, n_walkers=96)
+    fixed, cat = _setup(B, ctx, s)
+    fixed_o, cat_o = O_model(oracle, s)
+    params = _dev(s["params"])
+    u = _dev(inputs.sampler_uniforms(np.random.default_rng(1), 96, 6))
+    zero = torch.zeros((6, 7), dtype=torch.float64, device="cuda")
+    m = B.Mcmc(fixed, cat, params, _dev(s["lo"]), _dev(s["hi"]), zero, u, ctx=ctx)
+    torch.cuda.synchronize()
+    c0 = m.chi2.cpu().numpy().copy()
+    ref = oracle.chi2_of_physical(fixed_o, cat_o, s["params"])
+    bound = _bounds(oracle, fixed_o, cat_o, s["params"])
+    assert np.all(np.abs(c0 - ref) <= bound), np.max(np.abs(c0 - ref) / bound)
+    for _ in range(3):
+        m.step()
+    torch.cuda.synchronize()
+    assert np.array_equal(params.cpu().numpy(), s["params"])
+    assert np.array_equal(m.chi2.cpu().numpy(), c0)
+    assert np.all(m.accepted.cpu().numpy() == 3)
+    m.close()
+
+
+def O_model(O, s):
+    return O.phys_to_pots(s["fixed"]), O.catalog_f(s["catalog"], s["zl"])
+
+
+def test_steps_match_oracle(B, ctx, oracle):
+    """24 steps of 128 walkers from prior draws, with proposals that leave the
+    prior box now and then, against the oracle's step on the same uniforms."""
+    from paper_2004_06352_amd import inputs
+    W, nf, K = 128, 6, 24
+    s = inputs.sampler_start(seed=4, n_walkers=W, step_frac=0.03)
+    fixed, cat = _setup(B, ctx, s)
+    fixed_o, cat_o = O_model(oracle, s)
+    lo, hi, step = s["lo"], s["hi"], s["step"]
+    params_o = s["params"].copy()
+    params = _dev(params_o)
+    u = torch.empty((W, 7 * nf + 1), dtype=torch.float64, device="cuda")
+    m = B.Mcmc(fixed, cat, params, _dev(lo), _dev(hi), _dev(step), u, ctx=ctx)
+    torch.cuda.synchronize()
+    chi2_o = oracle.chi2_of_physical(fixed_o, cat_o, params_o)
+    acc_o = np.zeros(W, np.int32)
+    rng = np.random.default_rng(11)
+    outside = near = 0
+    for k in range(K):
+        un = inputs.sampler_uniforms(rng, W, nf)
+        u.copy_(torch.from_numpy(un))
+        m.step()
+        # the oracle's view of this step: proposals, their chi^2, margins
+        prop = params_o + step[None] * (2.0 * un[:, :7 * nf].reshape(W, nf, 7) - 1.0)
+        inside = np.all((prop >= lo[None]) & (prop <= hi[None]), axis=(1, 2))
+        outside += int((~inside).sum())
+        chi2p_o = np.full(W, np.inf)
+        if inside.any():
+            chi2p_o[inside] = oracle.chi2_of_physical(fixed_o, cat_o, prop[inside])
+        margin = np.abs(-2.0 * np.log(un[:, -1]) - (chi2p_o - chi2_o))
+        before = params_o.copy()
+        oracle.mcmc_step(fixed_o, cat_o, params_o, chi2_o, acc_o, lo, hi, step, un)
+        assert np.array_equal(params_o[inside == False], before[inside == False])  # noqa: E712
+        torch.cuda.synchronize()
+        g_par = params.cpu().numpy()
+        g_chi2 = m.chi2.cpu().numpy()
+        g_acc = m.accepted.cpu().numpy()
+        tie = inside & (margin <= 1e-8 * (np.abs(chi2p_o) + np.abs(chi2_o) + 1.0))
+        same = g_acc == acc_o
+        assert np.all(same | tie), (k, np.flatnonzero(~(same | tie)))
+        ok = ~tie
+        assert np.array_equal(g_par[ok], params_o[ok]), k
+        rel = np.abs(g_chi2[ok] - chi2_o[ok]) / np.maximum(np.abs(chi2_o[ok]), 1.0)
+        assert np.all(rel <= 1e-9), (k, float(rel.max()))
+        if tie.any():
+            near += int(tie.sum())
+            idx = torch.as_tensor(np.flatnonzero(tie), device="cuda")
+            params[idx] = _dev(params_o[tie])
+            m.chi2[idx] = _dev(chi2_o[tie])
+            m.accepted[idx] = torch.as_tensor(acc_o[tie], device="cuda")
+    total = int(acc_o.sum())
+    print(f"sampler: {K} steps x {W} walkers, {total} accepted, {outside} proposals outside "
+          f"the prior box, {near} near ties")
+    assert outside > 0 and 0 < total < K * W
+    bound = _bounds(oracle, fixed_o, cat_o, params_o)
+    g_chi2 = m.chi2.cpu().numpy()
+    assert np.all(np.abs(g_chi2 - chi2_o) <= bound)
+    m.close()
+
+
+def test_rejects_invalid_boxes_and_walkers(B, ctx):
+    from paper_2004_06352_amd import inputs
+    s = inputs.sampler_start(seed=5, n_walkers=8)
+    fixed, cat = _setup(B, ctx, s)
+    u = _dev(inputs.sampler_uniforms(np.random.default_rng(2), 8, 6))
+    bad = s["params"].copy()
+    bad[3, 1, 2] = s["hi"][1, 2] + 1.0  # a walker outside its box
+    with pytest.raises(B.LensError, match="outside the prior box"):
+        B.Mcmc(fixed, cat, _dev(bad), _dev(s["lo"]), _dev(s["hi"]), _dev(s["step"]), u, ctx=ctx)
+    hi = s["hi"].copy()
+    hi[0, 3] = 1.0  # ellipticity may reach 1
+    with pytest.raises(B.LensError, match="valid domain"):
+        B.Mcmc(fixed, cat, _dev(s["params"]), _dev(s["lo"]), _dev(hi), _dev(s["step"]), u,
+               ctx=ctx)
+    hi = s["hi"].copy()
+    hi[2, 5] = s["lo"][2, 6]  # core may reach the cut radius
+    with pytest.raises(B.LensError, match="valid domain"):
+        B.Mcmc(fixed, cat, _dev(s["params"]), _dev(s["lo"]), _dev(hi), _dev(s["step"]), u,
+               ctx=ctx)
+    step = s["step"].copy()
+    step[0, 0] = -1.0
+    with pytest.raises(B.LensError, match="step"):
+        B.Mcmc(fixed, cat, _dev(s["params"]), _dev(s["lo"]), _dev(s["hi"]), _dev(step), u,
+               ctx=ctx)
+    assert math.isfinite(float(s["step"].sum()))
