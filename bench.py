@@ -68,7 +68,9 @@ def timed_steps(fn, steps, warmup, torch, per_step=True):
 
 
 MAP_SOURCES = ("paper_2004_06352_amd/csrc/maps.hip", "paper_2004_06352_amd/csrc/eval.h",
-               "paper_2004_06352_amd/csrc/lens_internal.h")
+               "paper_2004_06352_amd/csrc/lens_internal.h",
+               "paper_2004_06352_amd/csrc/series_coeffs.h",
+               "paper_2004_06352_amd/csrc/prologue.h")
 COUNTERS = os.path.join(ROOT, "profiles", "map_kernel_cfg2_2048sq_502pot_counters.md")
 
 

@@ -333,9 +333,10 @@ int batched_blocks(const lens_ctx_t *ctx, int S) {
 
 // Which parts of the source-plane sequence to issue: everything; only what
 // depends on the fixed potentials and the catalogue (their prologue and the
-// per-image constants); or only what depends on the free potentials (their
-// prologue and the per-sample kernel, the per-image constants being ready).
-enum SrcParts { SRC_ALL, SRC_FIXED_ONLY, SRC_FREE_ONLY };
+// per-image constants); only what depends on the free potentials (their
+// prologue and the per-sample kernel, the per-image constants being ready);
+// or only the per-sample kernel (the free derived table written elsewhere).
+enum SrcParts { SRC_ALL, SRC_FIXED_ONLY, SRC_FREE_ONLY, SRC_SAMPLES_ONLY };
 
 // Prologues, fixed deflection at the constraints, then the per-sample kernel.
 lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
@@ -353,7 +354,7 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
                                  DV.stride, ctx->small, st));
     else if (parts == SRC_FIXED_ONLY)
         TRY(run_prologue(ctx, &b->fixed, DF, st));
-    else
+    else if (parts == SRC_FREE_ONLY)
         TRY(run_prologue(ctx, &b->free, DV, st));
     if (with_check) TRY(status_check(ctx, st));
     Chi2SrcLaunch L;
@@ -376,7 +377,7 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
     L.src_y = sources ? L.src_x + (size_t)b->n_samples * c->n_sys : nullptr;
     const bool batched = path == LENS_CHI2_PATH_BATCHED;
     L.prec = prec == LENS_FP64 ? 0 : 1;
-    if (parts != SRC_FREE_ONLY) HIP_TRY(launch_chi2_prep(L, st));
+    if (parts == SRC_ALL || parts == SRC_FIXED_ONLY) HIP_TRY(launch_chi2_prep(L, st));
     if (parts == SRC_FIXED_ONLY || b->n_samples == 0) return LENS_OK;
     if (batched) {
         L.persistent = 1;
@@ -954,7 +955,7 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
                 return fail(LENS_EINVAL, "walker %d parameter %d = %g outside the prior box", w,
                             i, v);
         }
-    // own memory: derived tables, per-image constants, amplitudes, proposals
+    // own memory: derived tables, per-image constants, proposals
     const size_t n = (size_t)W * nf;
     Carve cv;
     SrcPlan sp;
@@ -963,7 +964,6 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
     sp.o_free = cv.take(derived_bytes((int)n));
     sp.o_rec = cv.take((size_t)3 * sp.nimg_pad * sizeof(double));
     sp.o_src = 0;
-    const size_t o_amp = cv.take(7 * n * sizeof(double));
     const size_t o_prop = cv.take((size_t)W * P * sizeof(double));
     const size_t o_in = cv.take((size_t)W * sizeof(int));
     const size_t o_chi2p = cv.take((size_t)W * sizeof(double));
@@ -991,13 +991,15 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
     e = hipMemcpyAsync(doff, off.data(), off.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
-    double *amp = (double *)(base + o_amp);
+    // the free table exists only as derived constants, written by the
+    // sampler's kernels
     lens_model_batch_t b;
     b.n_samples = W;
     b.free_offset = doff;
-    b.free = lens_pot_table_t{(int32_t)n, amp, amp + n, amp + 2 * n, amp + 3 * n, amp + 4 * n,
-                              amp + 5 * n, amp + 6 * n};
+    b.free = lens_pot_table_t{(int32_t)n, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, nullptr};
     b.fixed = *fixed;
+    const Derived DV = derived_in(base, sp.o_free, (int)n);
     lens_status_t s = check_contents(ctx, &b, c, st);
     if (s != LENS_OK) return bail(s);
     McmcArgs A;
@@ -1011,18 +1013,21 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
     A.step = d->step;
     A.u = d->u;
     A.prop = (double *)(base + o_prop);
-    A.amp = amp;
     A.inside = (int *)(base + o_in);
     A.chi2p = (const double *)(base + o_chi2p);
+    A.dd = const_cast<double *>(DV.d);
+    A.df = const_cast<float *>(DV.f);
+    A.stride = DV.stride;
+    A.status = ctx->small;
     A.bK = d->convention == 1 ? 4.0 : 6.0;
     // the fixed part once; the chi^2 of the initial state into chi2
-    e = launch_mcmc_load(A, st);
-    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
     s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp, nullptr, false, st,
                      checked(ctx), SRC_FIXED_ONLY);
-    if (s == LENS_OK)
-        s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp, d->chi2, false, st,
-                         checked(ctx), SRC_FREE_ONLY);
+    if (s != LENS_OK) return bail(s);
+    e = launch_mcmc_load(A, st);
+    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
+    s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp, d->chi2, false, st,
+                     false, SRC_SAMPLES_ONLY);
     if (s != LENS_OK) return bail(s);
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
@@ -1033,7 +1038,7 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
     hipError_t le = launch_mcmc_propose(A, st);
     if (le == hipSuccess)
         s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp,
-                         (double *)(base + o_chi2p), false, st, false, SRC_FREE_ONLY);
+                         (double *)(base + o_chi2p), false, st, false, SRC_SAMPLES_ONLY);
     if (le == hipSuccess && s == LENS_OK) le = launch_mcmc_accept(A, st);
     e = hipStreamEndCapture(st, &m->graph);
     if (le != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(le)));

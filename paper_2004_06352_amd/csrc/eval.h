@@ -23,12 +23,14 @@
 //   - reciprocals needed at the same time share one reciprocal of their
 //     product (1/a = b/(ab), 1/b = a/(ab));
 //   - atan(N/D) is reduced to |b| <= tan(pi/16) with atan(t) = pi/2 -
-//     atan(1/t) and a shift to the nearest of three centres, then summed as
-//     the Taylor series b - b^3/3 + ... to b^21/21 (truncation below 2e-17 b);
+//     atan(1/t) and a shift to the nearest of three centres, then
+//     atan(b) = b + b^3 p(b^2) with p of degree 7 (a Chebyshev interpolant;
+//     relative error below 1e-18 with its FP64 coefficients);
 //   - atanh(N/D) = ln(P/Q)/2, P = D + N, Q = D - N, is reduced by the binary
 //     exponent k of P/Q to ln(P/Q) = k ln 2 + 2 atanh(s), s = (P 2^-k - Q) /
 //     (P 2^-k + Q) (s = N/D exactly when k = 0), |s| <= 3 - 2 sqrt(2), and
-//     atanh(s) = s + s^3/3 + ... to s^19/19.
+//     atanh(s) = s + s^3 q(s^2) with q of degree 6 (relative error below
+//     5e-18).
 #pragma once
 
 #include "lens_internal.h"
@@ -79,8 +81,7 @@ constexpr double kLn2 = 0.6931471805599453;
 // nearest of the centres c = 0, tan(pi/8), 1 by atan(t) = atan(c) +
 // atan((t - c)/(1 + t c)) (exact for the rounded centre, whose arctangent is
 // the stored constant), leaving |b| <= tan(pi/16); then atan(|N|/D) =
-// pi/2 - atan(D/|N|) when |N| > D.  Series to b^21/21 (truncation below
-// 2e-17 b).
+// pi/2 - atan(D/|N|) when |N| > D.  Then the polynomial of degree 7 in b^2.
 constexpr double kTanPi16 = 0.198912367379658;
 constexpr double kTan3Pi16 = 0.6681786379192989;
 constexpr double kC1 = 0.41421356237309503;       // tan(pi/8), rounded
@@ -108,7 +109,7 @@ __device__ __forceinline__ double atan_finish(const AtanRed &r, double b, const 
     const double b2 = b * b;
     double p = S.at[0];
 #pragma unroll
-    for (int i = 1; i < 10; ++i) p = fma(p, b2, S.at[i]);
+    for (int i = 1; i < LENS_ATAN_N; ++i) p = fma(p, b2, S.at[i]);
     double t = fma(b * b2, p, b) + r.base;
     t = r.big ? kPi2 - t : t;
     return copysign(t, r.sign);
@@ -136,7 +137,7 @@ __device__ __forceinline__ double atanh_finish(const AtanhRed &r, double s, cons
     const double s2 = s * s;
     double p = S.ah[0];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) p = fma(p, s2, S.ah[i]);
+    for (int i = 1; i < LENS_ATANH_N; ++i) p = fma(p, s2, S.ah[i]);
     const double t = fma(s * s2, p, s);
     return fma(0.5 * kLn2, (double)r.k, t);
 }
@@ -194,8 +195,8 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
                 const double R2 = rcp64(ra_.den * rh.den);
                 const double b = ra_.num * (R2 * rh.den);
                 const double s = rh.num * (R2 * ra_.den);
-                ax = c[D_PF] * atan_finish(ra_, b, S);
-                ay = c[D_PF] * atanh_finish(rh, s, S);
+                ax = atan_finish(ra_, b, S);
+                ay = atanh_finish(rh, s, S);
             }
         } else {
             // circular: k = 0, D_w = A_w^2
@@ -210,13 +211,13 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
             }
             if (GRAD) {
                 const double g = c[D_DC] * inv_sum;
-                const double t = c[D_PF] * (g + c[D_DS]) * i12;
+                const double t = (g + c[D_DS]) * i12;
                 ax = t * xp;
                 ay = t * yp;
             }
         }
         if (HESS) {
-            const double ha = c[D_HF] * ra * iDa, hs = c[D_HF] * rs * iDs;
+            const double ha = ra * iDa, hs = rs * iDs;
             const double sa = c[D_SA] * pa, ss = c[D_SS] * ps;
             const double dh = ha - hs;
             hxx = fma(y2, dh, fma(ha, c[D_CA] + sa, -(hs * (c[D_CS_] + ss))));
@@ -242,22 +243,21 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
                 const double b = ra_.num * (RD * rh.den);
                 const double s = rh.num * (RD * ra_.den);
                 if (HESS) iDa = R2 * den;
-                ax = c[D_PF] * atan_finish(ra_, b, S);
-                ay = c[D_PF] * atanh_finish(rh, s, S);
+                ax = atan_finish(ra_, b, S);
+                ay = atanh_finish(rh, s, S);
             } else if (HESS) {
                 iDa = rcp64(Da);
             }
         } else {
             const double iA1 = rcp64(A1);
             if (GRAD) {
-                const double t = c[D_PF] * iA1;
-                ax = t * xp;
-                ay = t * yp;
+                ax = iA1 * xp;
+                ay = iA1 * yp;
             }
             iDa = iA1 * iA1;
         }
         if (HESS) {
-            const double ha = c[D_HF] * ra * iDa;
+            const double ha = ra * iDa;
             const double sa = c[D_SA] * pa;
             hxx = ha * (c[D_CA] + y2 + sa);
             hyy = ha * (c[D_SA2] + x2 + sa);
@@ -265,16 +265,27 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         }
     }
     if (SING && zero) ax = ay = hxx = hxy = hyy = 0.0;
+    // rotate back and accumulate, the prefactors folded into the rotation
+    // constants (ax, ay, hxx, hxy, hyy above carry no PF or HF)
     if (GRAD) {
-        acc[0] += fma(cp, ax, -(sp * ay));
-        acc[1] += fma(sp, ax, cp * ay);
+        const double pfc = c[D_PFC], pfs = c[D_PFS];
+        acc[0] = fma(pfc, ax, acc[0]);
+        acc[0] = fma(-pfs, ay, acc[0]);
+        acc[1] = fma(pfs, ax, acc[1]);
+        acc[1] = fma(pfc, ay, acc[1]);
     }
     if (HESS) {
-        const double c2 = c[D_C2], s2 = c[D_S2], cs = c[D_CS], cms = c[D_CMS];
-        const double t = 2.0 * cs * hxy;
-        acc[2] += fma(c2, hxx, fma(s2, hyy, -t));
-        acc[3] += fma(cs, hxx - hyy, cms * hxy);
-        acc[4] += fma(s2, hxx, fma(c2, hyy, t));
+        const double c2 = c[D_HC2], s2 = c[D_HS2], cs = c[D_HCS], cs2 = c[D_HCS2];
+        const double cms = c[D_HCMS];
+        acc[2] = fma(c2, hxx, acc[2]);
+        acc[2] = fma(s2, hyy, acc[2]);
+        acc[2] = fma(-cs2, hxy, acc[2]);
+        acc[3] = fma(cs, hxx, acc[3]);
+        acc[3] = fma(-cs, hyy, acc[3]);
+        acc[3] = fma(cms, hxy, acc[3]);
+        acc[4] = fma(s2, hxx, acc[4]);
+        acc[4] = fma(c2, hyy, acc[4]);
+        acc[4] = fma(cs2, hxy, acc[4]);
     }
 }
 
@@ -395,8 +406,8 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 const float Dy = fmaf(B1, B2, -f[F_K2] * y2);
                 const AtanRedF ra_ = atan_reduce_f(Nx, Dx);
                 const AtanhRedF rh = atanh_reduce_f(Ny, Dy);
-                ax = f[F_PF] * atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
-                ay = f[F_PF] * atanh_finish_f(rh, rh.num * frcp(rh.den), S);
+                ax = atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
+                ay = atanh_finish_f(rh, rh.num * frcp(rh.den), S);
             }
         } else {
             const float i12 = frcp(A1 * A2);
@@ -407,13 +418,13 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
             }
             if (GRAD) {
                 const float g = f[F_DC] * inv_sum;
-                const float t = f[F_PF] * (g + f[F_DS]) * i12;
+                const float t = (g + f[F_DS]) * i12;
                 ax = t * xp;
                 ay = t * yp;
             }
         }
         if (HESS) {
-            const float ha = f[F_HF] * ra * iDa, hs = f[F_HF] * rs * iDs;
+            const float ha = ra * iDa, hs = rs * iDs;
             const float sa = f[F_SA] * pa, ss = f[F_SS] * ps;
             hxx = fmaf(ha, f[F_CA] + y2 + sa, -(hs * (f[F_CS_] + y2 + ss)));
             hyy = fmaf(ha, f[F_SA2] + x2 + sa, -(hs * (f[F_SS2] + x2 + ss)));
@@ -431,21 +442,20 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 const float B1 = pa + f[F_Q2SA];
                 const AtanRedF ra_ = atan_reduce_f(k * xp, A1);
                 const AtanhRedF rh = atanh_reduce_f(k * yp, B1);
-                ax = f[F_PF] * atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
-                ay = f[F_PF] * atanh_finish_f(rh, rh.num * frcp(rh.den), S);
+                ax = atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
+                ay = atanh_finish_f(rh, rh.num * frcp(rh.den), S);
             }
             if (HESS) iDa = frcp(fmaf(A1, A1, f[F_K2] * x2));
         } else {
             const float iA1 = frcp(A1);
             if (GRAD) {
-                const float t = f[F_PF] * iA1;
-                ax = t * xp;
-                ay = t * yp;
+                ax = iA1 * xp;
+                ay = iA1 * yp;
             }
             iDa = iA1 * iA1;
         }
         if (HESS) {
-            const float ha = f[F_HF] * ra * iDa;
+            const float ha = ra * iDa;
             const float sa = f[F_SA] * pa;
             hxx = ha * (f[F_CA] + y2 + sa);
             hyy = ha * (f[F_SA2] + x2 + sa);
@@ -453,13 +463,14 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
         }
     }
     if (SING && zero) ax = ay = hxx = hxy = hyy = 0.f;
+    // rotate back, the prefactors folded into the rotation constants
     if (GRAD) {
-        const float cp = (float)cpd, sp = (float)spd;
-        out[0] = fmaf(cp, ax, -(sp * ay));
-        out[1] = fmaf(sp, ax, cp * ay);
+        const float pfc = f[F_PFC], pfs = f[F_PFS];
+        out[0] = fmaf(pfc, ax, -(pfs * ay));
+        out[1] = fmaf(pfs, ax, pfc * ay);
     }
     if (HESS) {
-        const float c2 = f[F_C2], s2 = f[F_S2], cs = f[F_CS], cms = f[F_CMS];
+        const float c2 = f[F_HC2], s2 = f[F_HS2], cs = f[F_HCS], cms = f[F_HCMS];
         const float t = 2.0f * cs * hxy;
         out[2] = fmaf(c2, hxx, fmaf(s2, hyy, -t));
         out[3] = fmaf(cs, hxx - hyy, cms * hxy);

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "lenshpc.h"
+#include "series_coeffs.h"
 
 namespace lens {
 
@@ -28,20 +29,24 @@ namespace lens {
 // ---------------------------------------------------------------------------
 enum DerivedIndex : int {
     D_X0 = 0, D_Y0, D_C, D_S,          // centre, cos(phi), sin(phi)
-    D_C2, D_S2, D_CS, D_CMS,           // c^2, s^2, c s, c^2 - s^2
+    D_PFC, D_PFS,                      // PF c, PF s: deflection rotated back
+    D_HC2, D_HS2, D_HCS, D_HCS2, D_HCMS,  // HF c^2, HF s^2, HF c s, 2 HF c s, HF (c^2 - s^2)
     D_Q2,                              // q^2
     D_CA, D_CS_, D_SA, D_SS,           // C_a = q^2 S_a^2, C_s, S_a, S_s
     D_Q2SA, D_Q2SS, D_SA2, D_SS2,      // q^2 S_a, q^2 S_s, S_a^2, S_s^2
     D_K, D_K2,                         // k, k^2
     D_DC, D_DS, D_Q2DS,                // C_s - C_a, S_s - S_a, q^2 (S_s - S_a)
-    D_PF, D_HF,                        // deflection and Hessian prefactors (F included)
+    D_PF,                              // deflection prefactor (F included)
     D_KIND,                            // kind bits: low word of the entry's bit pattern
     NDER
 };
 // Float copy of the constants used after the FP64 offset/rotation step.
 enum DerivedIndexF : int {
-    F_C2 = 0, F_S2, F_CS, F_CMS, F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS, F_SA2,
-    F_SS2, F_K, F_K2, F_DC, F_DS, F_Q2DS, F_PF, F_HF, NDERF
+    F_HC2 = 0, F_HS2, F_HCS, F_HCMS,   // HF c^2, HF s^2, HF c s, HF (c^2 - s^2)
+    F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS, F_SA2,
+    F_SS2, F_K, F_K2, F_DC, F_DS, F_Q2DS,
+    F_PFC, F_PFS,                      // PF c, PF s
+    NDERF
 };
 
 enum KindBits : int {
@@ -81,20 +86,23 @@ struct PotSoA {
     const double *x0, *y0, *b0, *eps, *phi, *rcore, *rcut;
 };
 
-// Taylor coefficients of atan and atanh (Horner order, highest first).  They
-// travel as a kernel argument so that the kernels read them from scalar
-// registers (literal FP64 constants would be held in vector registers and
-// copied before every fused multiply-add).
+// Polynomial coefficients of atan and atanh (Horner order, highest first):
+// FP64 Chebyshev interpolants on the reduced intervals (series_coeffs.h),
+// FP32 Taylor coefficients.  They travel as a kernel argument so that the
+// kernels read them from scalar registers (literal FP64 constants would be
+// held in vector registers and copied before every fused multiply-add).
 struct Series {
-    double at[10];  // 1/21, -1/19, 1/17, ..., -1/3
-    double ah[9];   // 1/19, 1/17, ..., 1/3
-    float atf[4];   // 1/9, -1/7, 1/5, -1/3
-    float ahf[4];   // 1/9, 1/7, 1/5, 1/3
+    double at[LENS_ATAN_N];   // atan(b) = b + b^3 p(b^2), p ~ -1/3 + b^2/5 - ...
+    double ah[LENS_ATANH_N];  // atanh(s) = s + s^3 q(s^2), q ~ 1/3 + s^2/5 + ...
+    float atf[4];             // 1/9, -1/7, 1/5, -1/3
+    float ahf[4];             // 1/9, 1/7, 1/5, 1/3
 };
 inline Series make_series() {
     Series S;
-    for (int i = 0; i < 10; ++i) S.at[i] = ((i % 2) ? -1.0 : 1.0) / (21 - 2 * i);
-    for (int i = 0; i < 9; ++i) S.ah[i] = 1.0 / (19 - 2 * i);
+    const double at[LENS_ATAN_N] = {LENS_ATAN_COEFFS};
+    const double ah[LENS_ATANH_N] = {LENS_ATANH_COEFFS};
+    for (int i = 0; i < LENS_ATAN_N; ++i) S.at[i] = at[i];
+    for (int i = 0; i < LENS_ATANH_N; ++i) S.ah[i] = ah[i];
     for (int i = 0; i < 4; ++i) S.atf[i] = (float)(((i % 2) ? -1.0 : 1.0) / (9 - 2 * i));
     for (int i = 0; i < 4; ++i) S.ahf[i] = (float)(1.0 / (9 - 2 * i));
     return S;

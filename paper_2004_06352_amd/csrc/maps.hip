@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include "eval.h"
+#include "prologue.h"
 
 namespace lens {
 
@@ -79,69 +80,11 @@ hipError_t launch_phys_to_amp(const double *sigma, const double *e, int n, int c
 
 // ---------------------------------------------------------------------------
 // Parameter prologue: amplitude-form table -> derived constants (FP64 block
-// and its FP32 copy).  Invalid entries get NaN prefactors (their contribution
-// is NaN) and raise ST_INVALID_TABLE.
+// and its FP32 copy).
 __device__ __forceinline__ void prologue_one(const PotSoA &in, int k, double *__restrict__ dd,
                                              float *__restrict__ df, int stride, int *status) {
-    const double x0 = in.x0[k], y0 = in.y0[k], b0 = in.b0[k], eps = in.eps[k];
-    const double phi = in.phi[k], a = in.rcore[k], s = in.rcut[k];
-    const bool cut = isfinite(s);
-    const bool ok = isfinite(x0) && isfinite(y0) && isfinite(b0) && b0 >= 0.0 &&
-                    isfinite(eps) && eps >= 0.0 && eps < 1.0 && isfinite(phi) &&
-                    isfinite(a) && a >= 0.0 && !isnan(s) && s > a;
-    const bool ell = eps > 0.0;
-    double c = 1.0, sn = 0.0;
-    if (ell) {
-        c = cos(phi);
-        sn = sin(phi);
-    }
-    const double q = (1.0 - eps) / (1.0 + eps), q2 = q * q;
-    const double Sa = (1.0 + eps) * a;
-    const double Ss = cut ? (1.0 + eps) * s : 0.0;
-    const double k1 = ell ? 2.0 * sqrt(eps) / (1.0 + eps) : 0.0;
-    const double F = cut ? s / (s - a) : 1.0;
-    const double om = 1.0 - eps;
-    const double DC = cut ? om * om * ((s - a) * (s + a)) : 0.0;
-    const double DS = cut ? (1.0 + eps) * (s - a) : 0.0;
-    double PF = ell ? F * b0 * (1.0 - eps * eps) / (2.0 * sqrt(eps)) : F * b0;
-    double HF = F * b0 * om;
-    int kind = (ell ? K_ELL : 0) | (cut ? K_CUT : 0) | (a == 0.0 ? K_SING : 0);
-    if (!ok) {
-        PF = NAN;
-        HF = NAN;
-        kind = K_INVALID | K_CUT | K_ELL;
-        atomicOr(status, ST_INVALID_TABLE);
-    }
-    double v[NDER];
-    v[D_X0] = x0;
-    v[D_Y0] = y0;
-    v[D_C] = c;
-    v[D_S] = sn;
-    v[D_C2] = c * c;
-    v[D_S2] = sn * sn;
-    v[D_CS] = c * sn;
-    v[D_CMS] = c * c - sn * sn;
-    v[D_Q2] = q2;
-    v[D_CA] = q2 * Sa * Sa;
-    v[D_CS_] = q2 * Ss * Ss;
-    v[D_SA] = Sa;
-    v[D_SS] = Ss;
-    v[D_Q2SA] = q2 * Sa;
-    v[D_Q2SS] = q2 * Ss;
-    v[D_SA2] = Sa * Sa;
-    v[D_SS2] = Ss * Ss;
-    v[D_K] = k1;
-    v[D_K2] = k1 * k1;
-    v[D_DC] = DC;
-    v[D_DS] = DS;
-    v[D_Q2DS] = q2 * DS;
-    v[D_PF] = PF;
-    v[D_HF] = HF;
-    v[D_KIND] = __longlong_as_double((long long)kind);  // bit pattern, low word = kind
-    for (int i = 0; i < NDER; ++i) dd[(size_t)i * stride + k] = v[i];
-    const int map_f[NDERF] = {D_C2, D_S2, D_CS, D_CMS, D_Q2, D_CA, D_CS_, D_SA, D_SS, D_Q2SA,
-                              D_Q2SS, D_SA2, D_SS2, D_K, D_K2, D_DC, D_DS, D_Q2DS, D_PF, D_HF};
-    for (int i = 0; i < NDERF; ++i) df[(size_t)i * stride + k] = (float)v[map_f[i]];
+    prologue_values(in.x0[k], in.y0[k], in.b0[k], in.eps[k], in.phi[k], in.rcore[k], in.rcut[k],
+                    k, dd, df, stride, status);
 }
 
 __global__ void prologue_kernel(PotSoA in, int n, double *__restrict__ dd, float *__restrict__ df,

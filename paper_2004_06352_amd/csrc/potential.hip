@@ -23,7 +23,7 @@
 namespace lens {
 
 // ln D for D > 0: D = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s),
-// s = (m - 1)/(m + 1) (|s| <= 3 - 2 sqrt 2), by the atanh series of eval.h.
+// s = (m - 1)/(m + 1) (|s| <= 3 - 2 sqrt 2), by the atanh polynomial of eval.h.
 __device__ __forceinline__ double log_pos(double D, const Series &S) {
     double m = __builtin_amdgcn_frexp_mant(D);  // [0.5, 1)
     int e = __builtin_amdgcn_frexp_exp(D);
@@ -35,7 +35,7 @@ __device__ __forceinline__ double log_pos(double D, const Series &S) {
     const double s2 = s * s;
     double p = S.ah[0];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) p = fma(p, s2, S.ah[i]);
+    for (int i = 1; i < LENS_ATANH_N; ++i) p = fma(p, s2, S.ah[i]);
     const double t = fma(s * s2, p, s);
     return fma(kLn2, (double)e, 2.0 * t);
 }
