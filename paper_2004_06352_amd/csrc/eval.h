@@ -57,6 +57,13 @@ __device__ __forceinline__ int uniform_kind(double k) {
     return __builtin_amdgcn_readfirstlane(__double2loint(k));
 }
 
+// True on every active lane when both predicates hold on all of them (scalar
+// operations on the compare masks and the execution mask).
+__device__ __forceinline__ bool wave_all(bool p, bool q) {
+    return (__builtin_amdgcn_ballot_w64(p) & __builtin_amdgcn_ballot_w64(q)) ==
+           __builtin_amdgcn_read_exec();
+}
+
 // ---------------------------------------------------------------------------
 // FP64 building blocks
 // The hardware estimates are accurate to about 2^-24 (measured over 2^20
@@ -105,12 +112,16 @@ __device__ __forceinline__ AtanRed atan_reduce(double N, double D) {
     r.sign = N;
     return r;
 }
-__device__ __forceinline__ double atan_finish(const AtanRed &r, double b, const Series &S) {
+// atan(b) for |b| <= tan(pi/16): b + b^3 p(b^2).
+__device__ __forceinline__ double atan_poly(double b, const Series &S) {
     const double b2 = b * b;
     double p = S.at[0];
 #pragma unroll
     for (int i = 1; i < LENS_ATAN_N; ++i) p = fma(p, b2, S.at[i]);
-    double t = fma(b * b2, p, b) + r.base;
+    return fma(b * b2, p, b);
+}
+__device__ __forceinline__ double atan_finish(const AtanRed &r, double b, const Series &S) {
+    double t = atan_poly(b, S) + r.base;
     t = r.big ? kPi2 - t : t;
     return copysign(t, r.sign);
 }
@@ -133,13 +144,17 @@ __device__ __forceinline__ AtanhRed atanh_reduce(double N, double D) {
     r.k = k;
     return r;
 }
-__device__ __forceinline__ double atanh_finish(const AtanhRed &r, double s, const Series &S) {
+// atanh(s) for |s| <= 3 - 2 sqrt 2: s + s^3 q(s^2).
+constexpr double kAtanhS = 0.171572875253809;  // 3 - 2 sqrt 2, rounded down
+__device__ __forceinline__ double atanh_poly(double s, const Series &S) {
     const double s2 = s * s;
     double p = S.ah[0];
 #pragma unroll
     for (int i = 1; i < LENS_ATANH_N; ++i) p = fma(p, s2, S.ah[i]);
-    const double t = fma(s * s2, p, s);
-    return fma(0.5 * kLn2, (double)r.k, t);
+    return fma(s * s2, p, s);
+}
+__device__ __forceinline__ double atanh_finish(const AtanhRed &r, double s, const Series &S) {
+    return fma(0.5 * kLn2, (double)r.k, atanh_poly(s, S));
 }
 
 // ---------------------------------------------------------------------------
@@ -190,13 +205,22 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
                 const double Dx = fma(A1, A2, k2x2);
                 const double Ny = k * yp * (g + c[D_Q2DS]);
                 const double Dy = fma(B1, B2, -c[D_K2] * y2);
-                const AtanRed ra_ = atan_reduce(Nx, Dx);
-                const AtanhRed rh = atanh_reduce(Ny, Dy);
-                const double R2 = rcp64(ra_.den * rh.den);
-                const double b = ra_.num * (R2 * rh.den);
-                const double s = rh.num * (R2 * ra_.den);
-                ax = atan_finish(ra_, b, S);
-                ay = atanh_finish(rh, s, S);
+                // Away from the cores both ratios are small (the two cores'
+                // terms nearly cancel): when they are inside the polynomials'
+                // intervals for the whole wave, skip the reductions.
+                if (wave_all(fabs(Nx) <= kTanPi16 * Dx, fabs(Ny) <= kAtanhS * Dy)) {
+                    const double R2 = rcp64(Dx * Dy);
+                    ax = atan_poly(Nx * (R2 * Dy), S);
+                    ay = atanh_poly(Ny * (R2 * Dx), S);
+                } else {
+                    const AtanRed ra_ = atan_reduce(Nx, Dx);
+                    const AtanhRed rh = atanh_reduce(Ny, Dy);
+                    const double R2 = rcp64(ra_.den * rh.den);
+                    const double b = ra_.num * (R2 * rh.den);
+                    const double s = rh.num * (R2 * ra_.den);
+                    ax = atan_finish(ra_, b, S);
+                    ay = atanh_finish(rh, s, S);
+                }
             }
         } else {
             // circular: k = 0, D_w = A_w^2
@@ -328,12 +352,15 @@ __device__ __forceinline__ AtanRedF atan_reduce_f(float N, float D) {
     r.sign = N;
     return r;
 }
-__device__ __forceinline__ float atan_finish_f(const AtanRedF &r, float b, const Series &S) {
+__device__ __forceinline__ float atan_poly_f(float b, const Series &S) {
     const float b2 = b * b;
     float p = S.atf[0];
 #pragma unroll
     for (int i = 1; i < 4; ++i) p = fmaf(p, b2, S.atf[i]);
-    float t = fmaf(b * b2, p, b) + r.base;
+    return fmaf(b * b2, p, b);
+}
+__device__ __forceinline__ float atan_finish_f(const AtanRedF &r, float b, const Series &S) {
+    float t = atan_poly_f(b, S) + r.base;
     t = r.big ? 1.57079633f - t : t;
     return copysignf(t, r.sign);
 }
@@ -354,13 +381,15 @@ __device__ __forceinline__ AtanhRedF atanh_reduce_f(float N, float D) {
     r.k = k;
     return r;
 }
-__device__ __forceinline__ float atanh_finish_f(const AtanhRedF &r, float s, const Series &S) {
+__device__ __forceinline__ float atanh_poly_f(float s, const Series &S) {
     const float s2 = s * s;
     float p = S.ahf[0];
 #pragma unroll
     for (int i = 1; i < 4; ++i) p = fmaf(p, s2, S.ahf[i]);
-    const float t = fmaf(s * s2, p, s);
-    return fmaf(0.34657359f, (float)r.k, t);
+    return fmaf(s * s2, p, s);
+}
+__device__ __forceinline__ float atanh_finish_f(const AtanhRedF &r, float s, const Series &S) {
+    return fmaf(0.34657359f, (float)r.k, atanh_poly_f(s, S));
 }
 
 // FP32 evaluation: offset and rotation in FP64 (|x| ~ 100" would lose
@@ -404,10 +433,15 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 const float Dx = fmaf(A1, A2, k2x2);
                 const float Ny = k * yp * (g + f[F_Q2DS]);
                 const float Dy = fmaf(B1, B2, -f[F_K2] * y2);
-                const AtanRedF ra_ = atan_reduce_f(Nx, Dx);
-                const AtanhRedF rh = atanh_reduce_f(Ny, Dy);
-                ax = atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
-                ay = atanh_finish_f(rh, rh.num * frcp(rh.den), S);
+                if (wave_all(fabsf(Nx) <= 0.19891237f * Dx, fabsf(Ny) <= 0.17157287f * Dy)) {
+                    ax = atan_poly_f(Nx * frcp(Dx), S);
+                    ay = atanh_poly_f(Ny * frcp(Dy), S);
+                } else {
+                    const AtanRedF ra_ = atan_reduce_f(Nx, Dx);
+                    const AtanhRedF rh = atanh_reduce_f(Ny, Dy);
+                    ax = atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
+                    ay = atanh_finish_f(rh, rh.num * frcp(rh.den), S);
+                }
             }
         } else {
             const float i12 = frcp(A1 * A2);

@@ -126,6 +126,12 @@ hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, 
 
 // ---------------------------------------------------------------------------
 // The map kernel.
+
+// A wave-uniform double moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double v) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
 struct MapArgs {
     Derived tab;
     GridArgs g;
@@ -168,8 +174,10 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
     extern __shared__ double lds[];
     const int bx = blockDim.x, by = blockDim.y;
     const int i_base = blockIdx.x * bx * PPT + threadIdx.x;
-    const int j = blockIdx.y * by + threadIdx.y;
-    const double y = grid_coord(a.g.y0, j, a.g.dy);
+    // block_x is a multiple of 64, so a wave never spans two rows: the row
+    // index and its coordinate are wave-uniform and live in scalar registers
+    const int j = __builtin_amdgcn_readfirstlane(blockIdx.y * by + threadIdx.y);
+    const double y = uniform_f64(grid_coord(a.g.y0, j, a.g.dy));
     double x[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) x[p] = grid_coord(a.g.x0, i_base + p * bx, a.g.dx);
