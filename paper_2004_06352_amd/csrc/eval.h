@@ -182,6 +182,7 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         const double ra = rsq64(ta), rs = rsq64(ts);
         const double pa = ta * ra, ps = ts * rs;
         const double A1 = pa + c[D_SA], A2 = ps + c[D_SS];
+        const double B1 = pa + c[D_Q2SA], B2 = ps + c[D_Q2SS];
         const double sum = pa + ps;
         double inv_sum, iDa = 0.0, iDs = 0.0;
         if (kind & K_ELL) {
@@ -200,18 +201,20 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
             if (GRAD) {
                 const double g = c[D_DC] * inv_sum;
                 const double k = c[D_K];
-                const double B1 = pa + c[D_Q2SA], B2 = ps + c[D_Q2SS];
                 const double Nx = k * xp * (g + c[D_DS]);
                 const double Dx = fma(A1, A2, k2x2);
                 const double Ny = k * yp * (g + c[D_Q2DS]);
                 const double Dy = fma(B1, B2, -c[D_K2] * y2);
                 // Away from the cores both ratios are small (the two cores'
                 // terms nearly cancel): when they are inside the polynomials'
-                // intervals for the whole wave, skip the reductions.
-                if (wave_all(fabs(Nx) <= kTanPi16 * Dx, fabs(Ny) <= kAtanhS * Dy)) {
-                    const double R2 = rcp64(Dx * Dy);
-                    ax = atan_poly(Nx * (R2 * Dy), S);
-                    ay = atanh_poly(Ny * (R2 * Dx), S);
+                // intervals for the whole wave, skip the reductions.  (The
+                // ratios are formed first; the few waves that fail the test
+                // discard them.)
+                const double R2f = rcp64(Dx * Dy);
+                const double bf = Nx * (R2f * Dy), sf = Ny * (R2f * Dx);
+                if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
+                    ax = atan_poly(bf, S);
+                    ay = atanh_poly(sf, S);
                 } else {
                     const AtanRed ra_ = atan_reduce(Nx, Dx);
                     const AtanhRed rh = atanh_reduce(Ny, Dy);
@@ -241,11 +244,12 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
             }
         }
         if (HESS) {
+            // per core: C_w + S_w psi_w = S_w B_w and S_w^2 + S_w psi_w = S_w A_w
             const double ha = ra * iDa, hs = rs * iDs;
-            const double sa = c[D_SA] * pa, ss = c[D_SS] * ps;
             const double dh = ha - hs;
-            hxx = fma(y2, dh, fma(ha, c[D_CA] + sa, -(hs * (c[D_CS_] + ss))));
-            hyy = fma(x2, dh, fma(ha, c[D_SA2] + sa, -(hs * (c[D_SS2] + ss))));
+            const double wa = ha * c[D_SA], ws = hs * c[D_SS];
+            hxx = fma(y2, dh, fma(wa, B1, -(ws * B2)));
+            hyy = fma(x2, dh, fma(wa, A1, -(ws * A2)));
             hxy = -(xp * yp) * dh;
         }
     } else {
@@ -253,12 +257,12 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         const double ra = rsq64(ta);
         const double pa = ta * ra;
         const double A1 = pa + c[D_SA];
+        const double B1 = pa + c[D_Q2SA];
         double iDa = 0.0;
         if (kind & K_ELL) {
             const double k = c[D_K];
             const double Da = fma(A1, A1, c[D_K2] * x2);
             if (GRAD) {
-                const double B1 = pa + c[D_Q2SA];
                 const AtanRed ra_ = atan_reduce(k * xp, A1);
                 const AtanhRed rh = atanh_reduce(k * yp, B1);
                 const double den = ra_.den * rh.den;
@@ -282,9 +286,9 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         }
         if (HESS) {
             const double ha = ra * iDa;
-            const double sa = c[D_SA] * pa;
-            hxx = ha * (c[D_CA] + y2 + sa);
-            hyy = ha * (c[D_SA2] + x2 + sa);
+            const double wa = ha * c[D_SA];
+            hxx = fma(ha, y2, wa * B1);
+            hyy = fma(ha, x2, wa * A1);
             hxy = -xp * yp * ha;
         }
     }

@@ -33,7 +33,7 @@ enum DerivedIndex : int {
     D_HC2, D_HS2, D_HCS, D_HCS2, D_HCMS,  // HF c^2, HF s^2, HF c s, 2 HF c s, HF (c^2 - s^2)
     D_Q2,                              // q^2
     D_CA, D_CS_, D_SA, D_SS,           // C_a = q^2 S_a^2, C_s, S_a, S_s
-    D_Q2SA, D_Q2SS, D_SA2, D_SS2,      // q^2 S_a, q^2 S_s, S_a^2, S_s^2
+    D_Q2SA, D_Q2SS,                    // q^2 S_a, q^2 S_s
     D_K, D_K2,                         // k, k^2
     D_DC, D_DS, D_Q2DS,                // C_s - C_a, S_s - S_a, q^2 (S_s - S_a)
     D_PF,                              // deflection prefactor (F included)
