@@ -145,6 +145,44 @@ def test_steps_match_oracle(B, ctx, oracle):
     m.close()
 
 
+@pytest.mark.parametrize("nf,W", [(1, 40), (40, 9)])
+def test_other_model_sizes(B, ctx, oracle, nf, W):
+    """One free potential (many walkers per block) and forty (a walker's
+    parameters span several blocks' worth of threads): three steps, walker
+    parameters bit-identical to the oracle's, chi^2 within 1e-9 relative."""
+    from paper_2004_06352_amd import inputs
+    rng = np.random.default_rng(100 + nf)
+    base = inputs.sampler_start(seed=5, n_walkers=1)
+    cx, cy = rng.uniform(-60, 60, nf), rng.uniform(-60, 60, nf)
+    lo = np.stack([cx - 1, cy - 1, np.full(nf, 100.0), np.zeros(nf), np.zeros(nf),
+                   np.full(nf, 0.01), np.full(nf, 5.0)], axis=1)
+    hi = np.stack([cx + 1, cy + 1, np.full(nf, 300.0), np.full(nf, 0.5), np.full(nf, np.pi),
+                   np.full(nf, 0.2), np.full(nf, 50.0)], axis=1)
+    params = lo + rng.random((W, nf, 7)) * (hi - lo)
+    step = 0.05 * (hi - lo)
+    s = dict(base, params=params, lo=lo, hi=hi, step=step)
+    fixed, cat = _setup(B, ctx, s)
+    fixed_o, cat_o = O_model(oracle, s)
+    params_o = params.copy()
+    pd = _dev(params_o)
+    u = torch.empty((W, 7 * nf + 1), dtype=torch.float64, device="cuda")
+    m = B.Mcmc(fixed, cat, pd, _dev(lo), _dev(hi), _dev(step), u, ctx=ctx)
+    torch.cuda.synchronize()
+    chi2_o = oracle.chi2_of_physical(fixed_o, cat_o, params_o)
+    acc_o = np.zeros(W, np.int32)
+    for k in range(3):
+        un = inputs.sampler_uniforms(rng, W, nf)
+        u.copy_(torch.from_numpy(un))
+        m.step()
+        oracle.mcmc_step(fixed_o, cat_o, params_o, chi2_o, acc_o, lo, hi, step, un)
+        torch.cuda.synchronize()
+        assert np.array_equal(m.accepted.cpu().numpy(), acc_o), k
+        assert np.array_equal(pd.cpu().numpy(), params_o), k
+        rel = np.abs(m.chi2.cpu().numpy() - chi2_o) / np.maximum(np.abs(chi2_o), 1.0)
+        assert np.all(rel <= 1e-9), (k, float(rel.max()))
+    m.close()
+
+
 def test_rejects_invalid_boxes_and_walkers(B, ctx):
     from paper_2004_06352_amd import inputs
     s = inputs.sampler_start(seed=5, n_walkers=8)
