@@ -238,9 +238,15 @@ hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Vertex deflection (Dls/Ds = 1) of samples m0 .. m0+nsamp-1: the fixed part
 // (given) plus the sample's free potentials in index order.  A block covers
-// 256 vertices of one sample; the sample's potentials are staged in LDS
-// (chunks of AG_CHUNK) and read by broadcast.
-constexpr int AG_CHUNK = 16;
+// 256 vertices of AG_SPB consecutive samples, whose free potentials are
+// contiguous in the table: they are staged in LDS (chunks of AG_CHUNK, read by
+// broadcast) once for the group, and each vertex's fixed deflection is read
+// once for the group.  Walking the staged potentials in order, a thread
+// finishes a sample when the next potential belongs to a later one (the
+// boundaries are uniform), so every sample sums fixed then free in index
+// order, as the one-sample-per-block form did.
+constexpr int AG_CHUNK = 32;
+constexpr int AG_SPB = 4;
 
 template <int PREC>
 __global__ void __launch_bounds__(256, 6) alpha_grid_kernel(AlphaGridLaunch a) {
@@ -249,21 +255,40 @@ __global__ void __launch_bounds__(256, 6) alpha_grid_kernel(AlphaGridLaunch a) {
     const size_t nv = (size_t)a.grid.nx * a.grid.ny;
     const int tid = threadIdx.x;
     const size_t v = (size_t)blockIdx.x * 256 + tid;
-    const int s = blockIdx.y;
-    const int m = a.m0 + s;
+    const int s0 = blockIdx.y * AG_SPB;
+    const int ns = min(AG_SPB, a.nsamp - s0);
     const int nf = a.freet.n, st = a.freet.stride;
-    const int k0 = min(max(a.free_off[m], 0), nf);
-    const int k1 = min(max(a.free_off[m + 1], k0), nf);
     const int i = (int)(v % a.grid.nx), j = (int)(v / a.grid.nx);
     const double x = grid_coord(a.grid.x0, i, a.grid.dx);
     const double y = grid_coord(a.grid.y0, j, a.grid.dy);
-    double acc[5] = {0, 0, 0, 0, 0};
+    double fx = 0.0, fy = 0.0;
     if (a.afix_x && v < nv) {
-        acc[0] = a.afix_x[v];
-        acc[1] = a.afix_y[v];
+        fx = a.afix_x[v];
+        fy = a.afix_y[v];
     }
-    for (int kc = k0; kc < k1; kc += AG_CHUNK) {
-        const int cnt = min(AG_CHUNK, k1 - kc);
+    // sample s of the group owns potentials [kb, ke) (offsets clamped to the
+    // table and made non-decreasing)
+    const int *off = a.free_off + a.m0 + s0;
+    const int K0 = min(max(off[0], 0), nf);
+    int kb = K0;
+    int K1 = K0;
+    for (int q = 1; q <= ns; ++q) K1 = min(max(off[q], K1), nf);
+    int s = 0;
+    int ke = min(max(off[1], kb), nf);
+    double acc[5] = {fx, fy, 0, 0, 0};
+    auto finish = [&]() {
+        if (v < nv) {
+            a.out[(size_t)(s0 + s) * 2 * nv + v] = acc[0];
+            a.out[(size_t)(s0 + s) * 2 * nv + nv + v] = acc[1];
+        }
+        acc[0] = fx;
+        acc[1] = fy;
+        ++s;
+        kb = ke;
+        if (s < ns) ke = min(max(off[s + 1], kb), nf);
+    };
+    for (int kc = K0; kc < K1; kc += AG_CHUNK) {
+        const int cnt = min(AG_CHUNK, K1 - kc);
         __syncthreads();
         for (int e = tid; e < cnt * NDER; e += 256) {
             const int ci = e / cnt, kk = e - ci * cnt;
@@ -277,6 +302,7 @@ __global__ void __launch_bounds__(256, 6) alpha_grid_kernel(AlphaGridLaunch a) {
         }
         __syncthreads();
         for (int kk = 0; kk < cnt; ++kk) {
+            while (s < ns && kc + kk >= ke) finish();
             if (PREC == 0) {
                 eval_pot_f64<true, false>(ConstD{pd + kk * NDER, 1}, x, y, acc, a.S);
             } else {
@@ -288,10 +314,7 @@ __global__ void __launch_bounds__(256, 6) alpha_grid_kernel(AlphaGridLaunch a) {
             }
         }
     }
-    if (v < nv) {
-        a.out[(size_t)s * 2 * nv + v] = acc[0];
-        a.out[(size_t)s * 2 * nv + nv + v] = acc[1];
-    }
+    while (s < ns) finish();
 }
 
 hipError_t launch_alpha_grid(const AlphaGridLaunch &L0, hipStream_t st) {
@@ -299,7 +322,7 @@ hipError_t launch_alpha_grid(const AlphaGridLaunch &L0, hipStream_t st) {
     L.S = make_series();
     const size_t nv = (size_t)L.grid.nx * L.grid.ny;
     if (nv == 0 || L.nsamp <= 0) return hipSuccess;
-    dim3 grid((unsigned)((nv + 255) / 256), L.nsamp);
+    dim3 grid((unsigned)((nv + 255) / 256), (unsigned)((L.nsamp + AG_SPB - 1) / AG_SPB));
     if (grid.y > 65535u) return hipErrorInvalidConfiguration;
     if (L.prec == 0)
         hipLaunchKernelGGL(alpha_grid_kernel<0>, grid, dim3(256), 0, st, L);
