@@ -421,6 +421,7 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
         const float ra = frsq(ta), rs = frsq(ts);
         const float pa = ta * ra, ps = ts * rs;
         const float A1 = pa + f[F_SA], A2 = ps + f[F_SS];
+        const float B1 = pa + f[F_Q2SA], B2 = ps + f[F_Q2SS];
         const float inv_sum = frcp(pa + ps);
         float iDa = 0.f, iDs = 0.f;
         if (kind & K_ELL) {
@@ -432,7 +433,6 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
             if (GRAD) {
                 const float g = f[F_DC] * inv_sum;
                 const float k = f[F_K];
-                const float B1 = pa + f[F_Q2SA], B2 = ps + f[F_Q2SS];
                 const float Nx = k * xp * (g + f[F_DS]);
                 const float Dx = fmaf(A1, A2, k2x2);
                 const float Ny = k * yp * (g + f[F_Q2DS]);
@@ -462,22 +462,24 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
             }
         }
         if (HESS) {
+            // per core: C_w + S_w psi_w = S_w B_w and S_w^2 + S_w psi_w = S_w A_w
             const float ha = ra * iDa, hs = rs * iDs;
-            const float sa = f[F_SA] * pa, ss = f[F_SS] * ps;
-            hxx = fmaf(ha, f[F_CA] + y2 + sa, -(hs * (f[F_CS_] + y2 + ss)));
-            hyy = fmaf(ha, f[F_SA2] + x2 + sa, -(hs * (f[F_SS2] + x2 + ss)));
-            hxy = -xp * yp * (ha - hs);
+            const float dh = ha - hs;
+            const float wa = ha * f[F_SA], ws = hs * f[F_SS];
+            hxx = fmaf(y2, dh, fmaf(wa, B1, -(ws * B2)));
+            hyy = fmaf(x2, dh, fmaf(wa, A1, -(ws * A2)));
+            hxy = -xp * yp * dh;
         }
     } else {
         const float ta = f[F_CA] + R;
         const float ra = frsq(ta);
         const float pa = ta * ra;
         const float A1 = pa + f[F_SA];
+        const float B1 = pa + f[F_Q2SA];
         float iDa = 0.f;
         if (kind & K_ELL) {
             const float k = f[F_K];
             if (GRAD) {
-                const float B1 = pa + f[F_Q2SA];
                 const AtanRedF ra_ = atan_reduce_f(k * xp, A1);
                 const AtanhRedF rh = atanh_reduce_f(k * yp, B1);
                 ax = atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
@@ -494,9 +496,9 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
         }
         if (HESS) {
             const float ha = ra * iDa;
-            const float sa = f[F_SA] * pa;
-            hxx = ha * (f[F_CA] + y2 + sa);
-            hyy = ha * (f[F_SA2] + x2 + sa);
+            const float wa = ha * f[F_SA];
+            hxx = fmaf(ha, y2, wa * B1);
+            hyy = fmaf(ha, x2, wa * A1);
             hxy = -xp * yp * ha;
         }
     }

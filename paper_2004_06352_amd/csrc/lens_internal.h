@@ -43,8 +43,8 @@ enum DerivedIndex : int {
 // Float copy of the constants used after the FP64 offset/rotation step.
 enum DerivedIndexF : int {
     F_HC2 = 0, F_HS2, F_HCS, F_HCMS,   // HF c^2, HF s^2, HF c s, HF (c^2 - s^2)
-    F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS, F_SA2,
-    F_SS2, F_K, F_K2, F_DC, F_DS, F_Q2DS,
+    F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS,
+    F_K, F_K2, F_DC, F_DS, F_Q2DS,
     F_PFC, F_PFS,                      // PF c, PF s
     NDERF
 };

@@ -72,7 +72,7 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     for (int i = 0; i < NDER; ++i) dd[(size_t)i * stride + k] = v[i];
     const double fv[NDERF] = {v[D_HC2],  v[D_HS2],   v[D_HCS],    v[D_HCMS], q2,
                               v[D_CA],   v[D_CS_],   Sa,          Ss,        v[D_Q2SA],
-                              v[D_Q2SS], Sa * Sa,    Ss * Ss,     k1,        v[D_K2],
+                              v[D_Q2SS], k1,         v[D_K2],
                               DC,        DS,         v[D_Q2DS],   v[D_PFC],  v[D_PFS]};
     for (int i = 0; i < NDERF; ++i) df[(size_t)i * stride + k] = (float)fv[i];
 }
