@@ -70,11 +70,20 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
             const double Dx = fma(A1, A2, k2x2);
             const double Ny = k * yp * (g + c[D_Q2DS]);
             const double Dy = fma(B1, B2, -c[D_K2] * y2);
-            const AtanRed ra_ = atan_reduce(Nx, Dx);
-            const AtanhRed rh = atanh_reduce(Ny, Dy);
-            const double R2 = rcp64(ra_.den * rh.den);
-            const double ax = c[D_PF] * atan_finish(ra_, ra_.num * (R2 * rh.den), S);
-            const double ay = c[D_PF] * atanh_finish(rh, rh.num * (R2 * ra_.den), S);
+            // the deflection's fast path (small ratios on the whole wave)
+            const double R2f = rcp64(Dx * Dy);
+            const double bf = Nx * (R2f * Dy), sf = Ny * (R2f * Dx);
+            double ax, ay;
+            if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
+                ax = c[D_PF] * atan_poly(bf, S);
+                ay = c[D_PF] * atanh_poly(sf, S);
+            } else {
+                const AtanRed ra_ = atan_reduce(Nx, Dx);
+                const AtanhRed rh = atanh_reduce(Ny, Dy);
+                const double R2 = rcp64(ra_.den * rh.den);
+                ax = c[D_PF] * atan_finish(ra_, ra_.num * (R2 * rh.den), S);
+                ay = c[D_PF] * atanh_finish(rh, rh.num * (R2 * ra_.den), S);
+            }
             const double la = log_pos(fma(A1, A1, k2x2), S), ls = log_pos(fma(A2, A2, k2x2), S);
             const double L = 0.5 * (c[D_PF] * k) * (c[D_SA] * la - c[D_SS] * ls);
             v = fma(xp, ax, yp * ay) - L;
