@@ -127,6 +127,14 @@ hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, 
 // ---------------------------------------------------------------------------
 // The map kernel.
 
+// A copy of a double in vector registers (kept there: the compiler cannot
+// rematerialise it from the scalar source).
+__device__ __forceinline__ double vgpr_f64(double x) {
+    double r;
+    asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
 // A wave-uniform double moved to scalar registers.
 __device__ __forceinline__ double uniform_f64(double v) {
     return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
@@ -195,11 +203,20 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
         }
 
     const int n = a.tab.n, st = a.tab.stride;
+    // The polynomials' first step multiplies the leading coefficient and adds
+    // the next: with both in scalar registers every evaluation would copy one
+    // to a vector register first (one constant-bus operand per instruction),
+    // so the leading coefficients are held in vector registers for the loop.
+    Series S = a.S;
+    if (PREC == 0) {
+        S.at[0] = vgpr_f64(a.S.at[0]);
+        S.ah[0] = vgpr_f64(a.S.ah[0]);
+    }
     auto body = [&](const ConstD cd, const ConstF cf) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             if (PREC == 0) {
-                eval_pot_f64<GRAD, HESS>(cd, x[p], y, acc[p], a.S);
+                eval_pot_f64<GRAD, HESS>(cd, x[p], y, acc[p], S);
             } else {
                 float o[5];
                 eval_pot_f32<GRAD, HESS>(cd, cf, x[p], y, o, a.S);
