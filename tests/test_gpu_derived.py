@@ -107,3 +107,28 @@ def test_derived_outputs_subset_and_errors(B, ctx):
     with pytest.raises(B.LensError):  # output far smaller than the grid: refused before launch
         B.derived_map(t, (8192, 8192, 0.0, 0.0, 0.01, 0.01), 0.7, B.FP64, ctx=ctx,
                       out={"kappa": torch.empty(10, dtype=torch.float64, device="cuda")})
+
+
+def test_config2_full_size_sampled(B, ctx, oracle):
+    """Derived maps of the 2048^2 x 502 workload (FP64, the benchmark's
+    model) at 1200 sampled pixels (corners and random) against the oracle's
+    formulas applied to its own second derivatives there."""
+    from lensutil import grid_points
+    from paper_2004_06352_amd import inputs
+    c = inputs.config2()
+    f = oracle.dlsds(c["zl"], c["zs"])
+    grid = c["grid"]
+    nx, ny = grid[0], grid[1]
+    rng = np.random.default_rng(31)
+    jj = np.concatenate([[0, 0, ny - 1, ny - 1], rng.integers(0, ny, 1196)])
+    ii = np.concatenate([[0, nx - 1, 0, nx - 1], rng.integers(0, nx, 1196)])
+    x, y = grid_points(grid, ii, jj)
+    val, mag = oracle.eval_points(oracle.phys_to_pots(c["pots"]), x, y)
+    h = (f * val[2], f * val[3], f * val[4])
+    ref = oracle.derived(*h)
+    bound = derived_bounds(h, (f * mag[2], f * mag[3], f * mag[4]), RTOL[0])
+    got = B.derived_map(_table(B, ctx, c["pots"]), grid, f, 0, ctx=ctx)
+    torch.cuda.synchronize()
+    sampled = {k: v[jj, ii] for k, v in got.items()}
+    n_mu = _check(sampled, ref, bound, "cfg2 sampled")
+    print(f"cfg2 derived sampled: mu compared at {n_mu} of {len(ii)} pixels")

@@ -86,3 +86,37 @@ def test_potential_map_rejects_fp32(B, ctx):
         B._check(B.lib().lens_potential_map(ctx.handle, B.C.byref(B._pot(t)),
                                             B.C.byref(B._grid((4, 4, 0.0, 0.0, 1.0, 1.0))),
                                             1.0, B.FP32_ACC64, B._ptr(out), None))
+
+
+def test_config2_full_size_sampled(B, ctx, oracle):
+    """Potential and time-delay maps of the 2048^2 x 502 workload at 600
+    sampled pixels (corners and random), each against the oracle on a 1x1
+    grid at that pixel's coordinates."""
+    from lensutil import grid_points
+    from paper_2004_06352_amd import inputs
+    c = inputs.config2()
+    f = oracle.dlsds(c["zl"], c["zs"])
+    scale = oracle.time_delay_scale(c["zl"], c["zs"])
+    beta = (3.0, -2.0)
+    grid = c["grid"]
+    nx, ny = grid[0], grid[1]
+    rng = np.random.default_rng(41)
+    jj = np.concatenate([[0, 0, ny - 1, ny - 1], rng.integers(0, ny, 596)])
+    ii = np.concatenate([[0, nx - 1, 0, nx - 1], rng.integers(0, nx, 596)])
+    x, y = grid_points(grid, ii, jj)
+    pots = oracle.phys_to_pots(c["pots"])
+    table = _table(B, ctx, c["pots"])
+    psi = B.potential_map(table, grid, f, ctx=ctx)
+    td = B.time_delay_map(table, grid, f, beta, scale, ctx=ctx)
+    torch.cuda.synchronize()
+    g_psi, g_td = psi.cpu().numpy()[jj, ii], td.cpu().numpy()[jj, ii]
+    r_psi, m_psi, r_td, m_td = (np.zeros(len(ii)) for _ in range(4))
+    for n in range(len(ii)):
+        pt = (1, 1, float(x[n]), float(y[n]), 1.0, 1.0)
+        v, m = oracle.potential_map(pots, pt, f)
+        r_psi[n], m_psi[n] = v[0, 0], m[0, 0]
+        v, m = oracle.potential_map(pots, pt, f, beta, scale)
+        r_td[n], m_td[n] = v[0, 0], m[0, 0]
+    w1 = assert_within(g_psi, r_psi, m_psi, RTOL[0], "cfg2 potential sampled")
+    w2 = assert_within(g_td, r_td, m_td, RTOL[0], "cfg2 time delay sampled")
+    print(f"cfg2 sampled: potential err/scale {w1:.3g}, time delay {w2:.3g}")

@@ -183,6 +183,39 @@ def test_other_model_sizes(B, ctx, oracle, nf, W):
     m.close()
 
 
+def test_full_size_sampled(B, oracle):
+    """4096 walkers of the six-potential model in the benchmark's launch
+    configuration (unchecked context); three steps; 48 sampled walkers against
+    the oracle's step on the same uniforms (walkers are independent chains)."""
+    from paper_2004_06352_amd import inputs
+    W, nf = 4096, 6
+    s = inputs.sampler_start(n_walkers=W)
+    uctx = B.Context(0, check=False)
+    fixed, cat = _setup(B, uctx, s)
+    fixed_o, cat_o = O_model(oracle, s)
+    params = _dev(s["params"])
+    u = torch.empty((W, 7 * nf + 1), dtype=torch.float64, device="cuda")
+    m = B.Mcmc(fixed, cat, params, _dev(s["lo"]), _dev(s["hi"]), _dev(s["step"]), u, ctx=uctx)
+    pick = np.random.default_rng(3).choice(W, 48, replace=False)
+    po = s["params"][pick].copy()
+    co = oracle.chi2_of_physical(fixed_o, cat_o, po)
+    ao = np.zeros(len(pick), np.int32)
+    rng = np.random.default_rng(21)
+    for k in range(3):
+        un = inputs.sampler_uniforms(rng, W, nf)
+        u.copy_(torch.from_numpy(un))
+        m.step()
+        oracle.mcmc_step(fixed_o, cat_o, po, co, ao, s["lo"], s["hi"], s["step"],
+                         np.ascontiguousarray(un[pick]))
+    torch.cuda.synchronize()
+    assert np.array_equal(m.accepted.cpu().numpy()[pick], ao)
+    assert np.array_equal(params.cpu().numpy()[pick], po)
+    rel = np.abs(m.chi2.cpu().numpy()[pick] - co) / np.maximum(np.abs(co), 1.0)
+    assert np.all(rel <= 1e-9), float(rel.max())
+    m.close()
+    uctx.close()
+
+
 def test_rejects_invalid_boxes_and_walkers(B, ctx):
     from paper_2004_06352_amd import inputs
     s = inputs.sampler_start(seed=5, n_walkers=8)
