@@ -84,10 +84,9 @@ def map_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per FP64 map launch from the committed FETCH_SIZE / WRITE_SIZE
-    passes, each scaled by what the same counter read for a plain copy of known
-    size; None when the counters were taken on other kernel sources."""
+def _counters():
+    """key: value lines of the committed counter summary, or None when the
+    counters were taken on other kernel sources."""
     if not os.path.exists(COUNTERS):
         return None
     kv = {}
@@ -97,6 +96,25 @@ def measured_traffic():
                 k, v = line[2:].split(": ", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("source_hash") != map_source_hash():
+        return None
+    return kv
+
+
+def measured_executed_flop():
+    """Executed FP64 FLOP per map launch (64 (ADD + MUL + TRANS) + 128 FMA per
+    wave instruction, from the committed VALU counter pass), or None."""
+    kv = _counters()
+    if kv is None or "map_executed_flop" not in kv:
+        return None
+    return float(kv["map_executed_flop"])
+
+
+def measured_traffic():
+    """HBM bytes per FP64 map launch from the committed FETCH_SIZE / WRITE_SIZE
+    passes, each scaled by what the same counter read for a plain copy of known
+    size; None when the counters were taken on other kernel sources."""
+    kv = _counters()
+    if kv is None:
         return None
     copy_bytes = float(kv["copy_bytes"])
     fetch = float(kv["map_fetch_kib"]) * copy_bytes / (1024 * float(kv["copy_fetch_kib"]))
@@ -239,6 +257,12 @@ def main():
                      "kernel": "map_kernel<fp64, grad+hess>", "flops_per_eval": FLOPS_PER_EVAL,
                      "avg_launch_ms": ev * 1e3},
     }
+    exe = measured_executed_flop()
+    if exe is not None:
+        # the executed-instruction view of the same launches (counters taken on
+        # the one-pixel-per-thread shape): FP64 vector work actually issued
+        rec["roofline"]["executed_flop_per_launch"] = exe
+        rec["roofline"]["executed_frac"] = exe / ev / 1e12 / PEAK_FP64_TFLOPS
     secondary = {}
     # FP32 evaluation with FP64 accumulation and compensated FP32
     for name, prec in (("fp32_acc64", B.FP32_ACC64), ("fp32_comp32", B.FP32_COMP32)):
