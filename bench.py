@@ -188,8 +188,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout "
-              "is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path (maps would shard by pixel bands and chi^2 batches by sample).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
