@@ -187,30 +187,38 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         double inv_sum, iDa = 0.0, iDs = 0.0;
         if (kind & K_ELL) {
             const double k2x2 = c[D_K2] * x2;
+            // One reciprocal (a quarter-rate instruction) serves every quotient:
+            // the cores' sum (for psi_s - psi_a), the Hessian denominators D_a,
+            // D_s and the deflection ratios' denominators Dx, Dy.
+            const double Dx = fma(A1, A2, k2x2);
+            const double Dy = fma(B1, B2, -c[D_K2] * y2);
+            const double XG = GRAD ? Dx * Dy : 1.0;
+            double Da = 0.0, Ds = 0.0, DD = 1.0;
             if (HESS) {
-                const double Da = fma(A1, A1, k2x2), Ds = fma(A2, A2, k2x2);
-                const double DD = Da * Ds;
-                const double R1 = rcp64(sum * DD);
-                inv_sum = R1 * DD;
+                Da = fma(A1, A1, k2x2);
+                Ds = fma(A2, A2, k2x2);
+                DD = Da * Ds;
+            }
+            const double XH = HESS ? sum * DD : sum;
+            const double Rall = rcp64(GRAD ? XH * XG : XH);
+            const double R1 = GRAD ? Rall * XG : Rall;  // 1/(sum DD) or 1/sum
+            inv_sum = HESS ? R1 * DD : R1;
+            if (HESS) {
                 const double t = R1 * sum;
                 iDa = t * Ds;
                 iDs = t * Da;
-            } else {
-                inv_sum = rcp64(sum);
             }
             if (GRAD) {
                 const double g = c[D_DC] * inv_sum;
                 const double k = c[D_K];
                 const double Nx = k * xp * (g + c[D_DS]);
-                const double Dx = fma(A1, A2, k2x2);
                 const double Ny = k * yp * (g + c[D_Q2DS]);
-                const double Dy = fma(B1, B2, -c[D_K2] * y2);
                 // Away from the cores both ratios are small (the two cores'
                 // terms nearly cancel): when they are inside the polynomials'
                 // intervals for the whole wave, skip the reductions.  (The
                 // ratios are formed first; the few waves that fail the test
                 // discard them.)
-                const double R2f = rcp64(Dx * Dy);
+                const double R2f = Rall * XH;  // 1/(Dx Dy)
                 const double bf = Nx * (R2f * Dy), sf = Ny * (R2f * Dx);
                 if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
                     ax = atan_poly(bf, S);
