@@ -430,13 +430,22 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
         const float pa = ta * ra, ps = ts * rs;
         const float A1 = pa + f[F_SA], A2 = ps + f[F_SS];
         const float B1 = pa + f[F_Q2SA], B2 = ps + f[F_Q2SS];
-        const float inv_sum = frcp(pa + ps);
-        float iDa = 0.f, iDs = 0.f;
+        const float sum = pa + ps;
+        float inv_sum, iDa = 0.f, iDs = 0.f;
         if (kind & K_ELL) {
             const float k2x2 = f[F_K2] * x2;
+            // reciprocals (quarter-rate) shared through products: one for the
+            // sum and the Hessian denominators, one for the ratio denominators
             if (HESS) {
-                iDa = frcp(fmaf(A1, A1, k2x2));
-                iDs = frcp(fmaf(A2, A2, k2x2));
+                const float Da = fmaf(A1, A1, k2x2), Ds = fmaf(A2, A2, k2x2);
+                const float DD = Da * Ds;
+                const float R1 = frcp(sum * DD);
+                inv_sum = R1 * DD;
+                const float t = R1 * sum;
+                iDa = t * Ds;
+                iDs = t * Da;
+            } else {
+                inv_sum = frcp(sum);
             }
             if (GRAD) {
                 const float g = f[F_DC] * inv_sum;
@@ -445,9 +454,11 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 const float Dx = fmaf(A1, A2, k2x2);
                 const float Ny = k * yp * (g + f[F_Q2DS]);
                 const float Dy = fmaf(B1, B2, -f[F_K2] * y2);
-                if (wave_all(fabsf(Nx) <= 0.19891237f * Dx, fabsf(Ny) <= 0.17157287f * Dy)) {
-                    ax = atan_poly_f(Nx * frcp(Dx), S);
-                    ay = atanh_poly_f(Ny * frcp(Dy), S);
+                const float R2 = frcp(Dx * Dy);
+                const float bf = Nx * (R2 * Dy), sf = Ny * (R2 * Dx);
+                if (wave_all(fabsf(bf) <= 0.19891237f, fabsf(sf) <= 0.17157287f)) {
+                    ax = atan_poly_f(bf, S);
+                    ay = atanh_poly_f(sf, S);
                 } else {
                     const AtanRedF ra_ = atan_reduce_f(Nx, Dx);
                     const AtanhRedF rh = atanh_reduce_f(Ny, Dy);
@@ -456,7 +467,10 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 }
             }
         } else {
-            const float i12 = frcp(A1 * A2);
+            const float A12 = A1 * A2;
+            const float R1 = frcp(sum * A12);
+            inv_sum = R1 * A12;
+            const float i12 = R1 * sum;
             if (HESS) {
                 const float iA1 = i12 * A2, iA2 = i12 * A1;
                 iDa = iA1 * iA1;
