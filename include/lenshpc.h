@@ -370,7 +370,7 @@ typedef struct {
 lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
                                const lens_catalog_t *cat, const lens_mcmc_desc_t *desc,
                                void *stream, lens_mcmc_t **out);
-/* One step of every walker (one graph launch, asynchronous on stream). */
+/* One step of every walker (one kernel launch, asynchronous on stream). */
 lens_status_t lens_mcmc_step(lens_mcmc_t *sampler, void *stream);
 lens_status_t lens_mcmc_destroy(lens_mcmc_t *sampler);
 

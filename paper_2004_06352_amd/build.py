@@ -34,7 +34,6 @@ SOURCES = {
     "chi2.hip": ["-ffp-contract=off"],
     "images.hip": ["-ffp-contract=off"],
     "potential.hip": ["-ffp-contract=off"],
-    "sampler.hip": ["-ffp-contract=off"],
 }
 
 

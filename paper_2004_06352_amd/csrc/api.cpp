@@ -15,7 +15,6 @@
 
 #include "chi2_launch.h"
 #include "potential_launch.h"
-#include "sampler_launch.h"
 
 using namespace lens;
 
@@ -60,9 +59,8 @@ struct lens_ctx {
 
 struct lens_mcmc {
     lens_ctx_t *ctx = nullptr;
-    void *mem = nullptr;  // derived tables, per-image constants, proposals, amplitudes
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    void *mem = nullptr;  // fixed potentials' derived table and per-image constants
+    lens::Chi2SrcLaunch step;  // the fused step launch (mode 2)
 };
 
 struct lens_chi2_plan {
@@ -282,22 +280,17 @@ lens_status_t check_catalog(const lens_catalog_t *c) {
 }
 
 // Checked contexts: the offset arrays and catalogue values, read back.
-lens_status_t check_contents(lens_ctx_t *ctx, const lens_model_batch_t *b,
-                             const lens_catalog_t *c, hipStream_t st) {
+// In checked contexts: the catalogue's offsets, errors, Dls/Ds and positions.
+lens_status_t check_catalog_contents(lens_ctx_t *ctx, const lens_catalog_t *c, hipStream_t st) {
     if (!checked(ctx)) return LENS_OK;
-    std::vector<int32_t> fo(b->n_samples + 1), io(c->n_sys + 1);
+    std::vector<int32_t> io(c->n_sys + 1);
     std::vector<double> sig(c->n_img), f(c->n_sys), x(c->n_img), y(c->n_img);
-    HIP_TRY(hipMemcpyAsync(fo.data(), b->free_offset, fo.size() * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(io.data(), c->img_offset, io.size() * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(sig.data(), c->sigma, sig.size() * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(f.data(), c->dlsds, f.size() * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(x.data(), c->x, x.size() * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(y.data(), c->y, y.size() * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (fo[0] != 0 || fo[b->n_samples] != b->free.n)
-        return fail(LENS_EINVAL, "free_offset must run from 0 to free.n = %d", b->free.n);
-    for (int m = 0; m < b->n_samples; ++m)
-        if (fo[m + 1] < fo[m]) return fail(LENS_EINVAL, "free_offset decreases at %d", m);
     if (io[0] != 0 || io[c->n_sys] != c->n_img)
         return fail(LENS_EINVAL, "img_offset must run from 0 to n_img = %d", c->n_img);
     for (int i = 0; i < c->n_sys; ++i) {
@@ -308,6 +301,20 @@ lens_status_t check_contents(lens_ctx_t *ctx, const lens_model_batch_t *b,
         if (!(sig[t] > 0.0) || !is_fin(sig[t]) || !is_fin(x[t]) || !is_fin(y[t]))
             return fail(LENS_EINVAL, "catalog image %d: bad position or sigma", t);
     return LENS_OK;
+}
+
+// In checked contexts: the batch's sample offsets, then the catalogue.
+lens_status_t check_contents(lens_ctx_t *ctx, const lens_model_batch_t *b,
+                             const lens_catalog_t *c, hipStream_t st) {
+    if (!checked(ctx)) return LENS_OK;
+    std::vector<int32_t> fo(b->n_samples + 1);
+    HIP_TRY(hipMemcpyAsync(fo.data(), b->free_offset, fo.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (fo[0] != 0 || fo[b->n_samples] != b->free.n)
+        return fail(LENS_EINVAL, "free_offset must run from 0 to free.n = %d", b->free.n);
+    for (int m = 0; m < b->n_samples; ++m)
+        if (fo[m + 1] < fo[m]) return fail(LENS_EINVAL, "free_offset decreases at %d", m);
+    return check_catalog_contents(ctx, c, st);
 }
 
 struct SrcPlan {
@@ -903,8 +910,10 @@ lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *b
 }
 
 // ---------------------------------------------------------------------------
-// Metropolis sampler: proposal kernel, batched chi^2 of the proposals (fixed
-// part resident), acceptance kernel; one step is one graph launch.
+// Metropolis sampler: the fixed part's per-image constants are computed once;
+// a step is one launch of the source-plane chi^2 kernel in its sampler form
+// (each wave proposes for its walker, derives the proposal's potentials,
+// evaluates its chi^2 and takes the decision).
 lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
                                const lens_catalog_t *c, const lens_mcmc_desc_t *d, void *stream,
                                lens_mcmc_t **out) {
@@ -955,19 +964,14 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
                 return fail(LENS_EINVAL, "walker %d parameter %d = %g outside the prior box", w,
                             i, v);
         }
-    // own memory: derived tables, per-image constants, proposals
-    const size_t n = (size_t)W * nf;
+    // own memory: the fixed potentials' derived table and per-image constants
     Carve cv;
     SrcPlan sp;
     sp.nimg_pad = (c->n_img + 63) / 64 * 64;
     sp.o_fix = cv.take(derived_bytes(fixed->n));
-    sp.o_free = cv.take(derived_bytes((int)n));
+    sp.o_free = cv.take(derived_bytes(0));
     sp.o_rec = cv.take((size_t)3 * sp.nimg_pad * sizeof(double));
     sp.o_src = 0;
-    const size_t o_prop = cv.take((size_t)W * P * sizeof(double));
-    const size_t o_in = cv.take((size_t)W * sizeof(int));
-    const size_t o_chi2p = cv.take((size_t)W * sizeof(double));
-    const size_t o_off = cv.take(((size_t)W + 1) * sizeof(int));
     lens_mcmc_t *m = new lens_mcmc_t();
     m->ctx = ctx;
     hipError_t e = hipMalloc(&m->mem, cv.off);
@@ -976,78 +980,61 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
         delete m;
         return fail(LENS_ENOMEM, "hipMalloc(%zu) for the sampler failed", cv.off);
     }
-    char *base = (char *)m->mem;
-    sp.base = base;
+    sp.base = (char *)m->mem;
     auto bail = [&](lens_status_t s) {
         (void)hipStreamSynchronize(st);
-        if (m->graph) (void)hipGraphDestroy(m->graph);
         (void)hipFree(m->mem);
         delete m;
         return s;
     };
-    std::vector<int32_t> off(W + 1);
-    for (int w = 0; w <= W; ++w) off[w] = w * nf;
-    int32_t *doff = (int32_t *)(base + o_off);
-    e = hipMemcpyAsync(doff, off.data(), off.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
-    // the free table exists only as derived constants, written by the
-    // sampler's kernels
+    // the fixed part once (its prologue and the per-image constants); the
+    // walkers' potentials are derived by the chi^2 waves themselves
     lens_model_batch_t b;
     b.n_samples = W;
-    b.free_offset = doff;
-    b.free = lens_pot_table_t{(int32_t)n, nullptr, nullptr, nullptr, nullptr,
-                              nullptr, nullptr, nullptr};
+    b.free_offset = nullptr;
+    b.free = lens_pot_table_t{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     b.fixed = *fixed;
-    const Derived DV = derived_in(base, sp.o_free, (int)n);
-    lens_status_t s = check_contents(ctx, &b, c, st);
+    lens_status_t s = check_catalog_contents(ctx, c, st);
     if (s != LENS_OK) return bail(s);
-    McmcArgs A;
-    A.W = W;
-    A.nfree = nf;
-    A.params = d->params;
-    A.chi2 = d->chi2;
-    A.accepted = d->accepted;
-    A.lo = d->lo;
-    A.hi = d->hi;
-    A.step = d->step;
-    A.u = d->u;
-    A.prop = (double *)(base + o_prop);
-    A.inside = (int *)(base + o_in);
-    A.chi2p = (const double *)(base + o_chi2p);
-    A.dd = const_cast<double *>(DV.d);
-    A.df = const_cast<float *>(DV.f);
-    A.stride = DV.stride;
-    A.status = ctx->small;
-    A.bK = d->convention == 1 ? 4.0 : 6.0;
-    // the fixed part once; the chi^2 of the initial state into chi2
-    s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp, nullptr, false, st,
-                     checked(ctx), SRC_FIXED_ONLY);
+    s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp, nullptr,
+                                   false, st, checked(ctx), SRC_FIXED_ONLY);
     if (s != LENS_OK) return bail(s);
-    e = launch_mcmc_load(A, st);
+    Chi2SrcLaunch &L = m->step;
+    L.freet = derived_in(sp.base, sp.o_free, 0);
+    L.fixedt = derived_in(sp.base, sp.o_fix, fixed->n);
+    L.free_off = nullptr;
+    L.n_samples = W;
+    L.sample0 = 0;
+    L.nsys = c->n_sys;
+    L.nimg = c->n_img;
+    L.img_off = c->img_offset;
+    L.x = c->x;
+    L.y = c->y;
+    L.sig = c->sigma;
+    L.f = c->dlsds;
+    L.nimg_pad = sp.nimg_pad;
+    L.chi2 = nullptr;
+    L.src_x = L.src_y = nullptr;
+    L.rec = (double *)(sp.base + sp.o_rec);
+    L.persistent = 1;
+    L.grid_blocks = batched_blocks(ctx, W);
+    L.prec = 0;
+    L.mc.nfree = nf;
+    L.mc.params = d->params;
+    L.mc.chi2 = d->chi2;
+    L.mc.accepted = d->accepted;
+    L.mc.lo = d->lo;
+    L.mc.hi = d->hi;
+    L.mc.step = d->step;
+    L.mc.u = d->u;
+    L.mc.bK = d->convention == 1 ? 4.0 : 6.0;
+    L.mc.status = ctx->small;
+    // chi^2 of the initial state
+    L.mc.mode = 1;
+    e = launch_mcmc_chi2(L, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
-    s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp, d->chi2, false, st,
-                     false, SRC_SAMPLES_ONLY);
-    if (s != LENS_OK) return bail(s);
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
-    // one step: propose, chi^2 of the proposals, accept
-    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess)
-        return bail(fail(LENS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e)));
-    hipError_t le = launch_mcmc_propose(A, st);
-    if (le == hipSuccess)
-        s = src_sequence(ctx, &b, c, LENS_FP64, LENS_CHI2_PATH_BATCHED, sp,
-                         (double *)(base + o_chi2p), false, st, false, SRC_SAMPLES_ONLY);
-    if (le == hipSuccess && s == LENS_OK) le = launch_mcmc_accept(A, st);
-    e = hipStreamEndCapture(st, &m->graph);
-    if (le != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(le)));
-    if (s != LENS_OK) return bail(s);
-    if (e != hipSuccess)
-        return bail(fail(LENS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e)));
-    e = hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess)
-        return bail(fail(LENS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)));
+    L.mc.mode = 2;
     *out = m;
     return LENS_OK;
 }
@@ -1055,15 +1042,13 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
 lens_status_t lens_mcmc_step(lens_mcmc_t *m, void *stream) {
     if (!m) return fail(LENS_EINVAL, "sampler is NULL");
     DeviceGuard dg(m->ctx->device);
-    HIP_TRY(hipGraphLaunch(m->exec, (hipStream_t)stream));
+    HIP_TRY(launch_mcmc_chi2(m->step, (hipStream_t)stream));
     return LENS_OK;
 }
 
 lens_status_t lens_mcmc_destroy(lens_mcmc_t *m) {
     if (!m) return LENS_OK;
     DeviceGuard dg(m->ctx->device);
-    if (m->exec) (void)hipGraphExecDestroy(m->exec);
-    if (m->graph) (void)hipGraphDestroy(m->graph);
     if (m->mem) (void)hipFree(m->mem);
     delete m;
     return LENS_OK;

@@ -19,6 +19,8 @@
 
 #include <algorithm>
 
+#include "prologue.h"
+
 #include "chi2_launch.h"
 #include "eval.h"
 
@@ -104,7 +106,32 @@ __global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) 
 // the batch it is evaluated in, on the path or on the launch shape.
 constexpr int SRC_IPL = 4;
 
-template <int PREC>
+// The sampler's walker: physical parameters of its potential k (the proposal
+// theta + step (2u - 1) when `in`, else the current state; the same rounded
+// operations as the acceptance's copy) -> amplitude form (sigma [km/s] -> b0
+// [arcsec] = K pi (sigma/c)^2 rad, e -> eps = e/(1 + sqrt(1 - e^2)), as the
+// table conversion) -> derived constants at dst (stride 1, FP64 only).
+__device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *th,
+                                            const double *uw, bool in, int k, double *dst) {
+    double q[7];
+    for (int j = 0; j < 7; ++j) {
+        const int i = 7 * k + j;
+        q[j] = in ? th[i] + mc.step[i] * (2.0 * uw[i] - 1.0) : th[i];
+    }
+    const double c_kms = 299792.458;
+    const double arcsec_per_rad = 648000.0 / M_PI;
+    const double v = q[2] / c_kms;
+    const double b0 = mc.bK * M_PI * v * v * arcsec_per_rad;
+    const double eps = q[3] / (1.0 + sqrt(1.0 - q[3] * q[3]));
+    prologue_values<false>(q[0], q[1], b0, eps, q[4], q[5], q[6], 0, dst, nullptr, 1, mc.status);
+}
+
+// MCMC: the sampler form.  Walker m's free potentials are derived by the wave
+// itself (lanes over the staged potentials), and after the chi^2 the wave
+// takes the Metropolis decision: accept iff the proposal is inside the prior
+// box and (chi2' <= chi2 or -2 ln u_last > chi2' - chi2), copying the
+// proposal into the walker's parameters.
+template <int PREC, bool MCMC = false>
 __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
     extern __shared__ double sh[];  // [2][nimg] unlensed x, y; then the staged potentials
     double *sx = sh, *sy = sh + a.nimg;
@@ -113,8 +140,27 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
     const int lane = threadIdx.x;
     const int pad = a.nimg_pad, st = a.freet.stride, nf = a.freet.n;
     for (int m = a.sample0 + blockIdx.x; m < a.n_samples; m += gridDim.x) {
-        const int k0 = __builtin_amdgcn_readfirstlane(min(max(a.free_off[m], 0), nf));
-        const int k1 = __builtin_amdgcn_readfirstlane(min(max(a.free_off[m + 1], k0), nf));
+        int k0, k1;
+        bool in = false;
+        const int P = 7 * a.mc.nfree;
+        const double *th = nullptr, *uw = nullptr;
+        if (MCMC) {
+            th = a.mc.params + (size_t)m * P;
+            uw = a.mc.u + (size_t)m * (P + 1);
+            k0 = 0;
+            k1 = a.mc.nfree;
+            if (a.mc.mode == 2) {
+                int out = 0;
+                for (int i = lane; i < P; i += 64) {
+                    const double v = th[i] + a.mc.step[i] * (2.0 * uw[i] - 1.0);
+                    if (!(v >= a.mc.lo[i] && v <= a.mc.hi[i])) out = 1;
+                }
+                in = __ballot(out) == 0;
+            }
+        } else {
+            k0 = __builtin_amdgcn_readfirstlane(min(max(a.free_off[m], 0), nf));
+            k1 = __builtin_amdgcn_readfirstlane(min(max(a.free_off[m + 1], k0), nf));
+        }
         for (int g0 = 0; g0 < a.nimg; g0 += 64 * SRC_IPL) {
             double x[SRC_IPL], y[SRC_IPL], acc[SRC_IPL][5];
 #pragma unroll
@@ -130,11 +176,15 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
             for (int kc = k0; kc < k1; kc += a.chunk) {
                 const int cnt = min(a.chunk, k1 - kc);
                 __syncthreads();
-                for (int e = lane; e < cnt * NDER; e += 64) {
-                    const int ci = e / cnt, kk = e - ci * cnt;
-                    pd[kk * NDER + ci] = a.freet.d[(size_t)ci * st + kc + kk];
+                if (MCMC) {
+                    if (lane < cnt) mcmc_derive(a.mc, th, uw, in, kc + lane, pd + lane * NDER);
+                } else {
+                    for (int e = lane; e < cnt * NDER; e += 64) {
+                        const int ci = e / cnt, kk = e - ci * cnt;
+                        pd[kk * NDER + ci] = a.freet.d[(size_t)ci * st + kc + kk];
+                    }
                 }
-                if (PREC != 0) {
+                if (PREC != 0 && !MCMC) {
                     for (int e = lane; e < cnt * NDERF; e += 64) {
                         const int ci = e / cnt, kk = e - ci * cnt;
                         pf[kk * NDERF + ci] = a.freet.f[(size_t)ci * st + kc + kk];
@@ -195,7 +245,28 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
             }
         }
         part = wave_sum(part);
-        if (lane == 0 && a.chi2) a.chi2[m] = part;
+        if (MCMC) {
+            // the shuffle tree leaves the total in lane 0: every lane takes
+            // the decision on lane 0's value
+            part = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(part)),
+                                    __builtin_amdgcn_readfirstlane(__double2loint(part)));
+            if (a.mc.mode == 1) {
+                if (lane == 0) a.mc.chi2[m] = part;
+            } else {
+                const double d = part - a.mc.chi2[m];
+                const double ul = uw[P];
+                if (in && (d <= 0.0 || -2.0 * log(ul) > d)) {
+                    for (int i = lane; i < P; i += 64)
+                        a.mc.params[(size_t)m * P + i] = th[i] + a.mc.step[i] * (2.0 * uw[i] - 1.0);
+                    if (lane == 0) {
+                        a.mc.chi2[m] = part;
+                        a.mc.accepted[m] += 1;
+                    }
+                }
+            }
+        } else if (lane == 0 && a.chi2) {
+            a.chi2[m] = part;
+        }
         __syncthreads();  // sx, sy are rewritten by the next sample
         if (!a.persistent) break;
     }
@@ -232,6 +303,19 @@ hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
         hipLaunchKernelGGL(chi2_src_kernel<0>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
     else
         hipLaunchKernelGGL(chi2_src_kernel<1>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_mcmc_chi2(const Chi2SrcLaunch &c0, hipStream_t st) {
+    Chi2SrcLaunch c = c0;
+    if (c.mc.mode != 1 && c.mc.mode != 2) return hipErrorInvalidValue;
+    if (c.n_samples <= 0) return hipSuccess;
+    c.S = make_series();
+    c.prec = 0;
+    c.chunk = src_chunk(c.nimg, 0);
+    const size_t shmem = 2 * (size_t)c.nimg * sizeof(double) + (size_t)c.chunk * NDER * sizeof(double);
+    if (shmem > 65536) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((chi2_src_kernel<0, true>), dim3(c.grid_blocks), dim3(64), shmem, st, c);
     return hipGetLastError();
 }
 

@@ -7,6 +7,22 @@
 
 namespace lens {
 
+// A Metropolis step fused into the source-plane chi^2 (one wave per walker):
+// walker m's free potentials are its 7 nfree physical parameters (x0, y0,
+// sigma, e, phi, rcore, rcut per potential), converted and run through the
+// parameter prologue by the wave itself.
+struct McmcFused {
+    int mode = 0;                   // 1: chi^2 of the current state; 2: one step
+    int nfree = 0;
+    double *params = nullptr;       // [W][7 nfree], updated on acceptance
+    double *chi2 = nullptr;         // [W] chi^2 of the current state
+    int *accepted = nullptr;        // [W] accepted moves
+    const double *lo = nullptr, *hi = nullptr, *step = nullptr;  // [7 nfree]
+    const double *u = nullptr;      // [W][7 nfree + 1] uniforms of this step
+    double bK = 6.0;                // sigma -> b0: 6 (dPIE) or 4 (SIS) times pi (sigma/c)^2
+    int *status = nullptr;          // status word (invalid parameters)
+};
+
 // Source-plane chi^2
 struct Chi2SrcLaunch {
     Derived freet;            // derived free potentials of all samples
@@ -26,9 +42,12 @@ struct Chi2SrcLaunch {
     int prec;
     int chunk;                // potentials per LDS stage (set by the launch wrapper)
     Series S;                 // filled by the launch wrapper
+    McmcFused mc;             // the sampler's step (mode 0: a plain chi^2 batch)
 };
 hipError_t launch_chi2_prep(const Chi2SrcLaunch &c, hipStream_t st);
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c, hipStream_t st);
+// The sampler's chi^2 (FP64, persistent): c.mc.mode 1 or 2.
+hipError_t launch_mcmc_chi2(const Chi2SrcLaunch &c, hipStream_t st);
 
 // Image plane
 // Image search: n_grids deflection grids (grid g at alpha + g*2*nv: x plane

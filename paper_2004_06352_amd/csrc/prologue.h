@@ -9,9 +9,10 @@
 namespace lens {
 
 // Amplitude-form parameters of potential k -> its derived constants (FP64
-// block and FP32 copy, entry k of tables with the given stride).  Invalid
-// entries get NaN prefactors (their contribution is NaN) and raise
-// ST_INVALID_TABLE.
+// block and, with F32, its FP32 copy; entry k of tables with the given
+// stride).  Invalid entries get NaN prefactors (their contribution is NaN) and
+// raise ST_INVALID_TABLE.
+template <bool F32 = true>
 __device__ __forceinline__ void prologue_values(double x0, double y0, double b0, double eps,
                                                 double phi, double a, double s, int k,
                                                 double *__restrict__ dd, float *__restrict__ df,
@@ -70,6 +71,7 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_PF] = PF;
     v[D_KIND] = __longlong_as_double((long long)kind);  // bit pattern, low word = kind
     for (int i = 0; i < NDER; ++i) dd[(size_t)i * stride + k] = v[i];
+    if (!F32) return;
     const double fv[NDERF] = {v[D_HC2],  v[D_HS2],   v[D_HCS],    v[D_HCMS], q2,
                               v[D_CA],   v[D_CS_],   Sa,          Ss,        v[D_Q2SA],
                               v[D_Q2SS], k1,         v[D_K2],
