@@ -145,6 +145,28 @@ def cpu_baseline_map(c, budget_s=12.0):
                        f"5 channels, {dt:.1f} s")
 
 
+def cpu_baseline_chi2(c3, budget_s=4.0):
+    """The oracle's source-plane chi^2 (OpenMP over samples) on a prefix of the
+    same batch, grown until it takes about budget_s."""
+    from oracle import oracle as O
+    fixed, free = O.phys_to_pots(c3["fixed"]), O.phys_to_pots(c3["free"])
+    cat = O.catalog_f(c3["catalog"], c3["zl"])
+    off_all = np.asarray(c3["free_off"])
+    total = len(off_all) - 1
+    n = 64
+    while True:
+        off = off_all[:n + 1]
+        t0 = time.perf_counter()
+        O.chi2_source(fixed, free, off, cat)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or n >= total:
+            break
+        n = min(total, max(2 * n, int(n * budget_s / max(dt, 1e-3) * 1.1)))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=n / dt, unit="samples/s", cores=threads, kind="oracle",
+                sample=f"{n} of the {total} samples, {dt:.1f} s")
+
+
 def bench_serving(map_rate, chi2_rate, n_requests):
     """Poisson stream of mixed map / chi^2 requests at 0.7x the single-stream
     capacity estimated from the measured map and chi^2 rates; served with 4
@@ -311,8 +333,10 @@ def main():
             secondary[f"chi2_source_{name}_samples_per_s"] = S * 50 / w
             plan.close()
         secondary["chi2_source_workload"] = c3["name"]
-        # Metropolis sampler: 4096 walkers of the same model, one graph launch
-        # per step (proposal, batched chi^2, acceptance); uniforms supplied
+        if not args.no_cpu:
+            secondary["chi2_source_cpu_baseline"] = cpu_baseline_chi2(c3)
+        # Metropolis sampler: 4096 walkers of the same model, one kernel launch
+        # per step (proposal, chi^2 and decision per wave); uniforms supplied
         # once and reused (filling them is the caller's generator's cost)
         sm = inputs.sampler_start(n_walkers=4096)
         Wn = sm["params"].shape[0]
