@@ -24,20 +24,33 @@ namespace lens {
 
 // ln D for D > 0: D = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s),
 // s = (m - 1)/(m + 1) (|s| <= 3 - 2 sqrt 2), by the atanh polynomial of eval.h.
-__device__ __forceinline__ double log_pos(double D, const Series &S) {
-    double m = __builtin_amdgcn_frexp_mant(D);  // [0.5, 1)
-    int e = __builtin_amdgcn_frexp_exp(D);
-    if (m < 0.7071067811865476) {
-        m = 2.0 * m;
-        e -= 1;
+// Split in two so that the reciprocal of m + 1 can be shared with others.
+struct LogRed {
+    double m;  // mantissa in [sqrt(1/2), sqrt(2))
+    int e;
+};
+__device__ __forceinline__ LogRed log_reduce(double D) {
+    LogRed r;
+    r.m = __builtin_amdgcn_frexp_mant(D);  // [0.5, 1)
+    r.e = __builtin_amdgcn_frexp_exp(D);
+    if (r.m < 0.7071067811865476) {
+        r.m = 2.0 * r.m;
+        r.e -= 1;
     }
-    const double s = (m - 1.0) * rcp64(m + 1.0);
+    return r;
+}
+__device__ __forceinline__ double log_finish(const LogRed &r, double inv_m1, const Series &S) {
+    const double s = (r.m - 1.0) * inv_m1;
     const double s2 = s * s;
     double p = S.ah[0];
 #pragma unroll
     for (int i = 1; i < LENS_ATANH_N; ++i) p = fma(p, s2, S.ah[i]);
     const double t = fma(s * s2, p, s);
-    return fma(kLn2, (double)e, 2.0 * t);
+    return fma(kLn2, (double)r.e, 2.0 * t);
+}
+__device__ __forceinline__ double log_pos(double D, const Series &S) {
+    const LogRed r = log_reduce(D);
+    return log_finish(r, rcp64(r.m + 1.0), S);
 }
 
 // Potential of one potential at (x, y), Dls/Ds = 1.
@@ -64,14 +77,21 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
         const double sum = pa + ps;
         if (kind & K_ELL) {
             const double k = c[D_K], k2x2 = c[D_K2] * x2;
-            const double g = c[D_DC] * rcp64(sum);
             const double B1 = pa + c[D_Q2SA], B2 = ps + c[D_Q2SS];
-            const double Nx = k * xp * (g + c[D_DS]);
             const double Dx = fma(A1, A2, k2x2);
-            const double Ny = k * yp * (g + c[D_Q2DS]);
             const double Dy = fma(B1, B2, -c[D_K2] * y2);
+            // the log terms' mantissas, then one reciprocal (a quarter-rate
+            // instruction) for 1/sum, 1/(Dx Dy) and the two 1/(m + 1)
+            const LogRed lra = log_reduce(fma(A1, A1, k2x2)), lrs = log_reduce(fma(A2, A2, k2x2));
+            const double DXY = Dx * Dy, P1 = sum * DXY;
+            const double ma1 = lra.m + 1.0, ms1 = lrs.m + 1.0, M = ma1 * ms1;
+            const double R = rcp64(P1 * M);
+            const double RM = R * M, RP = R * P1;  // 1/P1, 1/M
+            const double g = c[D_DC] * (RM * DXY);
+            const double Nx = k * xp * (g + c[D_DS]);
+            const double Ny = k * yp * (g + c[D_Q2DS]);
             // the deflection's fast path (small ratios on the whole wave)
-            const double R2f = rcp64(Dx * Dy);
+            const double R2f = RM * sum;
             const double bf = Nx * (R2f * Dy), sf = Ny * (R2f * Dx);
             double ax, ay;
             if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
@@ -84,7 +104,7 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
                 ax = c[D_PF] * atan_finish(ra_, ra_.num * (R2 * rh.den), S);
                 ay = c[D_PF] * atanh_finish(rh, rh.num * (R2 * ra_.den), S);
             }
-            const double la = log_pos(fma(A1, A1, k2x2), S), ls = log_pos(fma(A2, A2, k2x2), S);
+            const double la = log_finish(lra, RP * ms1, S), ls = log_finish(lrs, RP * ma1, S);
             const double L = 0.5 * (c[D_PF] * k) * (c[D_SA] * la - c[D_SS] * ls);
             v = fma(xp, ax, yp * ay) - L;
         } else {
