@@ -339,11 +339,15 @@ int batched_blocks(const lens_ctx_t *ctx, int S) {
 }
 
 // Which parts of the source-plane sequence to issue: everything; only what
-// depends on the fixed potentials and the catalogue (their prologue and the
-// per-image constants); only what depends on the free potentials (their
-// prologue and the per-sample kernel, the per-image constants being ready);
-// or only the per-sample kernel (the free derived table written elsewhere).
-enum SrcParts { SRC_ALL, SRC_FIXED_ONLY, SRC_FREE_ONLY, SRC_SAMPLES_ONLY };
+// depends on the fixed potentials and the catalogue (the per-image
+// constants); only what depends on the free potentials (their prologue and
+// the per-sample kernel, the per-image constants being ready); only the
+// per-sample kernel (the free derived table written elsewhere); or
+// everything and the fixed potentials' derived table too (for callers that
+// evaluate the fixed potentials again, the image plane).  Without the last,
+// the fixed potentials' constants are formed inside the per-image launch and
+// no table of them is written.
+enum SrcParts { SRC_ALL, SRC_FIXED_ONLY, SRC_FREE_ONLY, SRC_SAMPLES_ONLY, SRC_ALL_TABLES };
 
 // Prologues, fixed deflection at the constraints, then the per-sample kernel.
 lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
@@ -354,16 +358,13 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
     const Derived DF = derived_in(base, p.o_fix, b->fixed.n);
     const Derived DV = derived_in(base, p.o_free, b->free.n);
     if (with_check) TRY(status_reset(ctx, st));
-    if (parts == SRC_ALL)
+    if (parts == SRC_ALL_TABLES)
         HIP_TRY(launch_prologue2(soa(&b->fixed), b->fixed.n, const_cast<double *>(DF.d),
                                  const_cast<float *>(DF.f), DF.stride, soa(&b->free), b->free.n,
                                  const_cast<double *>(DV.d), const_cast<float *>(DV.f),
                                  DV.stride, ctx->small, st));
-    else if (parts == SRC_FIXED_ONLY)
-        TRY(run_prologue(ctx, &b->fixed, DF, st));
     else if (parts == SRC_FREE_ONLY)
         TRY(run_prologue(ctx, &b->free, DV, st));
-    if (with_check) TRY(status_check(ctx, st));
     Chi2SrcLaunch L;
     L.freet = DV;
     L.free_off = b->free_offset;
@@ -384,7 +385,17 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
     L.src_y = sources ? L.src_x + (size_t)b->n_samples * c->n_sys : nullptr;
     const bool batched = path == LENS_CHI2_PATH_BATCHED;
     L.prec = prec == LENS_FP64 ? 0 : 1;
-    if (parts == SRC_ALL || parts == SRC_FIXED_ONLY) HIP_TRY(launch_chi2_prep(L, st));
+    if (parts == SRC_ALL || parts == SRC_FIXED_ONLY) {
+        L.inline_fixed = 1;
+        L.free_prologue = parts == SRC_ALL ? 1 : 0;
+        L.nfixed = b->fixed.n;
+        L.fixed_amp = soa(&b->fixed);
+        L.free_amp = soa(&b->free);
+        L.status = ctx->small;
+    }
+    if (parts == SRC_ALL || parts == SRC_FIXED_ONLY || parts == SRC_ALL_TABLES)
+        HIP_TRY(launch_chi2_prep(L, st));
+    if (with_check) TRY(status_check(ctx, st));
     if (parts == SRC_FIXED_ONLY || b->n_samples == 0) return LENS_OK;
     if (batched) {
         L.persistent = 1;
@@ -676,7 +687,8 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
     TRY(ensure_scratch(ctx, cv.off));
     TRY(check_contents(ctx, b, c, st));
     HIP_TRY(launch_zero_i32(ctx->small + 2, 1, st));  // overflow word
-    TRY(src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr, true, st, true));
+    TRY(src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr, true, st, true,
+                     SRC_ALL_TABLES));
     const double *srcx = (const double *)sc(ctx, sp.o_src);
     const double *srcy = srcx + (size_t)S * c->n_sys;
     double *afx = (double *)sc(ctx, o_afix), *afy = afx + nv;

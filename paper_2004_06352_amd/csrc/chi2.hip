@@ -55,20 +55,50 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int PREP_OFF_MAX = 4097;
 constexpr int PREP_BLOCK = 256;
 
-template <int PREC>
+// INLINE: the fixed potentials' derived constants are not read from a table
+// but formed by each thread from the amplitude table (the table prologue's
+// arithmetic, into registers), so no prologue launch of the fixed table
+// precedes this one; blocks beyond the images then run the free table's
+// prologue, which the per-sample kernel reads.  One launch instead of two.
+template <int PREC, bool INLINE = false>
 __global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) {
     __shared__ int s_off[PREP_OFF_MAX];
     __shared__ double s_red[2][PREP_BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int t = blockIdx.x;
+    if (INLINE && t >= a.nimg) {
+        const int k = (t - a.nimg) * PREP_BLOCK + tid;
+        if (k < a.freet.n) {
+            const PotSoA &F = a.free_amp;
+            prologue_values(F.x0[k], F.y0[k], F.b0[k], F.eps[k], F.phi[k], F.rcore[k], F.rcut[k],
+                            k, const_cast<double *>(a.freet.d), const_cast<float *>(a.freet.f),
+                            a.freet.stride, a.status);
+        }
+        return;  // uniform per block
+    }
     const bool staged = a.nsys + 1 <= PREP_OFF_MAX;
     if (staged)
         for (int i = tid; i <= a.nsys; i += PREP_BLOCK) s_off[i] = a.img_off[i];
     double acc[5] = {0, 0, 0, 0, 0};
     const double x = a.x[t], y = a.y[t];
     const int st = a.fixedt.stride;
-    for (int k = tid; k < a.fixedt.n; k += PREP_BLOCK) {
-        if (PREC == 0) {
+    const int nfix = INLINE ? a.nfixed : a.fixedt.n;
+    for (int k = tid; k < nfix; k += PREP_BLOCK) {
+        if (INLINE) {
+            double v[NDER];
+            float vf[NDERF];
+            const PotSoA &T = a.fixed_amp;
+            prologue_values<PREC != 0>(T.x0[k], T.y0[k], T.b0[k], T.eps[k], T.phi[k], T.rcore[k],
+                                       T.rcut[k], 0, v, vf, 1, a.status);
+            if (PREC == 0) {
+                eval_pot_f64<true, false, false>(ConstD{v, 1}, x, y, acc, a.S);
+            } else {
+                float o[5];
+                eval_pot_f32<true, false, false>(ConstD{v, 1}, ConstF{vf, 1}, x, y, o, a.S);
+                acc[0] += (double)o[0];
+                acc[1] += (double)o[1];
+            }
+        } else if (PREC == 0) {
             eval_pot_f64<true, false, false>(ConstD{a.fixedt.d + k, st}, x, y, acc, a.S);
         } else {
             float o[5];
@@ -281,9 +311,24 @@ static int src_chunk(int nimg, int prec) {
 }
 
 hipError_t launch_chi2_prep(const Chi2SrcLaunch &c0, hipStream_t st) {
-    if (c0.nimg <= 0) return hipSuccess;
     Chi2SrcLaunch c = c0;
     c.S = make_series();
+    if (c.inline_fixed) {
+        const long long free_blocks =
+            c.free_prologue ? ((long long)c.freet.n + PREP_BLOCK - 1) / PREP_BLOCK : 0;
+        const long long blocks = (long long)std::max(c.nimg, 0) + free_blocks;
+        if (blocks == 0) return hipSuccess;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        if (!c.free_prologue) c.freet.n = 0;
+        if (c.prec == 0)
+            hipLaunchKernelGGL((chi2_prep_kernel<0, true>), dim3((unsigned)blocks), dim3(PREP_BLOCK),
+                               0, st, c);
+        else
+            hipLaunchKernelGGL((chi2_prep_kernel<1, true>), dim3((unsigned)blocks), dim3(PREP_BLOCK),
+                               0, st, c);
+        return hipGetLastError();
+    }
+    if (c0.nimg <= 0) return hipSuccess;
     if (c.prec == 0)
         hipLaunchKernelGGL(chi2_prep_kernel<0>, dim3(c.nimg), dim3(PREP_BLOCK), 0, st, c);
     else

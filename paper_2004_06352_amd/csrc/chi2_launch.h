@@ -43,6 +43,13 @@ struct Chi2SrcLaunch {
     int chunk;                // potentials per LDS stage (set by the launch wrapper)
     Series S;                 // filled by the launch wrapper
     McmcFused mc;             // the sampler's step (mode 0: a plain chi^2 batch)
+    // prep with inline fixed prologue (inline_fixed = 1): the fixed potentials'
+    // amplitude table (nfixed entries) instead of fixedt, and with
+    // free_prologue = 1 the free table's prologue (free_amp -> freet) in the
+    // same launch; status receives ST_INVALID_TABLE
+    int inline_fixed = 0, free_prologue = 0, nfixed = 0;
+    PotSoA fixed_amp = {}, free_amp = {};
+    int *status = nullptr;
 };
 hipError_t launch_chi2_prep(const Chi2SrcLaunch &c, hipStream_t st);
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c, hipStream_t st);
