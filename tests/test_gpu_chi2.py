@@ -217,3 +217,33 @@ def test_invalid_catalogue_rejected(B, ctx):
     badoff[-1] += 1
     with pytest.raises(B.LensError):
         B.chi2_batch(fixed, free, badoff, cat, ctx=ctx)
+
+
+@pytest.mark.parametrize("which", ["fixed", "free"])
+def test_invalid_potentials_rejected_in_both_planes(B, ctx, which):
+    """An invalid entry (eps >= 1) in the fixed or the free table is reported
+    as LENS_EINVAL by a checked context, in the source plane (whose per-image
+    launch forms the fixed constants itself) and in the image plane, and the
+    chi^2 output is left untouched."""
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=3)
+    fixed, free, off = device_model(B, ctx, c)
+    cat = gpu_catalog(B, c)
+    t = dict(fixed if which == "fixed" else free)
+    t["eps"] = t["eps"].clone()
+    t["eps"][1] = 1.5
+    fx, fr = (t, free) if which == "fixed" else (fixed, t)
+    import ctypes as C
+    out = torch.full((3,), -7.0, dtype=torch.float64, device="cuda")
+    bt, kt = B._batch(fx, fr, off), B._catalog(cat)
+    ot = B._opts(B.CHI2_SOURCE, B.FP64, B.PATH_BATCHED, None, 16, 0.0)
+    st = B.lib().lens_chi2_batch(ctx.handle, C.byref(bt), C.byref(kt), C.byref(ot), B._ptr(out),
+                                 None, None, None, B._stream(out.device))
+    torch.cuda.synchronize()
+    assert B.STATUS.get(st) == "LENS_EINVAL"
+    assert "invalid" in B.lib().lens_last_error().decode()
+    assert torch.all(out == -7.0)
+    grid = inputs.pixel_centre_grid(64, -75.0, 75.0)
+    with pytest.raises(B.LensError, match="invalid"):
+        B.chi2_batch(fx, fr, off, cat, mode=B.CHI2_IMAGE, grid=grid, kmax=8, penalty=1.0,
+                     ctx=ctx)
