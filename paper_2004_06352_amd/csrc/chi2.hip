@@ -568,6 +568,7 @@ __global__ void __launch_bounds__(RF_THREADS) refine_images_kernel(RefineLaunch 
             for (int w = 1; w < RF_WAVES; ++w) v += red[w][c][lane];
             h[c] = v;
         }
+        hess_of_parts(h[2], h[3], h[4], &h[2]);
         if (state == 0) {
             const double rx = bx - (x - f * h[0]);
             const double ry = by - (y - f * h[1]);

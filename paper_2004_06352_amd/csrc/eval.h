@@ -176,7 +176,8 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
     const double yp = fma(dy, cp, -(dx * sp));
     const double x2 = xp * xp, y2 = yp * yp;
     const double R = fma(c[D_Q2], x2, y2);
-    double ax = 0.0, ay = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
+    // htr, hdf: psi_xx + psi_yy and psi_xx - psi_yy; hxy holds -psi_xy
+    double ax = 0.0, ay = 0.0, htr = 0.0, hdf = 0.0, hxy = 0.0;
     if (kind & K_CUT) {
         const double ta = c[D_CA] + R, ts = c[D_CS_] + R;
         const double ra = rsq64(ta), rs = rsq64(ts);
@@ -252,13 +253,12 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
             }
         }
         if (HESS) {
-            // per core: C_w + S_w psi_w = S_w B_w and S_w^2 + S_w psi_w = S_w A_w
+            // trace r_a - r_s; difference and -psi_xy from h_w = 1/(psi_w D_w)
             const double ha = ra * iDa, hs = rs * iDs;
             const double dh = ha - hs;
-            const double wa = ha * c[D_SA], ws = hs * c[D_SS];
-            hxx = fma(y2, dh, fma(wa, B1, -(ws * B2)));
-            hyy = fma(x2, dh, fma(wa, A1, -(ws * A2)));
-            hxy = -(xp * yp) * dh;
+            htr = ra - rs;
+            hdf = fma(y2 - x2, dh, fma(ha, c[D_EA], -(hs * c[D_ES])));
+            hxy = (xp * yp) * dh;
         }
     } else {
         const double ta = c[D_CA] + R;
@@ -294,15 +294,14 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         }
         if (HESS) {
             const double ha = ra * iDa;
-            const double wa = ha * c[D_SA];
-            hxx = fma(ha, y2, wa * B1);
-            hyy = fma(ha, x2, wa * A1);
-            hxy = -xp * yp * ha;
+            htr = ra;
+            hdf = ha * ((y2 - x2) + c[D_EA]);
+            hxy = (xp * yp) * ha;
         }
     }
-    if (SING && zero) ax = ay = hxx = hxy = hyy = 0.0;
+    if (SING && zero) ax = ay = htr = hdf = hxy = 0.0;
     // rotate back and accumulate, the prefactors folded into the rotation
-    // constants (ax, ay, hxx, hxy, hyy above carry no PF or HF)
+    // constants (ax, ay, htr, hdf, hxy above carry no PF or HF)
     if (GRAD) {
         const double pfc = c[D_PFC], pfs = c[D_PFS];
         acc[0] = fma(pfc, ax, acc[0]);
@@ -311,17 +310,13 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         acc[1] = fma(pfc, ay, acc[1]);
     }
     if (HESS) {
-        const double c2 = c[D_HC2], s2 = c[D_HS2], cs = c[D_HCS], cs2 = c[D_HCS2];
-        const double cms = c[D_HCMS];
-        acc[2] = fma(c2, hxx, acc[2]);
-        acc[2] = fma(s2, hyy, acc[2]);
-        acc[2] = fma(-cs2, hxy, acc[2]);
-        acc[3] = fma(cs, hxx, acc[3]);
-        acc[3] = fma(-cs, hyy, acc[3]);
-        acc[3] = fma(cms, hxy, acc[3]);
-        acc[4] = fma(s2, hxx, acc[4]);
-        acc[4] = fma(c2, hyy, acc[4]);
-        acc[4] = fma(cs2, hxy, acc[4]);
+        // rotating by phi leaves the trace and turns (difference/2, psi_xy)
+        // by 2 phi: acc[2] = T, acc[3] = U, acc[4] = V
+        acc[2] = fma(c[D_HT], htr, acc[2]);
+        acc[3] = fma(c[D_HCMH], hdf, acc[3]);
+        acc[3] = fma(c[D_HCS2], hxy, acc[3]);
+        acc[4] = fma(c[D_HCS], hdf, acc[4]);
+        acc[4] = fma(-c[D_HCMS], hxy, acc[4]);
     }
 }
 
@@ -423,7 +418,7 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
     const float yp = (float)fma(dy, cpd, -(dx * spd));
     const float x2 = xp * xp, y2 = yp * yp;
     const float R = fmaf(f[F_Q2], x2, y2);
-    float ax = 0.f, ay = 0.f, hxx = 0.f, hxy = 0.f, hyy = 0.f;
+    float ax = 0.f, ay = 0.f, htr = 0.f, hdf = 0.f, hxy = 0.f;  // as in the FP64 form
     if (kind & K_CUT) {
         const float ta = f[F_CA] + R, ts = f[F_CS_] + R;
         const float ra = frsq(ta), rs = frsq(ts);
@@ -484,13 +479,11 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
             }
         }
         if (HESS) {
-            // per core: C_w + S_w psi_w = S_w B_w and S_w^2 + S_w psi_w = S_w A_w
             const float ha = ra * iDa, hs = rs * iDs;
             const float dh = ha - hs;
-            const float wa = ha * f[F_SA], ws = hs * f[F_SS];
-            hxx = fmaf(y2, dh, fmaf(wa, B1, -(ws * B2)));
-            hyy = fmaf(x2, dh, fmaf(wa, A1, -(ws * A2)));
-            hxy = -xp * yp * dh;
+            htr = ra - rs;
+            hdf = fmaf(y2 - x2, dh, fmaf(ha, f[F_EA], -(hs * f[F_ES])));
+            hxy = (xp * yp) * dh;
         }
     } else {
         const float ta = f[F_CA] + R;
@@ -518,13 +511,12 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
         }
         if (HESS) {
             const float ha = ra * iDa;
-            const float wa = ha * f[F_SA];
-            hxx = fmaf(ha, y2, wa * B1);
-            hyy = fmaf(ha, x2, wa * A1);
-            hxy = -xp * yp * ha;
+            htr = ra;
+            hdf = ha * ((y2 - x2) + f[F_EA]);
+            hxy = (xp * yp) * ha;
         }
     }
-    if (SING && zero) ax = ay = hxx = hxy = hyy = 0.f;
+    if (SING && zero) ax = ay = htr = hdf = hxy = 0.f;
     // rotate back, the prefactors folded into the rotation constants
     if (GRAD) {
         const float pfc = f[F_PFC], pfs = f[F_PFS];
@@ -532,11 +524,10 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
         out[1] = fmaf(pfs, ax, pfc * ay);
     }
     if (HESS) {
-        const float c2 = f[F_HC2], s2 = f[F_HS2], cs = f[F_HCS], cms = f[F_HCMS];
-        const float t = 2.0f * cs * hxy;
-        out[2] = fmaf(c2, hxx, fmaf(s2, hyy, -t));
-        out[3] = fmaf(cs, hxx - hyy, cms * hxy);
-        out[4] = fmaf(s2, hxx, fmaf(c2, hyy, t));
+        // out[2..4] = this potential's T, U, V
+        out[2] = f[F_HT] * htr;
+        out[3] = fmaf(f[F_HCMH], hdf, f[F_HCS2] * hxy);
+        out[4] = fmaf(f[F_HCS], hdf, -(f[F_HCMS] * hxy));
     }
 }
 
@@ -556,6 +547,14 @@ __device__ __forceinline__ void neumaier_add(float &s, float &c, float v) {
     const float t = s + v;
     c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
     s = t;
+}
+
+// Second derivatives from the accumulated parts: psi_xx = T + U,
+// psi_xy = V, psi_yy = T - U.
+__device__ __forceinline__ void hess_of_parts(double T, double U, double V, double h[3]) {
+    h[0] = T + U;
+    h[1] = V;
+    h[2] = T - U;
 }
 
 }  // namespace lens

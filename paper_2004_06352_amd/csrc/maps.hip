@@ -259,6 +259,16 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
     }
 
     if (j >= a.g.ny) return;
+    // summed values per channel: deflection, then psi_xx, psi_xy, psi_yy from
+    // the accumulated trace, difference and off-diagonal parts
+    double tot[PPT][5];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+#pragma unroll
+        for (int ch = 0; ch < 5; ++ch)
+            tot[p][ch] = PREC == 2 ? (double)fs[p][ch] + (double)fc[p][ch] : acc[p][ch];
+        if (HESS) hess_of_parts(tot[p][2], tot[p][3], tot[p][4], &tot[p][2]);
+    }
     if (HESS && a.derived) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
@@ -267,9 +277,7 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
             const size_t idx = (size_t)j * a.g.nx + i;
             double h[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                h[c] = a.dlsds * (PREC == 2 ? (double)fs[p][2 + c] + (double)fc[p][2 + c]
-                                            : acc[p][2 + c]);
+            for (int c = 0; c < 3; ++c) h[c] = a.dlsds * tot[p][2 + c];
             double v[6];
             derived_of(h[0], h[1], h[2], v);
 #pragma unroll
@@ -291,14 +299,10 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
 #pragma unroll
         for (int ch = 0; ch < 5; ++ch) {
             if (a.out[ch] == nullptr) continue;
-            if (PREC == 0) {
-                static_cast<double *>(a.out[ch])[idx] = a.dlsds * acc[p][ch];
-            } else if (PREC == 1) {
-                static_cast<float *>(a.out[ch])[idx] = (float)(a.dlsds * acc[p][ch]);
-            } else {
-                static_cast<float *>(a.out[ch])[idx] =
-                    (float)(a.dlsds * ((double)fs[p][ch] + (double)fc[p][ch]));
-            }
+            if (PREC == 0)
+                static_cast<double *>(a.out[ch])[idx] = a.dlsds * tot[p][ch];
+            else
+                static_cast<float *>(a.out[ch])[idx] = (float)(a.dlsds * tot[p][ch]);
         }
     }
 }

@@ -51,11 +51,11 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_S] = sn;
     v[D_PFC] = PF * c;
     v[D_PFS] = PF * sn;
-    v[D_HC2] = HF * (c * c);
-    v[D_HS2] = HF * (sn * sn);
+    v[D_HT] = 0.5 * HF;
+    v[D_HCMS] = HF * (c * c - sn * sn);
+    v[D_HCMH] = 0.5 * v[D_HCMS];
     v[D_HCS] = HF * (c * sn);
     v[D_HCS2] = 2.0 * v[D_HCS];
-    v[D_HCMS] = HF * (c * c - sn * sn);
     v[D_Q2] = q2;
     v[D_CA] = q2 * Sa * Sa;
     v[D_CS_] = q2 * Ss * Ss;
@@ -69,13 +69,16 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_DS] = DS;
     v[D_Q2DS] = q2 * DS;
     v[D_PF] = PF;
+    v[D_EA] = Sa * (q2 * Sa - Sa);
+    v[D_ES] = Ss * (q2 * Ss - Ss);
     v[D_KIND] = __longlong_as_double((long long)kind);  // bit pattern, low word = kind
     for (int i = 0; i < NDER; ++i) dd[(size_t)i * stride + k] = v[i];
     if (!F32) return;
-    const double fv[NDERF] = {v[D_HC2],  v[D_HS2],   v[D_HCS],    v[D_HCMS], q2,
-                              v[D_CA],   v[D_CS_],   Sa,          Ss,        v[D_Q2SA],
-                              v[D_Q2SS], k1,         v[D_K2],
-                              DC,        DS,         v[D_Q2DS],   v[D_PFC],  v[D_PFS]};
+    const double fv[NDERF] = {v[D_HT],   v[D_HCMH],  v[D_HCS],    v[D_HCS2], v[D_HCMS],
+                              q2,        v[D_CA],    v[D_CS_],    Sa,        Ss,
+                              v[D_Q2SA], v[D_Q2SS],  k1,          v[D_K2],   DC,
+                              DS,        v[D_Q2DS],  v[D_PFC],    v[D_PFS],  v[D_EA],
+                              v[D_ES]};
     for (int i = 0; i < NDERF; ++i) df[(size_t)i * stride + k] = (float)fv[i];
 }
 
