@@ -175,70 +175,80 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
     const double xp = fma(dx, cp, dy * sp);
     const double yp = fma(dy, cp, -(dx * sp));
     const double x2 = xp * xp, y2 = yp * yp;
-    const double R = fma(c[D_Q2], x2, y2);
     // htr, hdf: psi_xx + psi_yy and psi_xx - psi_yy; hxy holds -psi_xy
     double ax = 0.0, ay = 0.0, htr = 0.0, hdf = 0.0, hxy = 0.0;
     if (kind & K_CUT) {
-        const double ta = c[D_CA] + R, ts = c[D_CS_] + R;
-        const double ra = rsq64(ta), rs = rsq64(ts);
-        const double pa = ta * ra, ps = ts * rs;
-        const double A1 = pa + c[D_SA], A2 = ps + c[D_SS];
-        const double B1 = pa + c[D_Q2SA], B2 = ps + c[D_Q2SS];
-        const double sum = pa + ps;
-        double inv_sum, iDa = 0.0, iDs = 0.0;
+        // ra, rs: 1/psi_w; iDa, iDs: 1/D_w.  Elliptical potentials work with
+        // every length of the closed form divided by k (psi_w/k, A_w/k, B_w/k):
+        // the ratios k x'/A_w and k y'/B_w lose their k and D_w/k^2 = A_w^2/k^2
+        // + x'^2; the Hessian constants carry the factors k and 1/k^3 this
+        // leaves on the trace and on the other parts.
+        double ra, rs, iDa = 0.0, iDs = 0.0;
         if (kind & K_ELL) {
-            const double k2x2 = c[D_K2] * x2;
-            // One reciprocal (a quarter-rate instruction) serves every quotient:
-            // the cores' sum (for psi_s - psi_a), the Hessian denominators D_a,
-            // D_s and the deflection ratios' denominators Dx, Dy.
-            const double Dx = fma(A1, A2, k2x2);
-            const double Dy = fma(B1, B2, -c[D_K2] * y2);
-            const double XG = GRAD ? Dx * Dy : 1.0;
-            double Da = 0.0, Ds = 0.0, DD = 1.0;
+            const double R = fma(c[D_EQ2], x2, c[D_EK2I] * y2);
+            const double ta = c[D_ECA] + R, ts = c[D_ECS] + R;
+            ra = rsq64(ta);
+            rs = rsq64(ts);
+            const double pa = ta * ra, ps = ts * rs;
+            const double A1 = pa + c[D_ESA], A2 = ps + c[D_ESS];
+            // one reciprocal (a quarter-rate instruction) of D_a D_s Dx Dy
+            // serves the Hessian denominators and the ratios' denominators
+            // Dx = A_a A_s + x'^2 and Dy = B_a B_s - y'^2 (the two cores'
+            // arctangents and hyperbolic arctangents subtracted in closed form)
+            double Da = 1.0, Ds = 1.0, DD = 1.0;
             if (HESS) {
-                Da = fma(A1, A1, k2x2);
-                Ds = fma(A2, A2, k2x2);
+                Da = fma(A1, A1, x2);
+                Ds = fma(A2, A2, x2);
                 DD = Da * Ds;
             }
-            const double XH = HESS ? sum * DD : sum;
-            const double Rall = rcp64(GRAD ? XH * XG : XH);
-            const double R1 = GRAD ? Rall * XG : Rall;  // 1/(sum DD) or 1/sum
-            inv_sum = HESS ? R1 * DD : R1;
-            if (HESS) {
-                const double t = R1 * sum;
-                iDa = t * Ds;
-                iDs = t * Da;
-            }
             if (GRAD) {
-                const double g = c[D_DC] * inv_sum;
-                const double k = c[D_K];
-                const double Nx = k * xp * (g + c[D_DS]);
-                const double Ny = k * yp * (g + c[D_Q2DS]);
-                // Away from the cores both ratios are small (the two cores'
-                // terms nearly cancel): when they are inside the polynomials'
-                // intervals for the whole wave, skip the reductions.  (The
-                // ratios are formed first; the few waves that fail the test
-                // discard them.)
-                const double R2f = Rall * XH;  // 1/(Dx Dy)
-                const double bf = Nx * (R2f * Dy), sf = Ny * (R2f * Dx);
+                const double B1 = pa + c[D_EQ2SA], B2 = ps + c[D_EQ2SS];
+                const double Dx = fma(A1, A2, x2);
+                const double Dy = fma(B1, B2, -y2);
+                const double XG = Dx * Dy;
+                const double Rall = rcp64(HESS ? DD * XG : XG);
+                if (HESS) {
+                    const double t = Rall * XG;  // 1/(D_a D_s)
+                    iDa = t * Ds;
+                    iDs = t * Da;
+                }
+                const double R2 = HESS ? Rall * DD : Rall;  // 1/(Dx Dy)
+                const double Nx = xp * (A2 - A1);
+                const double Ny = yp * (B2 - B1);
+                // Away from the cores both ratios are small: when they are
+                // inside the polynomials' intervals for the whole wave, skip
+                // the reductions.  (The ratios are formed first; the few waves
+                // that fail the test discard them.)
+                const double bf = Nx * (R2 * Dy), sf = Ny * (R2 * Dx);
                 if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
                     ax = atan_poly(bf, S);
                     ay = atanh_poly(sf, S);
                 } else {
                     const AtanRed ra_ = atan_reduce(Nx, Dx);
                     const AtanhRed rh = atanh_reduce(Ny, Dy);
-                    const double R2 = rcp64(ra_.den * rh.den);
-                    const double b = ra_.num * (R2 * rh.den);
-                    const double s = rh.num * (R2 * ra_.den);
+                    const double R3 = rcp64(ra_.den * rh.den);
+                    const double b = ra_.num * (R3 * rh.den);
+                    const double s = rh.num * (R3 * ra_.den);
                     ax = atan_finish(ra_, b, S);
                     ay = atanh_finish(rh, s, S);
                 }
+            } else if (HESS) {
+                const double t = rcp64(DD);
+                iDa = t * Ds;
+                iDs = t * Da;
             }
         } else {
             // circular: k = 0, D_w = A_w^2
+            const double R = fma(c[D_Q2], x2, y2);
+            const double ta = c[D_CA] + R, ts = c[D_CS_] + R;
+            ra = rsq64(ta);
+            rs = rsq64(ts);
+            const double pa = ta * ra, ps = ts * rs;
+            const double A1 = pa + c[D_SA], A2 = ps + c[D_SS];
+            const double sum = pa + ps;
             const double A12 = A1 * A2;
             const double R1 = rcp64(sum * A12);
-            inv_sum = R1 * A12;
+            const double inv_sum = R1 * A12;
             const double i12 = R1 * sum;
             if (HESS) {
                 const double iA1 = i12 * A2, iA2 = i12 * A1;
@@ -261,18 +271,18 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
             hxy = (xp * yp) * dh;
         }
     } else {
-        const double ta = c[D_CA] + R;
-        const double ra = rsq64(ta);
-        const double pa = ta * ra;
-        const double A1 = pa + c[D_SA];
-        const double B1 = pa + c[D_Q2SA];
-        double iDa = 0.0;
+        double ra, iDa = 0.0;
         if (kind & K_ELL) {
-            const double k = c[D_K];
-            const double Da = fma(A1, A1, c[D_K2] * x2);
+            // lengths divided by k as in the two-core form
+            const double ta = c[D_ECA] + fma(c[D_EQ2], x2, c[D_EK2I] * y2);
+            ra = rsq64(ta);
+            const double pa = ta * ra;
+            const double A1 = pa + c[D_ESA];
+            const double B1 = pa + c[D_EQ2SA];
+            const double Da = fma(A1, A1, x2);
             if (GRAD) {
-                const AtanRed ra_ = atan_reduce(k * xp, A1);
-                const AtanhRed rh = atanh_reduce(k * yp, B1);
+                const AtanRed ra_ = atan_reduce(xp, A1);
+                const AtanhRed rh = atanh_reduce(yp, B1);
                 const double den = ra_.den * rh.den;
                 const double R2 = rcp64(HESS ? den * Da : den);
                 const double RD = HESS ? R2 * Da : R2;
@@ -285,7 +295,9 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
                 iDa = rcp64(Da);
             }
         } else {
-            const double iA1 = rcp64(A1);
+            const double ta = c[D_CA] + fma(c[D_Q2], x2, y2);
+            ra = rsq64(ta);
+            const double iA1 = rcp64(ta * ra + c[D_SA]);
             if (GRAD) {
                 ax = iA1 * xp;
                 ay = iA1 * yp;
@@ -443,11 +455,9 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 inv_sum = frcp(sum);
             }
             if (GRAD) {
-                const float g = f[F_DC] * inv_sum;
-                const float k = f[F_K];
-                const float Nx = k * xp * (g + f[F_DS]);
+                const float Nx = xp * fmaf(f[F_DC], inv_sum, f[F_DS]);
                 const float Dx = fmaf(A1, A2, k2x2);
-                const float Ny = k * yp * (g + f[F_Q2DS]);
+                const float Ny = yp * fmaf(f[F_DC], inv_sum, f[F_Q2DS]);
                 const float Dy = fmaf(B1, B2, -f[F_K2] * y2);
                 const float R2 = frcp(Dx * Dy);
                 const float bf = Nx * (R2 * Dy), sf = Ny * (R2 * Dx);

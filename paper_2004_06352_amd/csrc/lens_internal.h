@@ -30,20 +30,26 @@ namespace lens {
 enum DerivedIndex : int {
     D_X0 = 0, D_Y0, D_C, D_S,          // centre, cos(phi), sin(phi)
     D_PFC, D_PFS,                      // PF c, PF s: deflection rotated back
-    D_HT, D_HCMH, D_HCS, D_HCS2, D_HCMS,  // HF/2, HF (c^2 - s^2)/2, HF c s, 2 HF c s, HF (c^2 - s^2)
+    D_HT, D_HCMH, D_HCS, D_HCS2, D_HCMS,  // HF/2, HF (c^2 - s^2)/2, HF c s, 2 HF c s, HF (c^2 - s^2);
+                                       // for eps > 0 times 1/k (D_HT) and 1/k^3 (the rest)
     D_Q2,                              // q^2
     D_CA, D_CS_, D_SA, D_SS,           // C_a = q^2 S_a^2, C_s, S_a, S_s
     D_Q2SA, D_Q2SS,                    // q^2 S_a, q^2 S_s
     D_K, D_K2,                         // k, k^2
-    D_DC, D_DS, D_Q2DS,                // C_s - C_a, S_s - S_a, q^2 (S_s - S_a)
+    D_DC, D_DS, D_Q2DS,                // C_s - C_a, S_s - S_a, q^2 (S_s - S_a), each times k
+                                       // when eps > 0 (the ratios' factor k folded in)
     D_PF,                              // deflection prefactor (F included)
     D_EA, D_ES,                        // E_a, E_s
+    // eps > 0: the lengths of the closed form divided by k (unscaled for eps = 0)
+    D_EQ2, D_EK2I,                     // q^2/k^2, 1/k^2 (the squared radius R/k^2)
+    D_ECA, D_ECS, D_ESA, D_ESS,        // C_a/k^2, C_s/k^2, S_a/k, S_s/k
+    D_EQ2SA, D_EQ2SS,                  // q^2 S_a/k, q^2 S_s/k
     D_KIND,                            // kind bits: low word of the entry's bit pattern
     NDER
 };
 // Float copy of the constants used after the FP64 offset/rotation step.
 enum DerivedIndexF : int {
-    F_HT = 0, F_HCMH, F_HCS, F_HCS2, F_HCMS,  // as D_HT .. D_HCMS
+    F_HT = 0, F_HCMH, F_HCS, F_HCS2, F_HCMS,  // as D_HT .. D_HCMS, without the factors of k
     F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS,
     F_K, F_K2, F_DC, F_DS, F_Q2DS,
     F_PFC, F_PFS,                      // PF c, PF s

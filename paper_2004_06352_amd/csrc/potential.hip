@@ -87,9 +87,9 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
             const double ma1 = lra.m + 1.0, ms1 = lrs.m + 1.0, M = ma1 * ms1;
             const double R = rcp64(P1 * M);
             const double RM = R * M, RP = R * P1;  // 1/P1, 1/M
-            const double g = c[D_DC] * (RM * DXY);
-            const double Nx = k * xp * (g + c[D_DS]);
-            const double Ny = k * yp * (g + c[D_Q2DS]);
+            const double inv_sum = RM * DXY;  // the stored differences carry k
+            const double Nx = xp * fma(c[D_DC], inv_sum, c[D_DS]);
+            const double Ny = yp * fma(c[D_DC], inv_sum, c[D_Q2DS]);
             // the deflection's fast path (small ratios on the whole wave)
             const double R2f = RM * sum;
             const double bf = Nx * (R2f * Dy), sf = Ny * (R2f * Dx);

@@ -21,7 +21,10 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     const bool ok = isfinite(x0) && isfinite(y0) && isfinite(b0) && b0 >= 0.0 &&
                     isfinite(eps) && eps >= 0.0 && eps < 1.0 && isfinite(phi) &&
                     isfinite(a) && a >= 0.0 && !isnan(s) && s > a;
-    const bool ell = eps > 0.0;
+    // Below this ellipticity the elliptical closed forms agree with the
+    // circular ones far below FP64 rounding (they differ at first order in
+    // eps), while lengths divided by k would leave the FP64 range.
+    const bool ell = eps > 1e-60;
     double c = 1.0, sn = 0.0;
     if (ell) {
         c = cos(phi);
@@ -51,11 +54,15 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_S] = sn;
     v[D_PFC] = PF * c;
     v[D_PFS] = PF * sn;
-    v[D_HT] = 0.5 * HF;
-    v[D_HCMS] = HF * (c * c - sn * sn);
-    v[D_HCMH] = 0.5 * v[D_HCMS];
-    v[D_HCS] = HF * (c * sn);
-    v[D_HCS2] = 2.0 * v[D_HCS];
+    // Hessian constants: the FP64 evaluation of an elliptical potential
+    // leaves a factor k on the trace and 1/k^3 on the other parts
+    const double kap = ell ? 1.0 / k1 : 1.0, kap2 = kap * kap, kap3 = kap2 * kap;
+    const double hcms = HF * (c * c - sn * sn), hcs = HF * (c * sn);
+    v[D_HT] = kap * (0.5 * HF);
+    v[D_HCMS] = kap3 * hcms;
+    v[D_HCMH] = kap3 * (0.5 * hcms);
+    v[D_HCS] = kap3 * hcs;
+    v[D_HCS2] = kap3 * (2.0 * hcs);
     v[D_Q2] = q2;
     v[D_CA] = q2 * Sa * Sa;
     v[D_CS_] = q2 * Ss * Ss;
@@ -65,19 +72,28 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_Q2SS] = q2 * Ss;
     v[D_K] = k1;
     v[D_K2] = k1 * k1;
-    v[D_DC] = DC;
-    v[D_DS] = DS;
-    v[D_Q2DS] = q2 * DS;
+    const double kd = ell ? k1 : 1.0;
+    v[D_DC] = kd * DC;
+    v[D_DS] = kd * DS;
+    v[D_Q2DS] = kd * (q2 * DS);
     v[D_PF] = PF;
     v[D_EA] = Sa * (q2 * Sa - Sa);
     v[D_ES] = Ss * (q2 * Ss - Ss);
+    v[D_EQ2] = kap2 * q2;
+    v[D_EK2I] = kap2;
+    v[D_ECA] = kap2 * v[D_CA];
+    v[D_ECS] = kap2 * v[D_CS_];
+    v[D_ESA] = kap * Sa;
+    v[D_ESS] = kap * Ss;
+    v[D_EQ2SA] = kap * v[D_Q2SA];
+    v[D_EQ2SS] = kap * v[D_Q2SS];
     v[D_KIND] = __longlong_as_double((long long)kind);  // bit pattern, low word = kind
     for (int i = 0; i < NDER; ++i) dd[(size_t)i * stride + k] = v[i];
     if (!F32) return;
-    const double fv[NDERF] = {v[D_HT],   v[D_HCMH],  v[D_HCS],    v[D_HCS2], v[D_HCMS],
+    const double fv[NDERF] = {0.5 * HF,  0.5 * hcms, hcs,         2.0 * hcs, hcms,
                               q2,        v[D_CA],    v[D_CS_],    Sa,        Ss,
-                              v[D_Q2SA], v[D_Q2SS],  k1,          v[D_K2],   DC,
-                              DS,        v[D_Q2DS],  v[D_PFC],    v[D_PFS],  v[D_EA],
+                              v[D_Q2SA], v[D_Q2SS],  k1,          v[D_K2],   v[D_DC],
+                              v[D_DS],   v[D_Q2DS],  v[D_PFC],    v[D_PFS],  v[D_EA],
                               v[D_ES]};
     for (int i = 0; i < NDERF; ++i) df[(size_t)i * stride + k] = (float)fv[i];
 }
