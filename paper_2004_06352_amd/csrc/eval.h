@@ -429,36 +429,31 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
     const float xp = (float)fma(dx, cpd, dy * spd);
     const float yp = (float)fma(dy, cpd, -(dx * spd));
     const float x2 = xp * xp, y2 = yp * yp;
-    const float R = fmaf(f[F_Q2], x2, y2);
+    // elliptical (K_ELL32): lengths divided by k, as in the FP64 form
+    const float R = fmaf(f[F_Q2], x2, f[F_K2I] * y2);
     float ax = 0.f, ay = 0.f, htr = 0.f, hdf = 0.f, hxy = 0.f;  // as in the FP64 form
     if (kind & K_CUT) {
         const float ta = f[F_CA] + R, ts = f[F_CS_] + R;
         const float ra = frsq(ta), rs = frsq(ts);
         const float pa = ta * ra, ps = ts * rs;
         const float A1 = pa + f[F_SA], A2 = ps + f[F_SS];
-        const float B1 = pa + f[F_Q2SA], B2 = ps + f[F_Q2SS];
-        const float sum = pa + ps;
-        float inv_sum, iDa = 0.f, iDs = 0.f;
-        if (kind & K_ELL) {
-            const float k2x2 = f[F_K2] * x2;
-            // reciprocals (quarter-rate) shared through products: one for the
-            // sum and the Hessian denominators, one for the ratio denominators
+        float iDa = 0.f, iDs = 0.f;
+        if (kind & K_ELL32) {
+            // one reciprocal (quarter-rate) for the Hessian denominators and
+            // one for the ratio denominators (their product would leave the
+            // FP32 range)
             if (HESS) {
-                const float Da = fmaf(A1, A1, k2x2), Ds = fmaf(A2, A2, k2x2);
-                const float DD = Da * Ds;
-                const float R1 = frcp(sum * DD);
-                inv_sum = R1 * DD;
-                const float t = R1 * sum;
+                const float Da = fmaf(A1, A1, x2), Ds = fmaf(A2, A2, x2);
+                const float t = frcp(Da * Ds);
                 iDa = t * Ds;
                 iDs = t * Da;
-            } else {
-                inv_sum = frcp(sum);
             }
             if (GRAD) {
-                const float Nx = xp * fmaf(f[F_DC], inv_sum, f[F_DS]);
-                const float Dx = fmaf(A1, A2, k2x2);
-                const float Ny = yp * fmaf(f[F_DC], inv_sum, f[F_Q2DS]);
-                const float Dy = fmaf(B1, B2, -f[F_K2] * y2);
+                const float B1 = pa + f[F_Q2SA], B2 = ps + f[F_Q2SS];
+                const float Nx = xp * (A2 - A1);
+                const float Dx = fmaf(A1, A2, x2);
+                const float Ny = yp * (B2 - B1);
+                const float Dy = fmaf(B1, B2, -y2);
                 const float R2 = frcp(Dx * Dy);
                 const float bf = Nx * (R2 * Dy), sf = Ny * (R2 * Dx);
                 if (wave_all(fabsf(bf) <= 0.19891237f, fabsf(sf) <= 0.17157287f)) {
@@ -472,9 +467,10 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 }
             }
         } else {
+            const float sum = pa + ps;
             const float A12 = A1 * A2;
             const float R1 = frcp(sum * A12);
-            inv_sum = R1 * A12;
+            const float inv_sum = R1 * A12;
             const float i12 = R1 * sum;
             if (HESS) {
                 const float iA1 = i12 * A2, iA2 = i12 * A1;
@@ -502,15 +498,14 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
         const float A1 = pa + f[F_SA];
         const float B1 = pa + f[F_Q2SA];
         float iDa = 0.f;
-        if (kind & K_ELL) {
-            const float k = f[F_K];
+        if (kind & K_ELL32) {
             if (GRAD) {
-                const AtanRedF ra_ = atan_reduce_f(k * xp, A1);
-                const AtanhRedF rh = atanh_reduce_f(k * yp, B1);
+                const AtanRedF ra_ = atan_reduce_f(xp, A1);
+                const AtanhRedF rh = atanh_reduce_f(yp, B1);
                 ax = atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
                 ay = atanh_finish_f(rh, rh.num * frcp(rh.den), S);
             }
-            if (HESS) iDa = frcp(fmaf(A1, A1, f[F_K2] * x2));
+            if (HESS) iDa = frcp(fmaf(A1, A1, x2));
         } else {
             const float iA1 = frcp(A1);
             if (GRAD) {

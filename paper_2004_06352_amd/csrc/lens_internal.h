@@ -47,11 +47,16 @@ enum DerivedIndex : int {
     D_KIND,                            // kind bits: low word of the entry's bit pattern
     NDER
 };
-// Float copy of the constants used after the FP64 offset/rotation step.
+// Float copy of the constants used after the FP64 offset/rotation step.  For
+// eps > 1e-8 (K_ELL32) the FP32 evaluation takes the lengths divided by k as
+// the FP64 one does (F_Q2 .. F_Q2SS, F_K2I and the Hessian constants as the
+// D_E* and D_H* entries); below, it takes the circular forms (they differ from
+// the elliptical ones at first order in eps, far below FP32 rounding), with
+// the circular prefactor in F_PFC, F_PFS.
 enum DerivedIndexF : int {
-    F_HT = 0, F_HCMH, F_HCS, F_HCS2, F_HCMS,  // as D_HT .. D_HCMS, without the factors of k
-    F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS,
-    F_K, F_K2, F_DC, F_DS, F_Q2DS,
+    F_HT = 0, F_HCMH, F_HCS, F_HCS2, F_HCMS,
+    F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS, F_K2I,
+    F_DC, F_DS,                        // C_s - C_a, S_s - S_a (the circular forms)
     F_PFC, F_PFS,                      // PF c, PF s
     F_EA, F_ES,
     NDERF
@@ -62,6 +67,7 @@ enum KindBits : int {
     K_CUT = 2,      // rcut finite: two cores
     K_SING = 4,     // rcore == 0: singular centre (zero contribution there)
     K_INVALID = 8,  // bad parameters: contributes NaN
+    K_ELL32 = 16,   // eps > 1e-8: elliptical closed forms in the FP32 evaluation
 };
 
 // Derived table in device memory: double block [NDER][stride], then float

@@ -40,11 +40,13 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     const double DS = cut ? (1.0 + eps) * (s - a) : 0.0;
     double PF = ell ? F * b0 * (1.0 - eps * eps) / (2.0 * sqrt(eps)) : F * b0;
     double HF = F * b0 * om;
-    int kind = (ell ? K_ELL : 0) | (cut ? K_CUT : 0) | (a == 0.0 ? K_SING : 0);
+    const bool ell32 = eps > 1e-8;
+    int kind = (ell ? K_ELL : 0) | (ell32 ? K_ELL32 : 0) | (cut ? K_CUT : 0) |
+               (a == 0.0 ? K_SING : 0);
     if (!ok) {
         PF = NAN;
         HF = NAN;
-        kind = K_INVALID | K_CUT | K_ELL;
+        kind = K_INVALID | K_CUT | K_ELL | K_ELL32;
         atomicOr(status, ST_INVALID_TABLE);
     }
     double v[NDER];
@@ -90,11 +92,14 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_KIND] = __longlong_as_double((long long)kind);  // bit pattern, low word = kind
     for (int i = 0; i < NDER; ++i) dd[(size_t)i * stride + k] = v[i];
     if (!F32) return;
-    const double fv[NDERF] = {0.5 * HF,  0.5 * hcms, hcs,         2.0 * hcs, hcms,
-                              q2,        v[D_CA],    v[D_CS_],    Sa,        Ss,
-                              v[D_Q2SA], v[D_Q2SS],  k1,          v[D_K2],   v[D_DC],
-                              v[D_DS],   v[D_Q2DS],  v[D_PFC],    v[D_PFS],  v[D_EA],
-                              v[D_ES]};
+    // the FP32 evaluation's own scaling (see the FP32 table's layout)
+    const double g = ell32 ? kap : 1.0, g2 = g * g, g3 = g2 * g;
+    const double PF32 = ell32 ? PF : (ok ? F * b0 : NAN);
+    const double fv[NDERF] = {g * (0.5 * HF), g3 * (0.5 * hcms), g3 * hcs, g3 * (2.0 * hcs),
+                              g3 * hcms,      g2 * q2,           g2 * v[D_CA], g2 * v[D_CS_],
+                              g * Sa,         g * Ss,            g * v[D_Q2SA], g * v[D_Q2SS],
+                              g2,             DC,                DS,        PF32 * c,
+                              PF32 * sn,      v[D_EA],           v[D_ES]};
     for (int i = 0; i < NDERF; ++i) df[(size_t)i * stride + k] = (float)fv[i];
 }
 
