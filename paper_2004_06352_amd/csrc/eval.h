@@ -177,139 +177,143 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
     const double x2 = xp * xp, y2 = yp * yp;
     // htr, hdf: psi_xx + psi_yy and psi_xx - psi_yy; hxy holds -psi_xy
     double ax = 0.0, ay = 0.0, htr = 0.0, hdf = 0.0, hxy = 0.0;
-    if (kind & K_CUT) {
-        // ra, rs: 1/psi_w; iDa, iDs: 1/D_w.  Elliptical potentials work with
-        // every length of the closed form divided by k (psi_w/k, A_w/k, B_w/k):
-        // the ratios k x'/A_w and k y'/B_w lose their k and D_w/k^2 = A_w^2/k^2
-        // + x'^2; the Hessian constants carry the factors k and 1/k^3 this
-        // leaves on the trace and on the other parts.
-        double ra, rs, iDa = 0.0, iDs = 0.0;
-        if (kind & K_ELL) {
-            const double R = fma(c[D_EQ2], x2, c[D_EK2I] * y2);
-            const double ta = c[D_ECA] + R, ts = c[D_ECS] + R;
-            ra = rsq64(ta);
-            rs = rsq64(ts);
-            const double pa = ta * ra, ps = ts * rs;
-            const double A1 = pa + c[D_ESA], A2 = ps + c[D_ESS];
-            // one reciprocal (a quarter-rate instruction) of D_a D_s Dx Dy
-            // serves the Hessian denominators and the ratios' denominators
-            // Dx = A_a A_s + x'^2 and Dy = B_a B_s - y'^2 (the two cores'
-            // arctangents and hyperbolic arctangents subtracted in closed form)
-            double Da = 1.0, Ds = 1.0, DD = 1.0;
+    // Two cores (ra, rs: 1/psi_w; iDa, iDs: 1/D_w): trace r_a - r_s, and the
+    // difference and -psi_xy from h_w = 1/(psi_w D_w).
+    const auto hess2 = [&](double ra, double rs, double iDa, double iDs) {
+        const double ha = ra * iDa, hs = rs * iDs;
+        const double dh = ha - hs;
+        htr = ra - rs;
+        hdf = fma(y2 - x2, dh, fma(ha, c[D_EA], -(hs * c[D_ES])));
+        hxy = (xp * yp) * dh;
+    };
+    const auto hess1 = [&](double ra, double iDa) {
+        const double ha = ra * iDa;
+        htr = ra;
+        hdf = ha * ((y2 - x2) + c[D_EA]);
+        hxy = (xp * yp) * ha;
+    };
+    // The four forms by a scalar switch on the kind bits, so that no kind test
+    // is carried from one form's code into another's.  Elliptical potentials
+    // work with every length of the closed form divided by k (psi_w/k, A_w/k,
+    // B_w/k): the ratios k x'/A_w and k y'/B_w lose their k and D_w/k^2 =
+    // A_w^2/k^2 + x'^2; the Hessian constants carry the factors k and 1/k^3
+    // this leaves on the trace and on the other parts.
+    switch (kind & (K_CUT | K_ELL)) {
+    case K_CUT | K_ELL: {
+        const double R = fma(c[D_EQ2], x2, c[D_EK2I] * y2);
+        const double ta = c[D_ECA] + R, ts = c[D_ECS] + R;
+        const double ra = rsq64(ta), rs = rsq64(ts);
+        const double pa = ta * ra, ps = ts * rs;
+        const double A1 = pa + c[D_ESA], A2 = ps + c[D_ESS];
+        // one reciprocal (a quarter-rate instruction) of D_a D_s Dx Dy serves
+        // the Hessian denominators and the ratios' denominators Dx = A_a A_s +
+        // x'^2 and Dy = B_a B_s - y'^2 (the two cores' arctangents and
+        // hyperbolic arctangents subtracted in closed form)
+        double Da = 1.0, Ds = 1.0, DD = 1.0, iDa = 0.0, iDs = 0.0;
+        if (HESS) {
+            Da = fma(A1, A1, x2);
+            Ds = fma(A2, A2, x2);
+            DD = Da * Ds;
+        }
+        if (GRAD) {
+            const double B1 = pa + c[D_EQ2SA], B2 = ps + c[D_EQ2SS];
+            const double Dx = fma(A1, A2, x2);
+            const double Dy = fma(B1, B2, -y2);
+            const double XG = Dx * Dy;
+            const double Rall = rcp64(HESS ? DD * XG : XG);
             if (HESS) {
-                Da = fma(A1, A1, x2);
-                Ds = fma(A2, A2, x2);
-                DD = Da * Ds;
-            }
-            if (GRAD) {
-                const double B1 = pa + c[D_EQ2SA], B2 = ps + c[D_EQ2SS];
-                const double Dx = fma(A1, A2, x2);
-                const double Dy = fma(B1, B2, -y2);
-                const double XG = Dx * Dy;
-                const double Rall = rcp64(HESS ? DD * XG : XG);
-                if (HESS) {
-                    const double t = Rall * XG;  // 1/(D_a D_s)
-                    iDa = t * Ds;
-                    iDs = t * Da;
-                }
-                const double R2 = HESS ? Rall * DD : Rall;  // 1/(Dx Dy)
-                const double Nx = xp * (A2 - A1);
-                const double Ny = yp * (B2 - B1);
-                // Away from the cores both ratios are small: when they are
-                // inside the polynomials' intervals for the whole wave, skip
-                // the reductions.  (The ratios are formed first; the few waves
-                // that fail the test discard them.)
-                const double bf = Nx * (R2 * Dy), sf = Ny * (R2 * Dx);
-                if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
-                    ax = atan_poly(bf, S);
-                    ay = atanh_poly(sf, S);
-                } else {
-                    const AtanRed ra_ = atan_reduce(Nx, Dx);
-                    const AtanhRed rh = atanh_reduce(Ny, Dy);
-                    const double R3 = rcp64(ra_.den * rh.den);
-                    const double b = ra_.num * (R3 * rh.den);
-                    const double s = rh.num * (R3 * ra_.den);
-                    ax = atan_finish(ra_, b, S);
-                    ay = atanh_finish(rh, s, S);
-                }
-            } else if (HESS) {
-                const double t = rcp64(DD);
+                const double t = Rall * XG;  // 1/(D_a D_s)
                 iDa = t * Ds;
                 iDs = t * Da;
             }
-        } else {
-            // circular: k = 0, D_w = A_w^2
-            const double R = fma(c[D_Q2], x2, y2);
-            const double ta = c[D_CA] + R, ts = c[D_CS_] + R;
-            ra = rsq64(ta);
-            rs = rsq64(ts);
-            const double pa = ta * ra, ps = ts * rs;
-            const double A1 = pa + c[D_SA], A2 = ps + c[D_SS];
-            const double sum = pa + ps;
-            const double A12 = A1 * A2;
-            const double R1 = rcp64(sum * A12);
-            const double inv_sum = R1 * A12;
-            const double i12 = R1 * sum;
-            if (HESS) {
-                const double iA1 = i12 * A2, iA2 = i12 * A1;
-                iDa = iA1 * iA1;
-                iDs = iA2 * iA2;
-            }
-            if (GRAD) {
-                const double g = c[D_DC] * inv_sum;
-                const double t = (g + c[D_DS]) * i12;
-                ax = t * xp;
-                ay = t * yp;
-            }
-        }
-        if (HESS) {
-            // trace r_a - r_s; difference and -psi_xy from h_w = 1/(psi_w D_w)
-            const double ha = ra * iDa, hs = rs * iDs;
-            const double dh = ha - hs;
-            htr = ra - rs;
-            hdf = fma(y2 - x2, dh, fma(ha, c[D_EA], -(hs * c[D_ES])));
-            hxy = (xp * yp) * dh;
-        }
-    } else {
-        double ra, iDa = 0.0;
-        if (kind & K_ELL) {
-            // lengths divided by k as in the two-core form
-            const double ta = c[D_ECA] + fma(c[D_EQ2], x2, c[D_EK2I] * y2);
-            ra = rsq64(ta);
-            const double pa = ta * ra;
-            const double A1 = pa + c[D_ESA];
-            const double B1 = pa + c[D_EQ2SA];
-            const double Da = fma(A1, A1, x2);
-            if (GRAD) {
-                const AtanRed ra_ = atan_reduce(xp, A1);
-                const AtanhRed rh = atanh_reduce(yp, B1);
-                const double den = ra_.den * rh.den;
-                const double R2 = rcp64(HESS ? den * Da : den);
-                const double RD = HESS ? R2 * Da : R2;
-                const double b = ra_.num * (RD * rh.den);
-                const double s = rh.num * (RD * ra_.den);
-                if (HESS) iDa = R2 * den;
+            const double R2 = HESS ? Rall * DD : Rall;  // 1/(Dx Dy)
+            const double Nx = xp * (A2 - A1);
+            const double Ny = yp * (B2 - B1);
+            // Away from the cores both ratios are small: when they are inside
+            // the polynomials' intervals for the whole wave, the reductions
+            // are skipped.  (The polynomials are evaluated first, into the
+            // registers the results keep; the few waves that fail the test
+            // overwrite them.)
+            const double bf = Nx * (R2 * Dy), sf = Ny * (R2 * Dx);
+            ax = atan_poly(bf, S);
+            ay = atanh_poly(sf, S);
+            if (!wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
+                const AtanRed ra_ = atan_reduce(Nx, Dx);
+                const AtanhRed rh = atanh_reduce(Ny, Dy);
+                const double R3 = rcp64(ra_.den * rh.den);
+                const double b = ra_.num * (R3 * rh.den);
+                const double s = rh.num * (R3 * ra_.den);
                 ax = atan_finish(ra_, b, S);
                 ay = atanh_finish(rh, s, S);
-            } else if (HESS) {
-                iDa = rcp64(Da);
             }
-        } else {
-            const double ta = c[D_CA] + fma(c[D_Q2], x2, y2);
-            ra = rsq64(ta);
-            const double iA1 = rcp64(ta * ra + c[D_SA]);
-            if (GRAD) {
-                ax = iA1 * xp;
-                ay = iA1 * yp;
-            }
-            iDa = iA1 * iA1;
+        } else if (HESS) {
+            const double t = rcp64(DD);
+            iDa = t * Ds;
+            iDs = t * Da;
+        }
+        if (HESS) hess2(ra, rs, iDa, iDs);
+        break;
+    }
+    case K_CUT: {
+        // circular: k = 0, D_w = A_w^2; psi_s - psi_a = (C_s - C_a)/(psi_a + psi_s)
+        const double R = fma(c[D_Q2], x2, y2);
+        const double ta = c[D_CA] + R, ts = c[D_CS_] + R;
+        const double ra = rsq64(ta), rs = rsq64(ts);
+        const double pa = ta * ra, ps = ts * rs;
+        const double A1 = pa + c[D_SA], A2 = ps + c[D_SS];
+        const double sum = pa + ps;
+        const double A12 = A1 * A2;
+        const double R1 = rcp64(sum * A12);
+        const double i12 = R1 * sum;
+        if (GRAD) {
+            const double g = c[D_DC] * (R1 * A12);
+            const double t = (g + c[D_DS]) * i12;
+            ax = t * xp;
+            ay = t * yp;
         }
         if (HESS) {
-            const double ha = ra * iDa;
-            htr = ra;
-            hdf = ha * ((y2 - x2) + c[D_EA]);
-            hxy = (xp * yp) * ha;
+            const double iA1 = i12 * A2, iA2 = i12 * A1;
+            hess2(ra, rs, iA1 * iA1, iA2 * iA2);
         }
+        break;
+    }
+    case K_ELL: {
+        // lengths divided by k as in the two-core form
+        const double ta = c[D_ECA] + fma(c[D_EQ2], x2, c[D_EK2I] * y2);
+        const double ra = rsq64(ta);
+        const double pa = ta * ra;
+        const double A1 = pa + c[D_ESA];
+        const double B1 = pa + c[D_EQ2SA];
+        const double Da = fma(A1, A1, x2);
+        double iDa = 0.0;
+        if (GRAD) {
+            const AtanRed ra_ = atan_reduce(xp, A1);
+            const AtanhRed rh = atanh_reduce(yp, B1);
+            const double den = ra_.den * rh.den;
+            const double R2 = rcp64(HESS ? den * Da : den);
+            const double RD = HESS ? R2 * Da : R2;
+            const double b = ra_.num * (RD * rh.den);
+            const double s = rh.num * (RD * ra_.den);
+            if (HESS) iDa = R2 * den;
+            ax = atan_finish(ra_, b, S);
+            ay = atanh_finish(rh, s, S);
+        } else if (HESS) {
+            iDa = rcp64(Da);
+        }
+        if (HESS) hess1(ra, iDa);
+        break;
+    }
+    default: {
+        const double ta = c[D_CA] + fma(c[D_Q2], x2, y2);
+        const double ra = rsq64(ta);
+        const double iA1 = rcp64(ta * ra + c[D_SA]);
+        if (GRAD) {
+            ax = iA1 * xp;
+            ay = iA1 * yp;
+        }
+        if (HESS) hess1(ra, iA1 * iA1);
+        break;
+    }
     }
     if (SING && zero) ax = ay = htr = hdf = hxy = 0.0;
     // rotate back and accumulate, the prefactors folded into the rotation
