@@ -35,9 +35,9 @@ enum DerivedIndex : int {
     D_Q2,                              // q^2
     D_CA, D_CS_, D_SA, D_SS,           // C_a = q^2 S_a^2, C_s, S_a, S_s
     D_Q2SA, D_Q2SS,                    // q^2 S_a, q^2 S_s
-    D_K, D_K2,                         // k, k^2
-    D_DC, D_DS, D_Q2DS,                // C_s - C_a, S_s - S_a, q^2 (S_s - S_a), each times k
-                                       // when eps > 0 (the ratios' factor k folded in)
+    D_DC, D_DS,                        // C_s - C_a, S_s - S_a (the circular forms)
+    D_LA, D_LS, D_LC,                  // eps > 0, the potential's log terms: PF k S_a/2,
+                                       // PF k S_s/2, PF k ln(k) (S_a - S_s)
     D_PF,                              // deflection prefactor (F included)
     D_EA, D_ES,                        // E_a, E_s
     // eps > 0: the lengths of the closed form divided by k (unscaled for eps = 0)

@@ -11,7 +11,7 @@
 // deflection terms combine as in the deflection map (one atan and one atanh
 // per potential); x' a'x + y' a'y is a dot product, so no rotation back is
 // needed.  L_w = PF k S_w (elliptical) or PF S_w (circular) in terms of the
-// derived constants, PF including F.
+// derived constants, PF including F (PF k = F b0 (1 - eps)).
 //
 // Design (gfx950): one thread per pixel, the potentials staged in LDS in
 // chunks and read by broadcast (as in the deflection map), FP64 throughout.
@@ -68,72 +68,82 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
     const double xp = fma(dx, cp, dy * sp);
     const double yp = fma(dy, cp, -(dx * sp));
     const double x2 = xp * xp, y2 = yp * yp;
-    const double R = fma(c[D_Q2], x2, y2);
-    double v;
-    if (kind & K_CUT) {
+    double v = 0.0;
+    // Elliptical forms in the lengths divided by k, as in the deflection map:
+    // the log terms' D_w/k^2 leave the constant L_w ln(k) per core, carried
+    // with the log terms' factors in D_LA, D_LS, D_LC.
+    switch (kind & (K_CUT | K_ELL)) {
+    case K_CUT | K_ELL: {
+        const double R = fma(c[D_EQ2], x2, c[D_EK2I] * y2);
+        const double ta = c[D_ECA] + R, ts = c[D_ECS] + R;
+        const double pa = ta * rsq64(ta), ps = ts * rsq64(ts);
+        const double A1 = pa + c[D_ESA], A2 = ps + c[D_ESS];
+        const double B1 = pa + c[D_EQ2SA], B2 = ps + c[D_EQ2SS];
+        const double Dx = fma(A1, A2, x2);
+        const double Dy = fma(B1, B2, -y2);
+        // the log terms' mantissas, then one reciprocal (a quarter-rate
+        // instruction) for 1/(Dx Dy) and the two 1/(m + 1)
+        const LogRed lra = log_reduce(fma(A1, A1, x2)), lrs = log_reduce(fma(A2, A2, x2));
+        const double DXY = Dx * Dy;
+        const double ma1 = lra.m + 1.0, ms1 = lrs.m + 1.0, M = ma1 * ms1;
+        const double Rr = rcp64(DXY * M);
+        const double RM = Rr * M, RP = Rr * DXY;  // 1/(Dx Dy), 1/M
+        const double Nx = xp * (A2 - A1);
+        const double Ny = yp * (B2 - B1);
+        // the deflection's fast path (small ratios on the whole wave)
+        const double bf = Nx * (RM * Dy), sf = Ny * (RM * Dx);
+        double ax, ay;
+        if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
+            ax = c[D_PF] * atan_poly(bf, S);
+            ay = c[D_PF] * atanh_poly(sf, S);
+        } else {
+            const AtanRed ra_ = atan_reduce(Nx, Dx);
+            const AtanhRed rh = atanh_reduce(Ny, Dy);
+            const double R2 = rcp64(ra_.den * rh.den);
+            ax = c[D_PF] * atan_finish(ra_, ra_.num * (R2 * rh.den), S);
+            ay = c[D_PF] * atanh_finish(rh, rh.num * (R2 * ra_.den), S);
+        }
+        const double la = log_finish(lra, RP * ms1, S), ls = log_finish(lrs, RP * ma1, S);
+        const double L = fma(c[D_LA], la, fma(-c[D_LS], ls, c[D_LC]));
+        v = fma(xp, ax, yp * ay) - L;
+        break;
+    }
+    case K_CUT: {
+        const double R = fma(c[D_Q2], x2, y2);
         const double ta = c[D_CA] + R, ts = c[D_CS_] + R;
         const double pa = ta * rsq64(ta), ps = ts * rsq64(ts);
         const double A1 = pa + c[D_SA], A2 = ps + c[D_SS];
         const double sum = pa + ps;
-        if (kind & K_ELL) {
-            const double k = c[D_K], k2x2 = c[D_K2] * x2;
-            const double B1 = pa + c[D_Q2SA], B2 = ps + c[D_Q2SS];
-            const double Dx = fma(A1, A2, k2x2);
-            const double Dy = fma(B1, B2, -c[D_K2] * y2);
-            // the log terms' mantissas, then one reciprocal (a quarter-rate
-            // instruction) for 1/sum, 1/(Dx Dy) and the two 1/(m + 1)
-            const LogRed lra = log_reduce(fma(A1, A1, k2x2)), lrs = log_reduce(fma(A2, A2, k2x2));
-            const double DXY = Dx * Dy, P1 = sum * DXY;
-            const double ma1 = lra.m + 1.0, ms1 = lrs.m + 1.0, M = ma1 * ms1;
-            const double R = rcp64(P1 * M);
-            const double RM = R * M, RP = R * P1;  // 1/P1, 1/M
-            const double inv_sum = RM * DXY;  // the stored differences carry k
-            const double Nx = xp * fma(c[D_DC], inv_sum, c[D_DS]);
-            const double Ny = yp * fma(c[D_DC], inv_sum, c[D_Q2DS]);
-            // the deflection's fast path (small ratios on the whole wave)
-            const double R2f = RM * sum;
-            const double bf = Nx * (R2f * Dy), sf = Ny * (R2f * Dx);
-            double ax, ay;
-            if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
-                ax = c[D_PF] * atan_poly(bf, S);
-                ay = c[D_PF] * atanh_poly(sf, S);
-            } else {
-                const AtanRed ra_ = atan_reduce(Nx, Dx);
-                const AtanhRed rh = atanh_reduce(Ny, Dy);
-                const double R2 = rcp64(ra_.den * rh.den);
-                ax = c[D_PF] * atan_finish(ra_, ra_.num * (R2 * rh.den), S);
-                ay = c[D_PF] * atanh_finish(rh, rh.num * (R2 * ra_.den), S);
-            }
-            const double la = log_finish(lra, RP * ms1, S), ls = log_finish(lrs, RP * ma1, S);
-            const double L = 0.5 * (c[D_PF] * k) * (c[D_SA] * la - c[D_SS] * ls);
-            v = fma(xp, ax, yp * ay) - L;
-        } else {
-            const double A12 = A1 * A2;
-            const double R1 = rcp64(sum * A12);
-            const double g = c[D_DC] * (R1 * A12);
-            const double t = c[D_PF] * (g + c[D_DS]) * (R1 * sum);
-            const double L = c[D_PF] * (c[D_SA] * log_pos(A1, S) - c[D_SS] * log_pos(A2, S));
-            v = t * (x2 + y2) - L;
-        }
-    } else {
-        const double ta = c[D_CA] + R;
+        const double A12 = A1 * A2;
+        const double R1 = rcp64(sum * A12);
+        const double g = c[D_DC] * (R1 * A12);
+        const double t = c[D_PF] * (g + c[D_DS]) * (R1 * sum);
+        const double L = c[D_PF] * (c[D_SA] * log_pos(A1, S) - c[D_SS] * log_pos(A2, S));
+        v = t * (x2 + y2) - L;
+        break;
+    }
+    case K_ELL: {
+        const double ta = c[D_ECA] + fma(c[D_EQ2], x2, c[D_EK2I] * y2);
         const double pa = ta * rsq64(ta);
-        const double A1 = pa + c[D_SA];
-        if (kind & K_ELL) {
-            const double k = c[D_K], k2x2 = c[D_K2] * x2;
-            const double B1 = pa + c[D_Q2SA];
-            const AtanRed ra_ = atan_reduce(k * xp, A1);
-            const AtanhRed rh = atanh_reduce(k * yp, B1);
-            const double R2 = rcp64(ra_.den * rh.den);
-            const double ax = c[D_PF] * atan_finish(ra_, ra_.num * (R2 * rh.den), S);
-            const double ay = c[D_PF] * atanh_finish(rh, rh.num * (R2 * ra_.den), S);
-            const double L = 0.5 * (c[D_PF] * k) * (c[D_SA] * log_pos(fma(A1, A1, k2x2), S));
-            v = fma(xp, ax, yp * ay) - L;
-        } else {
-            const double t = c[D_PF] * rcp64(A1);
-            const double L = c[D_SA] == 0.0 ? 0.0 : c[D_PF] * (c[D_SA] * log_pos(A1, S));
-            v = t * (x2 + y2) - L;
-        }
+        const double A1 = pa + c[D_ESA];
+        const double B1 = pa + c[D_EQ2SA];
+        const AtanRed ra_ = atan_reduce(xp, A1);
+        const AtanhRed rh = atanh_reduce(yp, B1);
+        const double R2 = rcp64(ra_.den * rh.den);
+        const double ax = c[D_PF] * atan_finish(ra_, ra_.num * (R2 * rh.den), S);
+        const double ay = c[D_PF] * atanh_finish(rh, rh.num * (R2 * ra_.den), S);
+        const double L = fma(c[D_LA], log_pos(fma(A1, A1, x2), S), c[D_LC]);
+        v = fma(xp, ax, yp * ay) - L;
+        break;
+    }
+    default: {
+        const double ta = c[D_CA] + fma(c[D_Q2], x2, y2);
+        const double A1 = ta * rsq64(ta) + c[D_SA];
+        const double t = c[D_PF] * rcp64(A1);
+        const double L = c[D_SA] == 0.0 ? 0.0 : c[D_PF] * (c[D_SA] * log_pos(A1, S));
+        v = t * (x2 + y2) - L;
+        break;
+    }
     }
     return zero ? 0.0 : v;
 }

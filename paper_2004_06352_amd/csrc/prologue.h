@@ -72,12 +72,12 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_SS] = Ss;
     v[D_Q2SA] = q2 * Sa;
     v[D_Q2SS] = q2 * Ss;
-    v[D_K] = k1;
-    v[D_K2] = k1 * k1;
-    const double kd = ell ? k1 : 1.0;
-    v[D_DC] = kd * DC;
-    v[D_DS] = kd * DS;
-    v[D_Q2DS] = kd * (q2 * DS);
+    v[D_DC] = DC;
+    v[D_DS] = DS;
+    const double pk = ell ? PF * k1 : 0.0;  // F b0 (1 - eps)
+    v[D_LA] = 0.5 * pk * Sa;
+    v[D_LS] = 0.5 * pk * Ss;
+    v[D_LC] = ell ? pk * log(k1) * (Sa - Ss) : 0.0;
     v[D_PF] = PF;
     v[D_EA] = Sa * (q2 * Sa - Sa);
     v[D_ES] = Ss * (q2 * Ss - Ss);

@@ -148,6 +148,30 @@ def test_fp32_modes_where_single_precision_is_weakest(B, ctx, oracle):
             print(f"hazard grid {grid[:2]} prec={prec}: max err/scale {w:.3g}")
 
 
+def test_ellipticity_limits_in_every_precision(B, ctx, oracle):
+    """Ellipticities around the two switches to the circular closed forms
+    (FP64 below 1e-60, FP32 below 1e-8; above them the evaluation divides the
+    lengths by k = 2 sqrt(eps)/(1 + eps)), with and without a cut radius: every
+    precision, and the FP64 potential map, stay within tolerance of the
+    oracle's elliptical forms."""
+    rows = []
+    for i, e in enumerate((1e-70, 1e-60, 1e-40, 1e-12, 1e-9, 1e-8, 2e-8, 1e-6, 0.3)):
+        rows.append((3.0 * i - 12.0, 1.5 * i - 6.0, 2.0 + 0.1 * i, e, 0.37 * i, 0.3, 25.0))
+        rows.append((12.0 - 3.0 * i, 1.2 * i - 5.0, 1.5, e, 0.5 + 0.2 * i, 0.4, math.inf))
+    a = np.array(rows)
+    pots = {k: a[:, i].copy() for i, k in enumerate(B.POT_KEYS)}
+    grid = (45, 37, -22.05, -18.05, 1.0, 1.0)
+    ref, mag = oracle.lens_map(pots, grid, 0.9)
+    for prec in (0, 1, 2):
+        got = run_map(B, ctx, amp_to_device(B, pots), grid, 0.9, prec)
+        w = assert_within(got, ref, mag, RTOL[prec], f"ellipticity limits prec={prec}")
+        print(f"ellipticity limits prec={prec}: max err/scale {w:.3g}")
+    pref, pmag = oracle.potential_map(pots, grid, 0.9)
+    pgot = B.potential_map(amp_to_device(B, pots), grid, 0.9, ctx=ctx)
+    torch.cuda.synchronize()
+    assert_within(pgot.cpu().numpy(), pref, pmag, RTOL[0], "ellipticity limits potential")
+
+
 def test_singular_centre_contributes_zero(B, ctx, oracle):
     one = {k: v[3:4] for k, v in special_pots().items()}
     grid = (3, 3, 0.0, 0.0, 1.0, 1.0)  # (1, 1) is the centre
