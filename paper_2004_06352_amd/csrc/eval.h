@@ -120,6 +120,15 @@ __device__ __forceinline__ double atan_poly(double b, const Series &S) {
     for (int i = 1; i < LENS_ATAN_N; ++i) p = fma(p, b2, S.at[i]);
     return fma(b * b2, p, b);
 }
+// The same on |b| <= tan(pi/16)/5 with the shorter polynomial.
+constexpr double kAtanSMax = LENS_ATAN_S_MAX;
+__device__ __forceinline__ double atan_poly_s(double b, const Series &S) {
+    const double b2 = b * b;
+    double p = S.ats[0];
+#pragma unroll
+    for (int i = 1; i < LENS_ATAN_S_N; ++i) p = fma(p, b2, S.ats[i]);
+    return fma(b * b2, p, b);
+}
 __device__ __forceinline__ double atan_finish(const AtanRed &r, double b, const Series &S) {
     double t = atan_poly(b, S) + r.base;
     t = r.big ? kPi2 - t : t;
@@ -153,6 +162,15 @@ __device__ __forceinline__ double atanh_poly(double s, const Series &S) {
     for (int i = 1; i < LENS_ATANH_N; ++i) p = fma(p, s2, S.ah[i]);
     return fma(s * s2, p, s);
 }
+// The same on |s| <= (3 - 2 sqrt 2)/5 with the shorter polynomial.
+constexpr double kAtanhSMax = LENS_ATANH_S_MAX;
+__device__ __forceinline__ double atanh_poly_s(double s, const Series &S) {
+    const double s2 = s * s;
+    double p = S.ahs[0];
+#pragma unroll
+    for (int i = 1; i < LENS_ATANH_S_N; ++i) p = fma(p, s2, S.ahs[i]);
+    return fma(s * s2, p, s);
+}
 __device__ __forceinline__ double atanh_finish(const AtanhRed &r, double s, const Series &S) {
     return fma(0.5 * kLn2, (double)r.k, atanh_poly(s, S));
 }
@@ -161,7 +179,7 @@ __device__ __forceinline__ double atanh_finish(const AtanhRed &r, double s, cons
 // SING: the potential has rcore = 0, and its contribution at its own centre
 // is zero (handled by a separate instance so that regular potentials carry no
 // test for it).
-template <bool GRAD, bool HESS, bool SING>
+template <bool GRAD, bool HESS, bool SING, bool SHORT>
 __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, double x, double y,
                                                   double acc[5], const Series &S) {
     double dx = x - c[D_X0];
@@ -231,20 +249,27 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
             const double Ny = yp * (B2 - B1);
             // Away from the cores both ratios are small: when they are inside
             // the polynomials' intervals for the whole wave, the reductions
-            // are skipped.  (The polynomials are evaluated first, into the
-            // registers the results keep; the few waves that fail the test
-            // overwrite them.)
+            // are skipped, and (SHORT) when they are inside the first fifth
+            // of them, the shorter polynomials serve.  (The polynomials are
+            // evaluated before the tests, into the registers the results
+            // keep; the waves that fail a test overwrite them.)
             const double bf = Nx * (R2 * Dy), sf = Ny * (R2 * Dx);
-            ax = atan_poly(bf, S);
-            ay = atanh_poly(sf, S);
-            if (!wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
-                const AtanRed ra_ = atan_reduce(Nx, Dx);
-                const AtanhRed rh = atanh_reduce(Ny, Dy);
-                const double R3 = rcp64(ra_.den * rh.den);
-                const double b = ra_.num * (R3 * rh.den);
-                const double s = rh.num * (R3 * ra_.den);
-                ax = atan_finish(ra_, b, S);
-                ay = atanh_finish(rh, s, S);
+            if (SHORT) {
+                ax = atan_poly_s(bf, S);
+                ay = atanh_poly_s(sf, S);
+            }
+            if (!SHORT || !wave_all(fabs(bf) <= kAtanSMax, fabs(sf) <= kAtanhSMax)) {
+                ax = atan_poly(bf, S);
+                ay = atanh_poly(sf, S);
+                if (!wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
+                    const AtanRed ra_ = atan_reduce(Nx, Dx);
+                    const AtanhRed rh = atanh_reduce(Ny, Dy);
+                    const double R3 = rcp64(ra_.den * rh.den);
+                    const double b = ra_.num * (R3 * rh.den);
+                    const double s = rh.num * (R3 * ra_.den);
+                    ax = atan_finish(ra_, b, S);
+                    ay = atanh_finish(rh, s, S);
+                }
             }
         } else if (HESS) {
             const double t = rcp64(DD);
@@ -339,14 +364,16 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
 // UNIF: every lane of the wave evaluates the same potential (the kind is read
 // into a scalar register and its branches are uniform); otherwise each lane
 // may hold a different potential and the branches diverge.
-template <bool GRAD, bool HESS, bool UNIF = true>
+// SHORT: the two-core elliptical form first tries the shorter polynomials
+// (worth it where most waves are far from every core, as on a map).
+template <bool GRAD, bool HESS, bool UNIF = true, bool SHORT = false>
 __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y, double acc[5],
                                              const Series &S) {
     const int kind = UNIF ? uniform_kind(c[D_KIND]) : kind_bits(c[D_KIND]);
     if (kind & K_SING)
-        eval_pot_f64_impl<GRAD, HESS, true>(c, kind, x, y, acc, S);
+        eval_pot_f64_impl<GRAD, HESS, true, SHORT>(c, kind, x, y, acc, S);
     else
-        eval_pot_f64_impl<GRAD, HESS, false>(c, kind, x, y, acc, S);
+        eval_pot_f64_impl<GRAD, HESS, false, SHORT>(c, kind, x, y, acc, S);
 }
 
 // ---------------------------------------------------------------------------

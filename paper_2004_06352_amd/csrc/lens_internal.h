@@ -108,6 +108,8 @@ struct PotSoA {
 struct Series {
     double at[LENS_ATAN_N];   // atan(b) = b + b^3 p(b^2), p ~ -1/3 + b^2/5 - ...
     double ah[LENS_ATANH_N];  // atanh(s) = s + s^3 q(s^2), q ~ 1/3 + s^2/5 + ...
+    double ats[LENS_ATAN_S_N];    // the same pair on the first fifth of each interval
+    double ahs[LENS_ATANH_S_N];
     float atf[4];             // 1/9, -1/7, 1/5, -1/3
     float ahf[4];             // 1/9, 1/7, 1/5, 1/3
 };
@@ -117,6 +119,10 @@ inline Series make_series() {
     const double ah[LENS_ATANH_N] = {LENS_ATANH_COEFFS};
     for (int i = 0; i < LENS_ATAN_N; ++i) S.at[i] = at[i];
     for (int i = 0; i < LENS_ATANH_N; ++i) S.ah[i] = ah[i];
+    const double ats[LENS_ATAN_S_N] = {LENS_ATAN_S_COEFFS};
+    const double ahs[LENS_ATANH_S_N] = {LENS_ATANH_S_COEFFS};
+    for (int i = 0; i < LENS_ATAN_S_N; ++i) S.ats[i] = ats[i];
+    for (int i = 0; i < LENS_ATANH_S_N; ++i) S.ahs[i] = ahs[i];
     for (int i = 0; i < 4; ++i) S.atf[i] = (float)(((i % 2) ? -1.0 : 1.0) / (9 - 2 * i));
     for (int i = 0; i < 4; ++i) S.ahf[i] = (float)(1.0 / (9 - 2 * i));
     return S;

@@ -211,12 +211,14 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
     if (PREC == 0) {
         S.at[0] = vgpr_f64(a.S.at[0]);
         S.ah[0] = vgpr_f64(a.S.ah[0]);
+        S.ats[0] = vgpr_f64(a.S.ats[0]);
+        S.ahs[0] = vgpr_f64(a.S.ahs[0]);
     }
     auto body = [&](const ConstD cd, const ConstF cf) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             if (PREC == 0) {
-                eval_pot_f64<GRAD, HESS>(cd, x[p], y, acc[p], S);
+                eval_pot_f64<GRAD, HESS, true, true>(cd, x[p], y, acc[p], S);
             } else {
                 float o[5];
                 eval_pot_f32<GRAD, HESS>(cd, cf, x[p], y, o, a.S);
