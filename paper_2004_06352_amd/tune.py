@@ -20,7 +20,7 @@ from . import binding as B
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_native", "map_tuning.json")
 
-DEFAULT = (64, 4, 1, 1, 64)
+DEFAULT = (64, 4, 2, 1, 64)
 
 
 def candidates():
