@@ -405,6 +405,13 @@ __global__ void __launch_bounds__(256, 6) alpha_grid_kernel(AlphaGridLaunch a) {
     int s = 0;
     int ke = min(max(off[1], kb), nf);
     double acc[5] = {fx, fy, 0, 0, 0};
+    // the polynomials' leading coefficients in vector registers (each first
+    // Horner step reads two coefficients; one may come from a scalar register)
+    Series S = a.S;
+    if (PREC == 0) {
+        S.at[0] = vgpr_f64(a.S.at[0]);
+        S.ah[0] = vgpr_f64(a.S.ah[0]);
+    }
     auto finish = [&]() {
         if (v < nv) {
             a.out[(size_t)(s0 + s) * 2 * nv + v] = acc[0];
@@ -433,7 +440,7 @@ __global__ void __launch_bounds__(256, 6) alpha_grid_kernel(AlphaGridLaunch a) {
         for (int kk = 0; kk < cnt; ++kk) {
             while (s < ns && kc + kk >= ke) finish();
             if (PREC == 0) {
-                eval_pot_f64<true, false>(ConstD{pd + kk * NDER, 1}, x, y, acc, a.S);
+                eval_pot_f64<true, false>(ConstD{pd + kk * NDER, 1}, x, y, acc, S);
             } else {
                 float o[5];
                 eval_pot_f32<true, false>(ConstD{pd + kk * NDER, 1}, ConstF{pf + kk * NDERF, 1},

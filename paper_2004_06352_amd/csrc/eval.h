@@ -57,6 +57,14 @@ __device__ __forceinline__ int uniform_kind(double k) {
     return __builtin_amdgcn_readfirstlane(__double2loint(k));
 }
 
+// A copy of a double in vector registers (kept there: the compiler cannot
+// rematerialise it from the scalar source).
+__device__ __forceinline__ double vgpr_f64(double x) {
+    double r;
+    asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
 // True on every active lane when both predicates hold on all of them (scalar
 // operations on the compare masks and the execution mask).
 __device__ __forceinline__ bool wave_all(bool p, bool q) {
@@ -146,10 +154,12 @@ __device__ __forceinline__ AtanhRed atanh_reduce(double N, double D) {
     int k = __builtin_amdgcn_frexp_exp(P) - __builtin_amdgcn_frexp_exp(Q);
     k += (mp > kSqrt2 * mq) ? 1 : 0;
     k -= (mq > kSqrt2 * mp) ? 1 : 0;
-    const double Pk = __builtin_amdgcn_ldexp(P, -k);
+    // (D+N) 2^-k - (D-N) as (D+N)(2^-k - 1) + 2N: exactly 2N when k = 0, with
+    // no select; 2^-k - 1 is exact for the exponents that occur
+    const double t = __builtin_amdgcn_ldexp(1.0, -k);
     AtanhRed r;
-    r.num = (k == 0) ? 2.0 * N : Pk - Q;
-    r.den = Pk + Q;
+    r.num = fma(P, t - 1.0, 2.0 * N);
+    r.den = fma(P, t, Q);
     r.k = k;
     return r;
 }

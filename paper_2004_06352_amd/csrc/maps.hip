@@ -127,13 +127,6 @@ hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, 
 // ---------------------------------------------------------------------------
 // The map kernel.
 
-// A copy of a double in vector registers (kept there: the compiler cannot
-// rematerialise it from the scalar source).
-__device__ __forceinline__ double vgpr_f64(double x) {
-    double r;
-    asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "s"(x));
-    return r;
-}
 
 // A wave-uniform double moved to scalar registers.
 __device__ __forceinline__ double uniform_f64(double v) {
