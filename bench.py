@@ -75,12 +75,18 @@ COUNTERS = os.path.join(ROOT, "profiles", "map_kernel_cfg2_2048sq_502pot_counter
 
 
 def map_source_hash():
-    """Hash of the sources that define the map kernel."""
+    """Hash of the code (comments and blank lines dropped) of the sources that
+    define the map kernel."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for p in MAP_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.split("\n"):
+            line = line.split("//", 1)[0].strip()
+            if line:
+                h.update(line.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -24,8 +24,16 @@ namespace lens {
 // S_w^2 + x'^2 + S_w psi_w], D_w = A_w^2 + k^2 x'^2.
 // The GPU path subtracts the two cores' arctangents and hyperbolic arctangents
 // in closed form (one atan2 and one log1p per potential instead of two of
-// each); psi_s - psi_a is formed as (C_s - C_a)/(psi_a + psi_s), which does not
-// cancel.
+// each).  For eps > 0 it works with every length divided by k (psi_w/k, A_w/k,
+// B_w/k; the D_E* entries), so that the ratios lose their k and D_w/k^2 =
+// (A_w/k)^2 + x'^2; the numerators x'(A_s - A_a) and y'(B_s - B_a) are formed
+// directly (their rounding is a few units of the cores' own terms).  Since
+// q^2 + k^2 = 1 and C_w = S_w q^2 S_w, the trace of a core's bracket is D_w: a
+// core's psi_xx + psi_yy is b0 (1-eps)/psi_w and needs no quotient, and
+// psi_xx - psi_yy is (y'^2 - x'^2 + E_w)/(psi_w D_w), E_w = S_w (q^2 S_w - S_w).
+// The second derivatives are accumulated as a trace part T, a difference part
+// U and the off-diagonal V in the frame of the sum: psi_xx = T + U,
+// psi_yy = T - U, psi_xy = V.
 // ---------------------------------------------------------------------------
 enum DerivedIndex : int {
     D_X0 = 0, D_Y0, D_C, D_S,          // centre, cos(phi), sin(phi)
