@@ -448,6 +448,16 @@ __device__ __forceinline__ float atanh_poly_f(float s, const Series &S) {
     for (int i = 1; i < 4; ++i) p = fmaf(p, s2, S.ahf[i]);
     return fmaf(s * s2, p, s);
 }
+// The same to the fifth power, for |b|, |s| within the first fifth of the
+// intervals (the omitted terms are below 1e-9 relative there).
+__device__ __forceinline__ float atan_poly_fs(float b, const Series &S) {
+    const float b2 = b * b;
+    return fmaf(b * b2, fmaf(S.atf[2], b2, S.atf[3]), b);
+}
+__device__ __forceinline__ float atanh_poly_fs(float s, const Series &S) {
+    const float s2 = s * s;
+    return fmaf(s * s2, fmaf(S.ahf[2], s2, S.ahf[3]), s);
+}
 __device__ __forceinline__ float atanh_finish_f(const AtanhRedF &r, float s, const Series &S) {
     return fmaf(0.34657359f, (float)r.k, atanh_poly_f(s, S));
 }
@@ -455,7 +465,7 @@ __device__ __forceinline__ float atanh_finish_f(const AtanhRedF &r, float s, con
 // FP32 evaluation: offset and rotation in FP64 (|x| ~ 100" would lose
 // ~1e-5" if formed in FP32), the rest in FP32.  out[] receives this
 // potential's rotated contribution.
-template <bool GRAD, bool HESS, bool SING>
+template <bool GRAD, bool HESS, bool SING, bool SHORT>
 __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f, int kind,
                                                   double x, double y, float out[5],
                                                   const Series &S) {
@@ -497,14 +507,22 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 const float Dy = fmaf(B1, B2, -y2);
                 const float R2 = frcp(Dx * Dy);
                 const float bf = Nx * (R2 * Dy), sf = Ny * (R2 * Dx);
-                if (wave_all(fabsf(bf) <= 0.19891237f, fabsf(sf) <= 0.17157287f)) {
-                    ax = atan_poly_f(bf, S);
-                    ay = atanh_poly_f(sf, S);
-                } else {
-                    const AtanRedF ra_ = atan_reduce_f(Nx, Dx);
-                    const AtanhRedF rh = atanh_reduce_f(Ny, Dy);
-                    ax = atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
-                    ay = atanh_finish_f(rh, rh.num * frcp(rh.den), S);
+                // (SHORT) a second, shorter tier as in the FP64 form
+                if (SHORT) {
+                    ax = atan_poly_fs(bf, S);
+                    ay = atanh_poly_fs(sf, S);
+                }
+                if (!SHORT || !wave_all(fabsf(bf) <= (float)kAtanSMax,
+                                        fabsf(sf) <= (float)kAtanhSMax)) {
+                    if (wave_all(fabsf(bf) <= 0.19891237f, fabsf(sf) <= 0.17157287f)) {
+                        ax = atan_poly_f(bf, S);
+                        ay = atanh_poly_f(sf, S);
+                    } else {
+                        const AtanRedF ra_ = atan_reduce_f(Nx, Dx);
+                        const AtanhRedF rh = atanh_reduce_f(Ny, Dy);
+                        ax = atan_finish_f(ra_, ra_.num * frcp(ra_.den), S);
+                        ay = atanh_finish_f(rh, rh.num * frcp(rh.den), S);
+                    }
                 }
             }
         } else {
@@ -577,14 +595,14 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
     }
 }
 
-template <bool GRAD, bool HESS, bool UNIF = true>
+template <bool GRAD, bool HESS, bool UNIF = true, bool SHORT = false>
 __device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, double x, double y,
                                              float out[5], const Series &S) {
     const int kind = UNIF ? uniform_kind(c[D_KIND]) : kind_bits(c[D_KIND]);
     if (kind & K_SING)
-        eval_pot_f32_impl<GRAD, HESS, true>(c, f, kind, x, y, out, S);
+        eval_pot_f32_impl<GRAD, HESS, true, SHORT>(c, f, kind, x, y, out, S);
     else
-        eval_pot_f32_impl<GRAD, HESS, false>(c, f, kind, x, y, out, S);
+        eval_pot_f32_impl<GRAD, HESS, false, SHORT>(c, f, kind, x, y, out, S);
 }
 
 // Neumaier compensated addition: s + c carries the sum to about twice the

@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
                 eval_pot_f64<GRAD, HESS, true, true>(cd, x[p], y, acc[p], S);
             } else {
                 float o[5];
-                eval_pot_f32<GRAD, HESS>(cd, cf, x[p], y, o, a.S);
+                eval_pot_f32<GRAD, HESS, true, true>(cd, cf, x[p], y, o, a.S);
 #pragma unroll
                 for (int ch = 0; ch < 5; ++ch) {
                     const bool used = (ch < 2) ? GRAD : HESS;
