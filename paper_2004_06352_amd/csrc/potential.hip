@@ -90,19 +90,23 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
         const double RM = Rr * M, RP = Rr * DXY;  // 1/(Dx Dy), 1/M
         const double Nx = xp * (A2 - A1);
         const double Ny = yp * (B2 - B1);
-        // the deflection's fast path (small ratios on the whole wave)
+        // the deflection's two fast tiers (small ratios on the whole wave), as
+        // in the deflection map
         const double bf = Nx * (RM * Dy), sf = Ny * (RM * Dx);
-        double ax, ay;
-        if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
-            ax = c[D_PF] * atan_poly(bf, S);
-            ay = c[D_PF] * atanh_poly(sf, S);
-        } else {
-            const AtanRed ra_ = atan_reduce(Nx, Dx);
-            const AtanhRed rh = atanh_reduce(Ny, Dy);
-            const double R2 = rcp64(ra_.den * rh.den);
-            ax = c[D_PF] * atan_finish(ra_, ra_.num * (R2 * rh.den), S);
-            ay = c[D_PF] * atanh_finish(rh, rh.num * (R2 * ra_.den), S);
+        double tx = atan_poly_s(bf, S), ty = atanh_poly_s(sf, S);
+        if (!wave_all(fabs(bf) <= kAtanSMax, fabs(sf) <= kAtanhSMax)) {
+            if (wave_all(fabs(bf) <= kTanPi16, fabs(sf) <= kAtanhS)) {
+                tx = atan_poly(bf, S);
+                ty = atanh_poly(sf, S);
+            } else {
+                const AtanRed ra_ = atan_reduce(Nx, Dx);
+                const AtanhRed rh = atanh_reduce(Ny, Dy);
+                const double R2 = rcp64(ra_.den * rh.den);
+                tx = atan_finish(ra_, ra_.num * (R2 * rh.den), S);
+                ty = atanh_finish(rh, rh.num * (R2 * ra_.den), S);
+            }
         }
+        const double ax = c[D_PF] * tx, ay = c[D_PF] * ty;
         const double la = log_finish(lra, RP * ms1, S), ls = log_finish(lrs, RP * ma1, S);
         const double L = fma(c[D_LA], la, fma(-c[D_LS], ls, c[D_LC]));
         v = fma(xp, ax, yp * ay) - L;
