@@ -228,11 +228,12 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
     // this leaves on the trace and on the other parts.
     switch (kind & (K_CUT | K_ELL)) {
     case K_CUT | K_ELL: {
-        const double R = fma(c[D_EQ2], x2, c[D_EK2I] * y2);
-        const double ta = c[D_ECA] + R, ts = c[D_ECS] + R;
+        // psi_w^2/k^2, the second as the first plus (C_s - C_a)/k^2; psi_w/k
+        // enters A_w/k and B_w/k through one FMA each
+        const double ta = fma(c[D_EQ2], x2, fma(c[D_EK2I], y2, c[D_ECA]));
+        const double ts = ta + c[D_DC];
         const double ra = rsq64(ta), rs = rsq64(ts);
-        const double pa = ta * ra, ps = ts * rs;
-        const double A1 = pa + c[D_ESA], A2 = ps + c[D_ESS];
+        const double A1 = fma(ta, ra, c[D_ESA]), A2 = fma(ts, rs, c[D_ESS]);
         // one reciprocal (a quarter-rate instruction) of D_a D_s Dx Dy serves
         // the Hessian denominators and the ratios' denominators Dx = A_a A_s +
         // x'^2 and Dy = B_a B_s - y'^2 (the two cores' arctangents and
@@ -244,7 +245,7 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
             DD = Da * Ds;
         }
         if (GRAD) {
-            const double B1 = pa + c[D_EQ2SA], B2 = ps + c[D_EQ2SS];
+            const double B1 = fma(ta, ra, c[D_EQ2SA]), B2 = fma(ts, rs, c[D_EQ2SS]);
             const double Dx = fma(A1, A2, x2);
             const double Dy = fma(B1, B2, -y2);
             const double XG = Dx * Dy;
@@ -314,11 +315,10 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
     }
     case K_ELL: {
         // lengths divided by k as in the two-core form
-        const double ta = c[D_ECA] + fma(c[D_EQ2], x2, c[D_EK2I] * y2);
+        const double ta = fma(c[D_EQ2], x2, fma(c[D_EK2I], y2, c[D_ECA]));
         const double ra = rsq64(ta);
-        const double pa = ta * ra;
-        const double A1 = pa + c[D_ESA];
-        const double B1 = pa + c[D_EQ2SA];
+        const double A1 = fma(ta, ra, c[D_ESA]);
+        const double B1 = fma(ta, ra, c[D_EQ2SA]);
         const double Da = fma(A1, A1, x2);
         double iDa = 0.0;
         if (GRAD) {
@@ -480,14 +480,15 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
     const float xp = (float)fma(dx, cpd, dy * spd);
     const float yp = (float)fma(dy, cpd, -(dx * spd));
     const float x2 = xp * xp, y2 = yp * yp;
-    // elliptical (K_ELL32): lengths divided by k, as in the FP64 form
-    const float R = fmaf(f[F_Q2], x2, f[F_K2I] * y2);
+    // elliptical (K_ELL32): lengths divided by k, as in the FP64 form; psi_w^2
+    // (the second core's as the first's plus C_s - C_a) and A_w, B_w by FMAs
+    const float ta = fmaf(f[F_Q2], x2, fmaf(f[F_K2I], y2, f[F_CA]));
     float ax = 0.f, ay = 0.f, htr = 0.f, hdf = 0.f, hxy = 0.f;  // as in the FP64 form
     if (kind & K_CUT) {
-        const float ta = f[F_CA] + R, ts = f[F_CS_] + R;
+        const float ts = ta + f[F_DC];
         const float ra = frsq(ta), rs = frsq(ts);
         const float pa = ta * ra, ps = ts * rs;
-        const float A1 = pa + f[F_SA], A2 = ps + f[F_SS];
+        const float A1 = fmaf(ta, ra, f[F_SA]), A2 = fmaf(ts, rs, f[F_SS]);
         float iDa = 0.f, iDs = 0.f;
         if (kind & K_ELL32) {
             // one reciprocal (quarter-rate) for the Hessian denominators and
@@ -500,7 +501,7 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
                 iDs = t * Da;
             }
             if (GRAD) {
-                const float B1 = pa + f[F_Q2SA], B2 = ps + f[F_Q2SS];
+                const float B1 = fmaf(ta, ra, f[F_Q2SA]), B2 = fmaf(ts, rs, f[F_Q2SS]);
                 const float Nx = xp * (A2 - A1);
                 const float Dx = fmaf(A1, A2, x2);
                 const float Ny = yp * (B2 - B1);
@@ -551,11 +552,9 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
             hxy = (xp * yp) * dh;
         }
     } else {
-        const float ta = f[F_CA] + R;
         const float ra = frsq(ta);
-        const float pa = ta * ra;
-        const float A1 = pa + f[F_SA];
-        const float B1 = pa + f[F_Q2SA];
+        const float A1 = fmaf(ta, ra, f[F_SA]);
+        const float B1 = fmaf(ta, ra, f[F_Q2SA]);
         float iDa = 0.f;
         if (kind & K_ELL32) {
             if (GRAD) {

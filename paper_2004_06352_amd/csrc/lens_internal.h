@@ -43,7 +43,8 @@ enum DerivedIndex : int {
     D_Q2,                              // q^2
     D_CA, D_CS_, D_SA, D_SS,           // C_a = q^2 S_a^2, C_s, S_a, S_s
     D_Q2SA, D_Q2SS,                    // q^2 S_a, q^2 S_s
-    D_DC, D_DS,                        // C_s - C_a, S_s - S_a (the circular forms)
+    D_DC, D_DS,                        // C_s - C_a (divided by k^2 for eps > 0, as the
+                                       // D_E* entries), S_s - S_a
     D_LA, D_LS, D_LC,                  // eps > 0, the potential's log terms: PF k S_a/2,
                                        // PF k S_s/2, PF k ln(k) (S_a - S_s)
     D_PF,                              // deflection prefactor (F included)
@@ -64,7 +65,7 @@ enum DerivedIndex : int {
 enum DerivedIndexF : int {
     F_HT = 0, F_HCMH, F_HCS, F_HCS2, F_HCMS,
     F_Q2, F_CA, F_CS_, F_SA, F_SS, F_Q2SA, F_Q2SS, F_K2I,
-    F_DC, F_DS,                        // C_s - C_a, S_s - S_a (the circular forms)
+    F_DC, F_DS,                        // C_s - C_a (in the FP32 length units), S_s - S_a
     F_PFC, F_PFS,                      // PF c, PF s
     F_EA, F_ES,
     NDERF

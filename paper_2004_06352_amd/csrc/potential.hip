@@ -74,11 +74,11 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
     // with the log terms' factors in D_LA, D_LS, D_LC.
     switch (kind & (K_CUT | K_ELL)) {
     case K_CUT | K_ELL: {
-        const double R = fma(c[D_EQ2], x2, c[D_EK2I] * y2);
-        const double ta = c[D_ECA] + R, ts = c[D_ECS] + R;
-        const double pa = ta * rsq64(ta), ps = ts * rsq64(ts);
-        const double A1 = pa + c[D_ESA], A2 = ps + c[D_ESS];
-        const double B1 = pa + c[D_EQ2SA], B2 = ps + c[D_EQ2SS];
+        const double ta = fma(c[D_EQ2], x2, fma(c[D_EK2I], y2, c[D_ECA]));
+        const double ts = ta + c[D_DC];
+        const double ra = rsq64(ta), rs = rsq64(ts);
+        const double A1 = fma(ta, ra, c[D_ESA]), A2 = fma(ts, rs, c[D_ESS]);
+        const double B1 = fma(ta, ra, c[D_EQ2SA]), B2 = fma(ts, rs, c[D_EQ2SS]);
         const double Dx = fma(A1, A2, x2);
         const double Dy = fma(B1, B2, -y2);
         // the log terms' mantissas, then one reciprocal (a quarter-rate
@@ -127,10 +127,10 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
         break;
     }
     case K_ELL: {
-        const double ta = c[D_ECA] + fma(c[D_EQ2], x2, c[D_EK2I] * y2);
-        const double pa = ta * rsq64(ta);
-        const double A1 = pa + c[D_ESA];
-        const double B1 = pa + c[D_EQ2SA];
+        const double ta = fma(c[D_EQ2], x2, fma(c[D_EK2I], y2, c[D_ECA]));
+        const double ra = rsq64(ta);
+        const double A1 = fma(ta, ra, c[D_ESA]);
+        const double B1 = fma(ta, ra, c[D_EQ2SA]);
         const AtanRed ra_ = atan_reduce(xp, A1);
         const AtanhRed rh = atanh_reduce(yp, B1);
         const double R2 = rcp64(ra_.den * rh.den);

@@ -72,7 +72,7 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_SS] = Ss;
     v[D_Q2SA] = q2 * Sa;
     v[D_Q2SS] = q2 * Ss;
-    v[D_DC] = DC;
+    v[D_DC] = kap2 * DC;
     v[D_DS] = DS;
     const double pk = ell ? PF * k1 : 0.0;  // F b0 (1 - eps)
     v[D_LA] = 0.5 * pk * Sa;
@@ -98,7 +98,7 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     const double fv[NDERF] = {g * (0.5 * HF), g3 * (0.5 * hcms), g3 * hcs, g3 * (2.0 * hcs),
                               g3 * hcms,      g2 * q2,           g2 * v[D_CA], g2 * v[D_CS_],
                               g * Sa,         g * Ss,            g * v[D_Q2SA], g * v[D_Q2SS],
-                              g2,             DC,                DS,        PF32 * c,
+                              g2,             g2 * DC,           DS,        PF32 * c,
                               PF32 * sn,      v[D_EA],           v[D_ES]};
     for (int i = 0; i < NDERF; ++i) df[(size_t)i * stride + k] = (float)fv[i];
 }
