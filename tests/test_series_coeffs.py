@@ -71,3 +71,30 @@ def test_short_interval_bounds():
                                                                 rel=1e-15)
     assert float.fromhex(D["LENS_ATANH_S_MAX"]) == pytest.approx((3 - 2 * math.sqrt(2)) / 5,
                                                                  rel=1e-15)
+
+
+@pytest.mark.parametrize("name,short", [("atan", False), ("atanh", False), ("atan", True),
+                                        ("atanh", True)])
+def test_fp32_taylor_tiers(name, short):
+    """The FP32 path's Taylor polynomials (to the ninth power on the whole
+    reduced interval, to the fifth on its first fifth), evaluated in FP32 in
+    the kernels' order, stay within 3 FP32 units of the true function."""
+    np = pytest.importorskip("numpy")
+    sign = -1.0 if name == "atan" else 1.0
+    coeffs = [np.float32(sign ** (4 - i) / (9 - 2 * i)) for i in range(4)]  # 1/9 .. 1/3
+    if short:
+        coeffs = coeffs[2:]
+    full = math.tan(math.pi / 16) if name == "atan" else 3 - 2 * math.sqrt(2)
+    bound = full / 5 if short else full
+    fn = math.atan if name == "atan" else math.atanh
+    worst = 0.0
+    for i in range(1, 4001):
+        b = np.float32(bound * i / 4000)
+        b2 = np.float32(b * b)
+        p = coeffs[0]
+        for c in coeffs[1:]:
+            p = np.float32(p * b2 + c)
+        got = np.float32(np.float32(b * b2) * p + b)
+        ref = fn(float(b))
+        worst = max(worst, abs(float(got) - ref) / ref)
+    assert worst < 3 * 2.0 ** -24, f"{name} short={short}: {worst:.3g}"
