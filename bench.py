@@ -200,6 +200,67 @@ def bench_serving(map_rate, chi2_rate, n_requests):
     return out
 
 
+def chi2_legs(args, ctx, secondary, torch, B, inputs):
+    """Source-plane chi^2 (batched, per-sample, graph plans), the sampler and
+    the image-plane chi^2; results into `secondary`."""
+    c3 = inputs.config3()
+    cat = B.catalog_to_device(B.catalog_with_dlsds(c3["catalog"], c3["zl"]))
+    fixed = B.table_from_physical(B.to_device(c3["fixed"], B.PHYS_KEYS), 0, ctx)
+    free = B.table_from_physical(B.to_device(c3["free"], B.PHYS_KEYS), 0, ctx)
+    off = torch.as_tensor(c3["free_off"], dtype=torch.int32, device="cuda")
+    S = int(off.numel()) - 1
+    if not args.no_tune:
+        from paper_2004_06352_amd import tune
+        wpc, _ = tune.tune_chi2(ctx, fixed, free, off, cat)
+        secondary["chi2_source_waves_per_cu"] = wpc
+    for name, path in (("batched", B.PATH_BATCHED), ("per_sample", B.PATH_PER_SAMPLE)):
+        n = 50 if path == B.PATH_BATCHED else 3
+        w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=path, ctx=ctx),
+                           n, 1, torch, per_step=False)
+        secondary[f"chi2_source_{name}_samples_per_s"] = S * n / w
+    for name, resident in (("graph", False), ("graph_fixed_resident", True)):
+        plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, resident=resident)
+        w, e = timed_steps(plan.launch, 50, 2, torch, per_step=False)
+        secondary[f"chi2_source_{name}_samples_per_s"] = S * 50 / w
+        plan.close()
+    secondary["chi2_source_workload"] = c3["name"]
+    if not args.no_cpu:
+        secondary["chi2_source_cpu_baseline"] = cpu_baseline_chi2(c3)
+    # Metropolis sampler: 4096 walkers of the same model, one kernel launch
+    # per step (proposal, chi^2 and decision per wave); uniforms supplied
+    # once and reused (filling them is the caller's generator's cost)
+    sm = inputs.sampler_start(n_walkers=4096)
+    Wn = sm["params"].shape[0]
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    um = dev(inputs.sampler_uniforms(np.random.default_rng(9), Wn, 6))
+    mc = B.Mcmc(fixed, cat, dev(sm["params"]), dev(sm["lo"]), dev(sm["hi"]),
+                dev(sm["step"]), um, ctx=ctx)
+    w, e = timed_steps(mc.step, 100, 3, torch, per_step=False)
+    secondary["mcmc_walker_steps_per_s"] = Wn * 100 / w
+    secondary["mcmc_ms_per_step"] = w / 100 * 1e3
+    mc.close()
+    if args.no_image:
+        return
+    # image-plane chi^2: 1000^2 grid, 512 samples of the same model
+    c4 = inputs.config4()
+    off4 = torch.as_tensor(c4["free_off"], dtype=torch.int32, device="cuda")
+    free4 = B.table_from_physical(B.to_device(c4["free"], B.PHYS_KEYS), 0, ctx)
+    S4 = int(off4.numel()) - 1
+    for name, prec in (("fp64", B.FP64), ("fp32_acc64", B.FP32_ACC64)):
+        w, e = timed_steps(lambda: B.chi2_batch(fixed, free4, off4, cat, mode=B.CHI2_IMAGE,
+                                                prec=prec, grid=c4["grid"], kmax=64,
+                                                penalty=100.0, ctx=ctx), 3, 1, torch,
+                           per_step=False)
+        secondary[f"chi2_image_{name}_samples_per_s"] = S4 * 3 / w
+    # the same with every found image refined by Newton's method to 1e-10"
+    w, e = timed_steps(lambda: B.chi2_batch(fixed, free4, off4, cat, mode=B.CHI2_IMAGE,
+                                            grid=c4["grid"], kmax=64, penalty=100.0,
+                                            refine=(20, 1e-10), ctx=ctx), 3, 1, torch,
+                       per_step=False)
+    secondary["chi2_image_fp64_refined_samples_per_s"] = S4 * 3 / w
+    secondary["chi2_image_workload"] = c4["name"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +275,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--skip-map", action="store_true",
+                    help="profiling aid: no map timing; the chi^2 legs only (no JSON line)")
+    ap.add_argument("--no-image", action="store_true", help="skip the image-plane chi^2 legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
@@ -257,6 +321,11 @@ def main():
             best, _ = tune.tune_map(ctx, table, grid, prec, reps=2)
             tuned[prec] = list(best)
         log(f"tuned launch shapes: {tuned}")
+    if args.skip_map:
+        secondary = {}
+        chi2_legs(args, ctx, secondary, torch, B, inputs)
+        log(json.dumps(secondary))
+        return
     log(f"map {nx}x{ny} x {npot} potentials, FP64, steps={args.steps}")
     wall, ev = timed_steps(step, args.steps, args.warmup, torch)
     evals = nx * ny * npot
@@ -318,60 +387,7 @@ def main():
     secondary["potential_map_fp64_avg_launch_ms"] = ep * 1e3
     del op
     if not args.no_chi2 and not args.only_map:
-        c3 = inputs.config3()
-        cat = B.catalog_to_device(B.catalog_with_dlsds(c3["catalog"], c3["zl"]))
-        fixed = B.table_from_physical(B.to_device(c3["fixed"], B.PHYS_KEYS), 0, ctx)
-        free = B.table_from_physical(B.to_device(c3["free"], B.PHYS_KEYS), 0, ctx)
-        off = torch.as_tensor(c3["free_off"], dtype=torch.int32, device="cuda")
-        S = int(off.numel()) - 1
-        if not args.no_tune:
-            from paper_2004_06352_amd import tune
-            wpc, _ = tune.tune_chi2(ctx, fixed, free, off, cat)
-            secondary["chi2_source_waves_per_cu"] = wpc
-        for name, path in (("batched", B.PATH_BATCHED), ("per_sample", B.PATH_PER_SAMPLE)):
-            n = 50 if path == B.PATH_BATCHED else 3
-            w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=path, ctx=ctx),
-                               n, 1, torch, per_step=False)
-            secondary[f"chi2_source_{name}_samples_per_s"] = S * n / w
-        for name, resident in (("graph", False), ("graph_fixed_resident", True)):
-            plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, resident=resident)
-            w, e = timed_steps(plan.launch, 50, 2, torch, per_step=False)
-            secondary[f"chi2_source_{name}_samples_per_s"] = S * 50 / w
-            plan.close()
-        secondary["chi2_source_workload"] = c3["name"]
-        if not args.no_cpu:
-            secondary["chi2_source_cpu_baseline"] = cpu_baseline_chi2(c3)
-        # Metropolis sampler: 4096 walkers of the same model, one kernel launch
-        # per step (proposal, chi^2 and decision per wave); uniforms supplied
-        # once and reused (filling them is the caller's generator's cost)
-        sm = inputs.sampler_start(n_walkers=4096)
-        Wn = sm["params"].shape[0]
-        dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
-        um = dev(inputs.sampler_uniforms(np.random.default_rng(9), Wn, 6))
-        mc = B.Mcmc(fixed, cat, dev(sm["params"]), dev(sm["lo"]), dev(sm["hi"]),
-                    dev(sm["step"]), um, ctx=ctx)
-        w, e = timed_steps(mc.step, 100, 3, torch, per_step=False)
-        secondary["mcmc_walker_steps_per_s"] = Wn * 100 / w
-        secondary["mcmc_ms_per_step"] = w / 100 * 1e3
-        mc.close()
-        # image-plane chi^2: 1000^2 grid, 512 samples of the same model
-        c4 = inputs.config4()
-        off4 = torch.as_tensor(c4["free_off"], dtype=torch.int32, device="cuda")
-        free4 = B.table_from_physical(B.to_device(c4["free"], B.PHYS_KEYS), 0, ctx)
-        S4 = int(off4.numel()) - 1
-        for name, prec in (("fp64", B.FP64), ("fp32_acc64", B.FP32_ACC64)):
-            w, e = timed_steps(lambda: B.chi2_batch(fixed, free4, off4, cat, mode=B.CHI2_IMAGE,
-                                                    prec=prec, grid=c4["grid"], kmax=64,
-                                                    penalty=100.0, ctx=ctx), 3, 1, torch,
-                               per_step=False)
-            secondary[f"chi2_image_{name}_samples_per_s"] = S4 * 3 / w
-        # the same with every found image refined by Newton's method to 1e-10"
-        w, e = timed_steps(lambda: B.chi2_batch(fixed, free4, off4, cat, mode=B.CHI2_IMAGE,
-                                                grid=c4["grid"], kmax=64, penalty=100.0,
-                                                refine=(20, 1e-10), ctx=ctx), 3, 1, torch,
-                           per_step=False)
-        secondary["chi2_image_fp64_refined_samples_per_s"] = S4 * 3 / w
-        secondary["chi2_image_workload"] = c4["name"]
+        chi2_legs(args, ctx, secondary, torch, B, inputs)
     if not args.no_chi2 and not args.only_map and not args.no_serve:
         log("serving stream")
         secondary["serving"] = bench_serving(value, secondary["chi2_source_batched_samples_per_s"],

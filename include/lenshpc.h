@@ -289,7 +289,14 @@ lens_status_t lens_derived_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
  *   stored image positions in increasing triangle id, unused slots NaN.
  *   Returns LENS_EOVERFLOW (after completing the stream, counts exact) when a
  *   (sample, system) had more images than max_img_per_sys.
- *   Image mode synchronises `stream` once at the end to report overflow. */
+ *   Image mode synchronises `stream` once at the end to report overflow and
+ *   the search's own checks (below).
+ * Domain of the image search (image mode and lens_find_images): a source's
+ * Dls/Ds must lie in (0, 1] (the tile cull assumes f > 0); the exact
+ * orientation tests are exact for finite coordinates (unlensed vertices and
+ * sources) whose nonzero magnitudes lie in [2^-400, 2^400].  Both are checked
+ * on the device while the search runs; a violation returns LENS_EINVAL after
+ * the stream completes (outputs written, not meaningful). */
 lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *batch,
                               const lens_catalog_t *cat, const lens_chi2_opts_t *opts,
                               double *chi2, int32_t *nimg, int32_t *nmissing, double *img_xy,
@@ -301,7 +308,9 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *batch,
  * (device arrays of n_src).  Outputs per source, images in increasing
  * triangle id: nimg[s] (exact count), img_tri/img_x/img_y[s*kmax + k]
  * (k < min(nimg[s], kmax); unused slots -1 / NaN).  Returns LENS_EOVERFLOW
- * when a count exceeded kmax (synchronises `stream`). */
+ * when a count exceeded kmax (synchronises `stream`), LENS_EINVAL for an f[s]
+ * outside (0, 1] or coordinates outside the exact domain (see above; that
+ * source gets no images, the others are searched). */
 lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *ay,
                                const lens_grid_t *grid, int32_t n_src, const double *src_x,
                                const double *src_y, const double *f, int32_t kmax,
@@ -386,6 +395,19 @@ lens_status_t lens_time_delay_scale(double zl, double zs, double h0, double om, 
                                     double *out);
 lens_status_t lens_b0_from_sigma(double sigma_kms, int32_t convention, double *out);
 lens_status_t lens_eps_from_e(double e, double *out);
+/* Context scratch (bytes) that one call of these sizes takes: for callers
+ * that budget device memory or size scratch_bytes_max (the serving loop).
+ * lens_map_scratch_bytes: any map call over a table of n_pot potentials (its
+ * derived constants).  lens_chi2_scratch_bytes: lens_chi2_batch with these
+ * table sizes, samples and catalogue sizes under opts (mode, path, grid,
+ * max_img_per_sys are read); image mode is sized for the largest chunk of
+ * samples the call uses when the context allows it (128, or 1 on the
+ * per-sample path).  Pure arithmetic: the result is exact for the current
+ * library, written to *out. */
+lens_status_t lens_map_scratch_bytes(int32_t n_pot, uint64_t *out);
+lens_status_t lens_chi2_scratch_bytes(int32_t n_fixed, int32_t n_free, int32_t n_samples,
+                                      int32_t n_sys, int32_t n_img,
+                                      const lens_chi2_opts_t *opts, uint64_t *out);
 
 const char *lens_last_error(void); /* thread-local; valid until the next call */
 int32_t lens_abi_version(void);

@@ -41,7 +41,8 @@ EXPORTS = ("lens_ctx_create", "lens_ctx_destroy", "lens_ctx_status", "lens_set_m
            "lens_chi2_plan_create", "lens_chi2_plan_create_ex",
            "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_mcmc_create",
            "lens_mcmc_step", "lens_mcmc_destroy", "lens_dlsds",
-           "lens_b0_from_sigma", "lens_eps_from_e", "lens_last_error", "lens_abi_version")
+           "lens_b0_from_sigma", "lens_eps_from_e", "lens_map_scratch_bytes",
+           "lens_chi2_scratch_bytes", "lens_last_error", "lens_abi_version")
 
 
 class LensError(RuntimeError):
@@ -138,6 +139,9 @@ def lib():
         L.lens_dlsds.argtypes = [dbl, dbl, dbl, dbl, C.POINTER(dbl)]
         L.lens_b0_from_sigma.argtypes = [dbl, i32, C.POINTER(dbl)]
         L.lens_eps_from_e.argtypes = [dbl, C.POINTER(dbl)]
+        L.lens_map_scratch_bytes.argtypes = [i32, C.POINTER(C.c_uint64)]
+        L.lens_chi2_scratch_bytes.argtypes = [i32, i32, i32, i32, i32, C.POINTER(_Opts),
+                                              C.POINTER(C.c_uint64)]
         L.lens_last_error.restype = C.c_char_p
         L.lens_abi_version.restype = i32
         for name in EXPORTS:
@@ -364,6 +368,23 @@ def _opts(mode, prec, path, grid, kmax, penalty, refine=None):
     g = _grid(grid) if grid is not None else _Grid(0, 0, 0, 0, 0, 0)
     it, tol = refine if refine is not None else (0, 0.0)
     return _Opts(mode, prec, path, g, int(kmax), float(penalty), int(it), float(tol))
+
+
+def map_scratch_bytes(n_pot):
+    """Context scratch of a map call over n_pot potentials (host arithmetic)."""
+    out = C.c_uint64()
+    _check(lib().lens_map_scratch_bytes(int(n_pot), C.byref(out)))
+    return out.value
+
+
+def chi2_scratch_bytes(n_fixed, n_free, n_samples, n_sys, n_img, mode=CHI2_SOURCE, prec=FP64,
+                       path=PATH_BATCHED, grid=None, kmax=16):
+    """Context scratch of a lens_chi2_batch call of these sizes (host arithmetic)."""
+    o = _opts(mode, prec, path, grid, kmax, 0.0, None)
+    out = C.c_uint64()
+    _check(lib().lens_chi2_scratch_bytes(int(n_fixed), int(n_free), int(n_samples), int(n_sys),
+                                         int(n_img), C.byref(o), C.byref(out)))
+    return out.value
 
 
 def chi2_batch(fixed, free, free_off, cat, mode=CHI2_SOURCE, prec=FP64, path=PATH_BATCHED,

@@ -412,6 +412,56 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
     return LENS_OK;
 }
 
+// Image-plane scratch after the source-plane part: the fixed potentials'
+// deflection grid, then per chunk of samples the deflection grids, slot
+// arrays and tile bounds.  The chunk is 128 samples (1 on the per-sample
+// path), fewer when the context's scratch limit does not hold that many.
+struct ImgPlan {
+    size_t o_afix, o_alpha, o_count, o_tri, o_ix, o_iy, o_part, o_miss, o_tb;
+    int chunk;
+};
+
+ImgPlan plan_img(Carve &cv, int nx, int ny, int n_sys, int kmax, int S, bool one_at_a_time,
+                 uint64_t scratch_max) {
+    ImgPlan p;
+    const size_t nv = (size_t)nx * ny;
+    p.o_afix = cv.take(2 * nv * sizeof(double));
+    const size_t fixed_bytes = cv.off;
+    int ntx, nty;
+    image_tiles(nx, ny, ntx, nty);
+    const size_t per_sample = 2 * nv * sizeof(double) + (size_t)ntx * nty * 4 * sizeof(double) +
+                              (size_t)n_sys * (sizeof(int) + 2 * sizeof(double) + sizeof(int) +
+                                               (size_t)kmax * (sizeof(long long) + 2 * sizeof(double))) +
+                              4096;
+    int chunk = one_at_a_time ? 1 : 128;
+    if (scratch_max > fixed_bytes) {
+        const size_t fit = (scratch_max - fixed_bytes) / per_sample;
+        chunk = (int)std::min<size_t>(chunk, std::max<size_t>(fit, 1));
+    }
+    chunk = std::max(1, std::min(chunk, std::max(S, 1)));
+    p.chunk = chunk;
+    p.o_alpha = cv.take((size_t)chunk * 2 * nv * sizeof(double));
+    p.o_count = cv.take((size_t)chunk * n_sys * sizeof(int));
+    p.o_tri = cv.take((size_t)chunk * n_sys * kmax * sizeof(long long));
+    p.o_ix = cv.take((size_t)chunk * n_sys * kmax * sizeof(double));
+    p.o_iy = cv.take((size_t)chunk * n_sys * kmax * sizeof(double));
+    p.o_part = cv.take((size_t)chunk * n_sys * sizeof(double));
+    p.o_miss = cv.take((size_t)chunk * n_sys * sizeof(int));
+    p.o_tb = cv.take((size_t)chunk * ntx * nty * 4 * sizeof(double));
+    return p;
+}
+
+// The image search's device-side findings (read back after the call).
+lens_status_t search_status(int bits) {
+    if (bits & ST_BAD_F)
+        return fail(LENS_EINVAL, "a source's Dls/Ds lies outside (0, 1]");
+    if (bits & ST_DOMAIN)
+        return fail(LENS_EINVAL,
+                    "an orientation test met a coordinate outside the exact domain "
+                    "(nonzero magnitudes in [2^-400, 2^400], finite)");
+    return LENS_OK;
+}
+
 lens_status_t check_chi2_args(lens_ctx_t *ctx, const lens_model_batch_t *b,
                               const lens_catalog_t *c, const lens_chi2_opts_t *o) {
     if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
@@ -661,29 +711,12 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
     // ---- image plane ----
     const GridArgs G{o->grid.nx, o->grid.ny, o->grid.x0, o->grid.y0, o->grid.dx, o->grid.dy};
     const size_t nv = (size_t)G.nx * G.ny;
-    const size_t o_afix = cv.take(2 * nv * sizeof(double));
-    const size_t fixed_bytes = cv.off;
-    // per-sample working set: deflection grid, tile bounds, slots
-    int ntx, nty;
-    image_tiles(G.nx, G.ny, ntx, nty);
-    const size_t per_sample = 2 * nv * sizeof(double) + (size_t)ntx * nty * 4 * sizeof(double) +
-                              (size_t)c->n_sys * (sizeof(int) + 2 * sizeof(double) + sizeof(int) +
-                                                  (size_t)kmax * (sizeof(long long) + 2 * sizeof(double))) +
-                              4096;
-    int chunk = o->path == LENS_CHI2_PATH_PER_SAMPLE ? 1 : 128;
-    if (ctx->scratch_max > fixed_bytes) {
-        const size_t fit = (ctx->scratch_max - fixed_bytes) / per_sample;
-        chunk = (int)std::min<size_t>(chunk, std::max<size_t>(fit, 1));
-    }
-    chunk = std::max(1, std::min(chunk, std::max(S, 1)));
-    const size_t o_alpha = cv.take((size_t)chunk * 2 * nv * sizeof(double));
-    const size_t o_count = cv.take((size_t)chunk * c->n_sys * sizeof(int));
-    const size_t o_tri = cv.take((size_t)chunk * c->n_sys * kmax * sizeof(long long));
-    const size_t o_ix = cv.take((size_t)chunk * c->n_sys * kmax * sizeof(double));
-    const size_t o_iy = cv.take((size_t)chunk * c->n_sys * kmax * sizeof(double));
-    const size_t o_part = cv.take((size_t)chunk * c->n_sys * sizeof(double));
-    const size_t o_miss = cv.take((size_t)chunk * c->n_sys * sizeof(int));
-    const size_t o_tb = cv.take((size_t)chunk * ntx * nty * 4 * sizeof(double));
+    const ImgPlan ip = plan_img(cv, G.nx, G.ny, c->n_sys, kmax, S,
+                                o->path == LENS_CHI2_PATH_PER_SAMPLE, ctx->scratch_max);
+    const int chunk = ip.chunk;
+    const size_t o_afix = ip.o_afix, o_alpha = ip.o_alpha, o_count = ip.o_count;
+    const size_t o_tri = ip.o_tri, o_ix = ip.o_ix, o_iy = ip.o_iy, o_part = ip.o_part;
+    const size_t o_miss = ip.o_miss, o_tb = ip.o_tb;
     TRY(ensure_scratch(ctx, cv.off));
     TRY(check_contents(ctx, b, c, st));
     HIP_TRY(launch_zero_i32(ctx->small + 2, 1, st));  // overflow word
@@ -740,6 +773,7 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
         I.ix = ix;
         I.iy = iy;
         I.tb = (double *)sc(ctx, o_tb);
+        I.status = ctx->small + 2;
         HIP_TRY(launch_find_images(I, st));
         HIP_TRY(launch_sort_images(ns * c->n_sys, kmax, count, tri, ix, iy, st));
         if (o->refine_max_iter > 0) {
@@ -788,6 +822,7 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
     HIP_TRY(hipMemcpyAsync(ctx->host_small + 2, ctx->small + 2, sizeof(int),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    TRY(search_status(ctx->host_small[2]));
     if (ctx->host_small[2] & ST_OVERFLOW)
         return fail(LENS_EOVERFLOW, "more images than max_img_per_sys in some (sample, system)");
     return LENS_OK;
@@ -823,6 +858,7 @@ lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *
     TRY(ensure_scratch(ctx, cv.off));
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(launch_zero_i32(nimg, n_src, st));
+    HIP_TRY(launch_zero_i32(ctx->small + 2, 1, st));  // search status word
     HIP_TRY(launch_fill_i64((long long *)img_tri, (size_t)n_src * kmax, -1, st));
     HIP_TRY(launch_fill_f64(img_x, (size_t)n_src * kmax, NAN, st));
     HIP_TRY(launch_fill_f64(img_y, (size_t)n_src * kmax, NAN, st));
@@ -840,11 +876,15 @@ lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *
     I.ix = img_x;
     I.iy = img_y;
     I.tb = (double *)sc(ctx, o_tb);
+    I.status = ctx->small + 2;
     HIP_TRY(launch_find_images(I, st));
     HIP_TRY(launch_sort_images(n_src, kmax, nimg, (long long *)img_tri, img_x, img_y, st));
     std::vector<int32_t> cnt(n_src);
     HIP_TRY(hipMemcpyAsync(cnt.data(), nimg, (size_t)n_src * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ctx->host_small + 2, ctx->small + 2, sizeof(int),
+                           hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    TRY(search_status(ctx->host_small[2]));
     for (int s = 0; s < n_src; ++s)
         if (cnt[s] > kmax) return fail(LENS_EOVERFLOW, "source %d has %d images > kmax", s, cnt[s]);
     return LENS_OK;
@@ -1080,6 +1120,43 @@ lens_status_t lens_chi2_plan_destroy(lens_chi2_plan_t *p) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->mem) (void)hipFree(p->mem);  // waits for launches still using it
     delete p;
+    return LENS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch sizing (host arithmetic only): the same carve the calls make.
+lens_status_t lens_map_scratch_bytes(int32_t n_pot, uint64_t *out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    if (n_pot < 0) return fail(LENS_EINVAL, "n_pot < 0");
+    Carve cv;
+    cv.take(derived_bytes(n_pot));
+    *out = cv.off;
+    return LENS_OK;
+}
+
+lens_status_t lens_chi2_scratch_bytes(int32_t n_fixed, int32_t n_free, int32_t n_samples,
+                                      int32_t n_sys, int32_t n_img, const lens_chi2_opts_t *o,
+                                      uint64_t *out) {
+    if (!out || !o) return fail(LENS_EINVAL, "out or opts is NULL");
+    if (n_fixed < 0 || n_free < 0 || n_samples < 0 || n_sys < 1 || n_img < 1)
+        return fail(LENS_EINVAL, "sizes out of range");
+    const bool img = o->mode == LENS_CHI2_IMAGE;
+    if (img && (o->grid.nx < 2 || o->grid.ny < 2 || o->max_img_per_sys < 1 ||
+                o->max_img_per_sys > 64))
+        return fail(LENS_EINVAL, "image mode: grid of at least 2 x 2, max_img_per_sys 1..64");
+    lens_model_batch_t b{};
+    b.n_samples = n_samples;
+    b.fixed.n = n_fixed;
+    b.free.n = n_free;
+    lens_catalog_t c{};
+    c.n_sys = n_sys;
+    c.n_img = n_img;
+    Carve cv;
+    plan_src(cv, &b, &c, img);
+    if (img)
+        plan_img(cv, o->grid.nx, o->grid.ny, n_sys, o->max_img_per_sys, n_samples,
+                 o->path == LENS_CHI2_PATH_PER_SAMPLE, UINT64_MAX);
+    *out = cv.off;
     return LENS_OK;
 }
 

@@ -71,6 +71,7 @@ struct ImgLaunch {
     double *ix, *iy;           // [n_grids*nq*kmax]
     double *tb;                // [n_grids*ntx*nty*4] tile deflection bounds (scratch)
     int ntx, nty;              // tiles per row / column (set by the launcher)
+    int *status;               // ST_DOMAIN / ST_BAD_F bits (atomic or)
 };
 void image_tiles(int nx, int ny, int &ntx, int &nty);
 hipError_t launch_find_images(const ImgLaunch &L, hipStream_t st);

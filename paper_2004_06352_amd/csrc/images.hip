@@ -31,15 +31,26 @@ namespace lens {
 // an FMA error term each and summed into a nonoverlapping expansion
 // (Shewchuk's Grow-Expansion); the sign of its largest nonzero component is
 // the sign of the exact value.  Exact for finite inputs whose nonzero
-// magnitudes lie in [2^-400, 2^400].
+// magnitudes lie in [2^-400, 2^400] (every product and its error term is then
+// a normal number); an expansion that meets any other input sets ST_DOMAIN in
+// the status word, which the entry points turn into an argument error.  (The
+// filter is valid for any finite inputs whose product sum lies in its range.)
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
     s = a + b;
     const double bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
 
+__device__ __forceinline__ bool exact_domain(double v) {
+    const double a = fabs(v);
+    return a == 0.0 || (a >= 0x1p-400 && a <= 0x1p400);
+}
+
 __device__ __noinline__ int orient_sign_expansion(double ax, double ay, double bx, double by,
-                                                  double px, double py) {
+                                                  double px, double py, int *status) {
+    if (!(exact_domain(ax) & exact_domain(ay) & exact_domain(bx) & exact_domain(by) &
+          exact_domain(px) & exact_domain(py)))
+        atomicOr(status, ST_DOMAIN);
     const double u[6] = {bx, -bx, -ax, -by, by, ay};
     const double w[6] = {py, ay, py, px, ax, px};
     double h[12];
@@ -65,19 +76,19 @@ __device__ __noinline__ int orient_sign_expansion(double ax, double ay, double b
 }
 
 __device__ __forceinline__ int orient_sign(double ax, double ay, double bx, double by, double px,
-                                           double py) {
+                                           double py, int *status) {
     const double l = (bx - ax) * (py - ay);
     const double r = (by - ay) * (px - ax);
     const double det = l - r;
     const double sum = fabs(l) + fabs(r);
     if (sum > 1e-280 && sum < 1e280 && fabs(det) > 1e-15 * sum) return det > 0.0 ? 1 : -1;
-    return orient_sign_expansion(ax, ay, bx, by, px, py);
+    return orient_sign_expansion(ax, ay, bx, by, px, py, status);
 }
 
 // Sign of orient(a, b, p + (d, d^2)), d -> 0+.
 __device__ __forceinline__ int orient_perturbed(double ax, double ay, double bx, double by,
-                                                double px, double py) {
-    const int s = orient_sign(ax, ay, bx, by, px, py);
+                                                double px, double py, int *status) {
+    const int s = orient_sign(ax, ay, bx, by, px, py, status);
     if (s) return s;
     if (by != ay) return by < ay ? 1 : -1;
     if (bx != ax) return bx > ax ? 1 : -1;
@@ -87,12 +98,13 @@ __device__ __forceinline__ int orient_perturbed(double ax, double ay, double bx,
 // Triangle (u0, u1, u2) holds p (perturbed), non-degenerate.  Caller has
 // already checked the exact bounding box.
 __device__ __noinline__ bool tri_contains(double u0x, double u0y, double u1x, double u1y,
-                                          double u2x, double u2y, double px, double py) {
-    if (orient_sign(u0x, u0y, u1x, u1y, u2x, u2y) == 0) return false;
-    const int s0 = orient_perturbed(u0x, u0y, u1x, u1y, px, py);
-    const int s1 = orient_perturbed(u1x, u1y, u2x, u2y, px, py);
+                                          double u2x, double u2y, double px, double py,
+                                          int *status) {
+    if (orient_sign(u0x, u0y, u1x, u1y, u2x, u2y, status) == 0) return false;
+    const int s0 = orient_perturbed(u0x, u0y, u1x, u1y, px, py, status);
+    const int s1 = orient_perturbed(u1x, u1y, u2x, u2y, px, py, status);
     if (s0 != s1) return false;
-    const int s2 = orient_perturbed(u2x, u2y, u0x, u0y, px, py);
+    const int s2 = orient_perturbed(u2x, u2y, u0x, u0y, px, py, status);
     return s1 == s2 && s0 != 0;
 }
 
@@ -251,7 +263,12 @@ __global__ void __launch_bounds__(256) find_images_kernel(ImgLaunch L) {
             const size_t gq = (size_t)g * L.nq + q0 + tid;
             s_px[tid] = L.sx[gq];
             s_py[tid] = L.sy[gq];
-            s_f[tid] = L.f[q0 + tid];
+            // the tile cull holds for 0 < f; a source with f outside (0, 1]
+            // is flagged and gets no images (NaN fails every box test)
+            const double fv = L.f[q0 + tid];
+            const bool f_ok = fv > 0.0 && fv <= 1.0;
+            if (!f_ok) atomicOr(L.status, ST_BAD_F);
+            s_f[tid] = f_ok ? fv : __builtin_nan("");
         }
         __syncthreads();
         for (int b0 = 0; b0 < nqc; b0 += 64) {
@@ -296,12 +313,12 @@ __global__ void __launch_bounds__(256) find_images_kernel(ImgLaunch L) {
                     const double u11x = x1 - f * a11x, u11y = y1 - f * a11y;
                     // T0 = (v[i,j], v[i+1,j], v[i,j+1])
                     if (box_may_hold(u00x, u00y, u10x, u10y, u01x, u01y, px, py) &&
-                        tri_contains(u00x, u00y, u10x, u10y, u01x, u01y, px, py))
+                        tri_contains(u00x, u00y, u10x, u10y, u01x, u01y, px, py, L.status))
                         store_image(L, gq, t0, u00x, u00y, u10x, u10y, u01x, u01y, x0, y0, x1,
                                     y0, x0, y1, px, py);
                     // T1 = (v[i+1,j+1], v[i,j+1], v[i+1,j])
                     if (box_may_hold(u11x, u11y, u01x, u01y, u10x, u10y, px, py) &&
-                        tri_contains(u11x, u11y, u01x, u01y, u10x, u10y, px, py))
+                        tri_contains(u11x, u11y, u01x, u01y, u10x, u10y, px, py, L.status))
                         store_image(L, gq, t0 + 1, u11x, u11y, u01x, u01y, u10x, u10y, x1, y1,
                                     x0, y1, x1, y0, px, py);
                 }

@@ -144,7 +144,12 @@ struct GridArgs {
 
 
 // status word bits written by device code
-enum StatusBits : int { ST_INVALID_TABLE = 1, ST_OVERFLOW = 2 };
+enum StatusBits : int {
+    ST_INVALID_TABLE = 1,
+    ST_OVERFLOW = 2,
+    ST_DOMAIN = 4,   // an exact orientation test met a coordinate outside its exact domain
+    ST_BAD_F = 8,    // a source's Dls/Ds outside (0, 1]
+};
 
 // ---------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip translation units).  Each returns the

@@ -8,8 +8,12 @@ model samples) arrive over time.  The scheduler
   * admits the oldest waiting request as soon as a launch slot is free and its
     HBM footprint fits the budget (head-of-line order; a request that cannot
     fit is counted as deferred and waits for completions to free memory),
-  * merges every waiting chi^2 request into one batched launch (up to a sample
-    limit) when a chi^2 request reaches the head of the queue,
+  * merges waiting chi^2 requests into one batched launch when a chi^2 request
+    reaches the head of the queue, up to a sample limit and to what the memory
+    budget still holds,
+  * charges each slot's library scratch to the budget up front, sized by the
+    library's own layout (`HbmAccount`), and each request's buffers while it
+    is in flight,
   * runs admitted work on several streams at once, so requests that arrive
     while others are on the GPU overlap with them on the device,
   * records arrival, admission and completion times, from which it reports
@@ -62,15 +66,20 @@ class Scheduler:
         self.max_merge_samples = max_merge_samples
         self.keep_results = keep_results
 
-    def _group(self, queue):
+    def _group(self, queue, room):
+        """The head request, and when it is a chi^2 batch every later waiting
+        chi^2 request that keeps the merged batch within the sample limit and
+        its footprint within `room` (the budget not in use)."""
         head = queue[0]
         if head.kind != "chi2" or not self.merge_chi2:
             return [head]
-        group, n = [], 0
-        for r in queue:
+        group, n = [head], head.samples
+        for r in list(queue)[1:]:
             if r.kind != "chi2":
                 continue
-            if group and n + r.samples > self.max_merge_samples:
+            if n + r.samples > self.max_merge_samples:
+                break
+            if self.backend.footprint(group + [r]) > room:
                 break
             group.append(r)
             n += r.samples
@@ -106,9 +115,9 @@ class Scheduler:
                     free_slots.append(slot)
                     progressed = True
             while queue and free_slots:
-                group = self._group(queue)
+                group = self._group(queue, self.budget - used)
                 need = self.backend.footprint(group)
-                if need > self.budget:
+                if need > self.budget:  # the head alone: it can never run
                     raise MemoryError(f"request {group[0].id} needs {need} B > budget {self.budget} B")
                 if used + need > self.budget:
                     deferred_ids.add(group[0].id)
@@ -197,20 +206,65 @@ class ScriptedClock:
 
 
 # ---------------------------------------------------------------------------
+class HbmAccount:
+    """The device memory the serving loop charges against its budget.
+
+    Each slot's library context holds scratch that persists between requests
+    (derived tables, per-image constants): it is reserved up front, sized by
+    the library's own layout (lens_map_scratch_bytes, lens_chi2_scratch_bytes)
+    for the largest request a slot may run -- a map of `max_map_pots`
+    potentials or a merged chi^2 batch of `max_merge_samples` samples -- and
+    the context is created with that limit.  A request in flight is charged
+    its own buffers: a map its five output planes; a chi^2 batch its free
+    potentials (physical and amplitude tables, 7 doubles each), offsets and
+    chi^2 values."""
+
+    def __init__(self, map_scratch, chi2_scratch, n_slots, n_fixed, n_sys, n_img,
+                 free_per_sample, max_merge_samples, max_map_pots):
+        self.slot_scratch = max(
+            map_scratch(max_map_pots),
+            chi2_scratch(n_fixed, max_merge_samples * free_per_sample, max_merge_samples, n_sys,
+                         n_img))
+        self.reserved = n_slots * self.slot_scratch
+
+    def budget(self, device_bytes):
+        """Budget left for requests out of `device_bytes` for the server."""
+        b = int(device_bytes) - self.reserved
+        if b <= 0:
+            raise MemoryError(f"{device_bytes} B cannot hold the slots' scratch ({self.reserved} B)")
+        return b
+
+    @staticmethod
+    def map_bytes(side, elem_size):
+        return 5 * side * side * elem_size
+
+    @staticmethod
+    def chi2_bytes(n_samples, n_free):
+        return n_free * 2 * 7 * 8 + (n_samples + 1) * 4 + n_samples * 8
+
+
 class GpuBackend:
     """Runs requests through the C library.  One (stream, context) pair per
     slot; lens models, the chi^2 fixed model and the catalogue are uploaded
     once and stay resident."""
 
     def __init__(self, n_slots=4, prec=0, models=None, map_range=(-100.0, 100.0),
-                 chi2_model=None, zs_map=2.0):
+                 chi2_model=None, zs_map=2.0, max_merge_samples=16384, max_map_pots=1000):
         import torch
 
         from . import binding as B
         from . import inputs
         self.torch, self.B, self.inputs = torch, B, inputs
         self.prec = prec
-        self.slots = [(torch.cuda.Stream(), B.Context(torch.cuda.current_device(), check=False))
+        c3 = chi2_model or inputs.config3(n_samples=1)
+        cat = c3["catalog"]
+        self.account = HbmAccount(B.map_scratch_bytes, B.chi2_scratch_bytes, n_slots,
+                                  len(c3["fixed"]["x0"]), len(cat["off"]) - 1,
+                                  int(cat["off"][-1]), inputs.N_FREE, max_merge_samples,
+                                  max_map_pots)
+        dev = torch.cuda.current_device()
+        self.slots = [(torch.cuda.Stream(),
+                       B.Context(dev, scratch_max=self.account.slot_scratch, check=False))
                       for _ in range(n_slots)]
         self.map_range = map_range
         self.f_map = B.dlsds(inputs.ZL, zs_map)
@@ -218,7 +272,6 @@ class GpuBackend:
         for mid, (npot, seed) in enumerate(models or []):
             phys = B.to_device(inputs.map_request_pots(npot, seed), B.PHYS_KEYS)
             self.models[mid] = B.table_from_physical(phys, 0, self.slots[0][1])
-        c3 = chi2_model or inputs.config3(n_samples=1)
         self.fixed = B.table_from_physical(B.to_device(c3["fixed"], B.PHYS_KEYS), 0,
                                            self.slots[0][1])
         self.cat = B.catalog_to_device(B.catalog_with_dlsds(c3["catalog"], c3["zl"]))
@@ -227,7 +280,7 @@ class GpuBackend:
 
     def default_budget(self):
         free, total = self.torch.cuda.mem_get_info()
-        return int(0.5 * free)
+        return self.account.budget(0.5 * free)
 
     # host payload of a chi^2 request: its samples drawn from the priors
     # (what a client sends); prepare() builds them before the stream starts
@@ -242,11 +295,10 @@ class GpuBackend:
 
     def footprint(self, group):
         if group[0].kind == "map":
-            r = group[0]
-            esz = 8 if self.prec == 0 else 4
-            return 5 * r.side * r.side * esz + (1 << 20)
+            return HbmAccount.map_bytes(group[0].side, 8 if self.prec == 0 else 4)
         n = sum(r.samples for r in group)
-        return n * (8 + 4 + 6 * 7 * 8 * 2 + 6 * 200) + (1 << 20)
+        nfree = sum(len(self.chi2_samples(r)[0]["x0"]) for r in group)
+        return HbmAccount.chi2_bytes(n, nfree)
 
     def grid(self, side):
         lo, hi = self.map_range

@@ -3,12 +3,17 @@ against the FP64 oracle, through the C ABI.
 
 Stage-isolated: the GPU search is fed the oracle's deflection grid and
 sources, so every decision and every interpolated position must be
-bit-identical.  End to end: the GPU computes its own deflections; image counts
-must be identical except for systems whose source lies within a certified
-margin of a triangle edge (none are expected), positions agree to 1e-7".
+bit-identical.  End to end: the GPU computes its own deflections, which may
+differ from the oracle's by the map tolerance (rtol times the scale); image
+counts must be identical except for systems whose source the oracle
+certifies within that error bound of a triangle edge, and every position and
+chi^2 must lie within the bound that tolerance implies (lensutil,
+compare_image_plane).
 """
 import numpy as np
 import pytest
+
+from lensutil import RTOL, compare_image_plane
 
 pytestmark = pytest.mark.gpu
 
@@ -105,6 +110,29 @@ def test_sources_on_vertices_and_edges(B, ctx, oracle, truth):
     compare_exact(oracle, ax, ay, grid, sx, sy, fs, got)
 
 
+def test_search_rejects_bad_dlsds_and_coordinates_outside_the_exact_domain(B, ctx, oracle):
+    """A source's Dls/Ds outside (0, 1] and a coordinate outside the exact
+    predicate's domain (here a source 2^-500 from a vertex, on an edge, so the
+    exact expansion runs) are reported as LENS_EINVAL after the search; the
+    other sources of the same call are still searched correctly."""
+    grid = (9, 9, -2.0, -2.0, 0.5, 0.5)
+    zero = np.zeros((9, 9))
+    sx, sy = [0.3, 0.3, 0.3], [0.2, 0.2, 0.2]
+    for bad in (0.0, -0.5, 1.5, float("nan")):
+        with pytest.raises(B.LensError) as e:
+            gpu_find(B, ctx, zero, zero, grid, sx, sy, [1.0, bad, 0.8])
+        assert e.value.status == -1 and "Dls/Ds" in str(e.value)
+    n, tri, ix, iy, over = gpu_find(B, ctx, zero, zero, grid, sx, sy, [1.0, 1.0, 0.8])
+    assert list(n) == [1, 1, 1]
+    with pytest.raises(B.LensError) as e:
+        gpu_find(B, ctx, zero, zero, grid, [0.3, 2.0 ** -500], [0.2, 0.0], [1.0, 1.0])
+    assert e.value.status == -1 and "exact domain" in str(e.value)
+    # a tiny coordinate whose tests the floating-point filter decides (the
+    # source strictly above a grid line) needs no expansion: accepted
+    n, *_ = gpu_find(B, ctx, zero, zero, grid, [0.3], [2.0 ** -500], [1.0])
+    assert list(n) == [1]
+
+
 def device_model(B, ctx, c):
     fixed = B.table_from_physical(B.to_device(c["fixed"], B.PHYS_KEYS), 0, ctx)
     free = B.table_from_physical(B.to_device(c["free"], B.PHYS_KEYS), 0, ctx)
@@ -128,39 +156,17 @@ def oracle_image_chi2(O, c, grid, m0, m1, kmax, penalty, alpha_fix=None):
                         alpha_fix=alpha_fix), cat
 
 
-def compare_image_results(O, c, grid, got, ref, cat, samples, m0):
-    """Counts identical unless the oracle certifies the source within 1e-9" of
-    a triangle edge; stored positions within 1e-7"; chi^2 within the error the
-    position tolerance allows."""
+def check_against_oracle(O, c, grid, got, ref, cat, samples, m0, prec=0, penalty=100.0):
     fixed, free = O.phys_to_pots(c["fixed"]), O.phys_to_pots(c["free"])
-    flagged = 0
-    worst_pos = worst_chi2 = 0.0
-    for r, m in enumerate(samples):
-        s = m - m0
-        mism = np.nonzero(got["nimg"][m] != ref["nimg"][s])[0]
-        if len(mism):
-            model = {k: np.concatenate([fixed[k], free[k][c["free_off"][m]:c["free_off"][m + 1]]])
-                     for k in fixed}
-            ax, ay = O.alpha_grid(model, grid)
-            sx, sy = O.sources(fixed, free, c["free_off"], m, cat)
-            for i in mism:
-                margin = O.edge_margin(ax, ay, grid, cat["f"][i], sx[i], sy[i])
-                assert margin < 1e-9, (m, i, got["nimg"][m, i], ref["nimg"][s, i], margin)
-                flagged += 1
-            continue
-        kmax = ref["x"].shape[2]
-        for i in range(got["nimg"].shape[1]):
-            k = min(ref["nimg"][s, i], kmax)
-            d = np.hypot(got["img_xy"][m, i, :k, 0] - ref["x"][s, i, :k],
-                         got["img_xy"][m, i, :k, 1] - ref["y"][s, i, :k])
-            assert np.all(d < 1e-7), (m, i, d)
-            worst_pos = max(worst_pos, float(d.max()) if d.size else 0.0)
-        assert got["nmissing"][m] == ref["nmiss"][s]
-        assert abs(got["chi2"][m] - ref["chi2"][s]) <= 1e-6 * max(1.0, ref["chi2"][s]), (
-            m, got["chi2"][m], ref["chi2"][s])
-        worst_chi2 = max(worst_chi2, abs(got["chi2"][m] - ref["chi2"][s]) / max(1.0, ref["chi2"][s]))
-    compare_image_results.last = (worst_pos, worst_chi2)
-    return flagged
+    return compare_image_plane(O, fixed, free, np.asarray(c["free_off"]), cat, grid, got, ref,
+                               samples, m0, RTOL[prec], penalty)
+
+
+def report(what, st):
+    print(f"{what}: {st['images']} images, max position error {st['pos_err']:.3g} arcsec "
+          f"({st['pos_ratio']:.3g} of its bound), chi2 error {st['chi2_rel']:.3g} relative "
+          f"({st['chi2_ratio']:.3g} of its bound); systems certified near an edge "
+          f"{st['excused']}, assignment near ties {st['near_tie']}")
 
 
 def test_image_chi2_end_to_end_small_grid(B, ctx, oracle):
@@ -170,10 +176,9 @@ def test_image_chi2_end_to_end_small_grid(B, ctx, oracle):
     got = run_gpu_image_chi2(B, ctx, c, grid, 16, 100.0)
     assert not got["overflow"]
     ref, cat = oracle_image_chi2(oracle, c, grid, 0, 8, 16, 100.0)
-    flagged = compare_image_results(oracle, c, grid, got, ref, cat, range(8), 0)
-    pos, rel = compare_image_results.last
-    print(f"image chi2 FP64 end to end: flagged near-edge systems {flagged}, max image position "
-          f"error {pos:.3g} arcsec, max chi2 error {rel:.3g} (relative, floor 1)")
+    st = check_against_oracle(oracle, c, grid, got, ref, cat, range(8), 0)
+    report("image chi2 FP64 end to end, 250^2", st)
+    assert st["images"] >= 100
     # the per-sample path gives identical results
     per = run_gpu_image_chi2(B, ctx, c, grid, 16, 100.0, path=B.PATH_PER_SAMPLE)
     assert np.array_equal(per["chi2"], got["chi2"]) and np.array_equal(per["nimg"], got["nimg"])
@@ -199,21 +204,7 @@ def test_image_chi2_uneven_and_empty_samples(B, ctx, oracle):
     assert np.array_equal(per["chi2"], got["chi2"]) and np.array_equal(per["nimg"], got["nimg"])
     for m in (1, 2, 8):
         ref, cat = oracle_image_chi2(oracle, c, grid, m, m + 1, 16, 100.0)
-        compare_image_results(oracle, c, grid, got, ref, cat, [m], m)
-
-
-def test_image_chi2_fp32_error_table(B, ctx, oracle):
-    """FP32 deflections: multiplicity mismatches and chi^2 error against FP64."""
-    from paper_2004_06352_amd import inputs
-    c = inputs.config3(n_samples=16)
-    grid = inputs.pixel_centre_grid(250, -75.0, 75.0)
-    g64 = run_gpu_image_chi2(B, ctx, c, grid, 16, 100.0, prec=0)
-    g32 = run_gpu_image_chi2(B, ctx, c, grid, 16, 100.0, prec=1)
-    mism = int(np.sum(g64["nimg"] != g32["nimg"]))
-    rel = np.abs(g32["chi2"] - g64["chi2"]) / np.maximum(g64["chi2"], 1.0)
-    print(f"FP32 vs FP64: {mism} of {g64['nimg'].size} multiplicities differ; "
-          f"chi2 rel err max {rel.max():.3g} median {np.median(rel):.3g}")
-    assert mism <= 0.02 * g64["nimg"].size
+        check_against_oracle(oracle, c, grid, got, ref, cat, [m], m)
 
 
 def test_overflow_keeps_counts_exact(B, ctx, oracle):
@@ -228,23 +219,41 @@ def test_overflow_keeps_counts_exact(B, ctx, oracle):
 
 def test_config4_full_size_sampled(B, oracle):
     """1000^2 grid, 512 samples in the benchmark's launch configuration
-    (unchecked context, batched path); two samples against the oracle."""
+    (unchecked context, batched path), FP64 and FP32 evaluation; samples 0, 1
+    and 511 of each against the oracle under the bounds of their tolerance
+    (1e-12 and 1e-5 of the deflection scale), and the FP32 run against the
+    FP64 one over all 512 samples (multiplicities and chi^2)."""
     from paper_2004_06352_amd import inputs
     c = inputs.config4()
     uctx = B.Context(0, check=False)
-    got = run_gpu_image_chi2(B, uctx, c, c["grid"], 64, 100.0)
+    runs = {prec: run_gpu_image_chi2(B, uctx, c, c["grid"], 64, 100.0, prec=prec)
+            for prec in (0, 1)}
     uctx.status()
-    print("max images per system:", got["nimg"].max(), "overflow:", got["overflow"])
-    assert got["nimg"].shape == (512, 60)
+    uctx.close()
+    for prec, got in runs.items():
+        print(f"prec {prec}: max images per system {got['nimg'].max()}, overflow {got['overflow']}")
+        assert got["nimg"].shape == (512, 60) and got["nimg"].max() <= 64
     fixed = oracle.phys_to_pots(c["fixed"])
     afix = oracle.alpha_grid(fixed, c["grid"])
-    for m in (0, 1, 511):
-        ref, cat = oracle_image_chi2(oracle, c, c["grid"], m, m + 1, 64, 100.0, alpha_fix=afix)
-        if got["nimg"][m].max() > 64:
-            assert np.array_equal(got["nimg"][m], ref["nimg"][0])
-            continue
-        compare_image_results(oracle, c, c["grid"], got, ref, cat, [m], m)
-    uctx.close()
+    samples = (0, 1, 511)
+    refs = {m: oracle_image_chi2(oracle, c, c["grid"], m, m + 1, 64, 100.0, alpha_fix=afix)
+            for m in samples}
+    for prec, name in ((0, "FP64"), (1, "FP32 evaluation")):
+        agg = None
+        for m in samples:
+            ref, cat = refs[m]
+            st = check_against_oracle(oracle, c, c["grid"], runs[prec], ref, cat, [m], m,
+                                      prec=prec)
+            agg = st if agg is None else {k: (agg[k] + st[k] if k in ("images", "excused",
+                                                                      "near_tie")
+                                              else max(agg[k], st[k])) for k in st}
+        report(f"config 4 {name} vs oracle, samples {samples}", agg)
+        assert agg["images"] >= 300
+    g64, g32 = runs[0], runs[1]
+    mism = int(np.sum(g64["nimg"] != g32["nimg"]))
+    rel = np.abs(g32["chi2"] - g64["chi2"]) / np.maximum(g64["chi2"], 1.0)
+    print(f"config 4 FP32 vs FP64 over 512 samples: {mism} of {g64['nimg'].size} multiplicities "
+          f"differ; chi2 relative difference max {rel.max():.3g}, median {np.median(rel):.3g}")
 
 
 REFINE = (20, 1e-10)

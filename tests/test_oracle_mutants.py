@@ -51,6 +51,23 @@ MUTANTS = [
     ("prior box ignored", "if (!(pr[i] >= lo[i] && pr[i] <= hi[i])) in = 0;", "(void)0;"),
     ("asymmetric proposal", "pr[i] = th[i] + step[i] * (2.0 * uw[i] - 1.0);",
      "pr[i] = th[i] + step[i] * (2.0 * uw[i] - 0.9);"),
+    ("edge margin without the anti-diagonal", "if (i + 1 >= nx || j + 1 >= ny) continue;",
+     "continue;"),
+    ("edge margin without the segment clamp",
+     "if (tt < 0) tt = 0;\n                if (tt > 1) tt = 1;\n                double qx = x1",
+     "double qx = x1"),
+    ("edge margin without the anti-diagonal's clamp",
+     "if (tt < 0) tt = 0;\n                    if (tt > 1) tt = 1;\n                    double qx = xa",
+     "double qx = xa"),
+    ("edge margin skips the last row",
+     "    for (j = 0; j < ny; j++) {\n        for (i = 0; i < nx; i++) {\n            /* edges from",
+     "    for (j = 0; j < ny - 1; j++) {\n        for (i = 0; i < nx; i++) {\n            /* edges from"),
+    ("edge margin deflection of the wrong vertex",
+     "double y2 = grid_coord(gy0, j2, dy) - f * ay[id2];",
+     "double y2 = grid_coord(gy0, j2, dy) - f * ay[id];"),
+    ("edge margin without Dls/Ds on the anti-diagonal",
+     "double xa = grid_coord(gx0, i + 1, dx) - f * ax[ia];",
+     "double xa = grid_coord(gx0, i + 1, dx) - ax[ia];"),
     ("ellipticity conversion", "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 - e * e)); }",
      "double or_eps_from_e(double e) { return e / (1.0 + sqrt(1.0 + e * e)); }"),
 ]
@@ -70,6 +87,7 @@ PINS = [
     (pins.test_zero_lens_gives_one_image_at_the_source, {}),
     (pins.test_cored_isothermal_images_and_odd_multiplicity, {}),
     (pins.test_assignment_rules, {}),
+    (pins.test_edge_margin_closed_forms, {}),
     (pins.test_source_chi2_zero_lens_closed_form, {}),
     (pins.test_image_chi2_zero_lens_closed_form, {}),
     (pins.test_derived_sis_closed_form, {}),

@@ -435,6 +435,66 @@ def test_cored_isothermal_images_and_odd_multiplicity(oracle):
             assert abs(g - r) < 0.05
 
 
+def grid_edge_distance(grid, px, py):
+    """Distance from (px, py) to the nearest triangle edge of an unlensed grid
+    split into T0/T1 by the anti-diagonal of each cell, in closed form: inside
+    the grid's rectangle the nearest edge is one of the containing cell's four
+    sides or its anti-diagonal u + v = 1 (local coordinates u, v in [0, 1]);
+    outside it, the rectangle's boundary is made of edges, so the distance is
+    the distance to the rectangle."""
+    nx, ny, x0, y0, dx, dy = grid
+    X1, Y1 = x0 + (nx - 1) * dx, y0 + (ny - 1) * dy
+    ox = max(x0 - px, 0.0, px - X1)
+    oy = max(y0 - py, 0.0, py - Y1)
+    if ox > 0 or oy > 0:
+        return math.hypot(ox, oy)
+    i = min(max(int(math.floor((px - x0) / dx)), 0), nx - 2)
+    j = min(max(int(math.floor((py - y0) / dy)), 0), ny - 2)
+    u, v = (px - (x0 + i * dx)) / dx, (py - (y0 + j * dy)) / dy
+    diag = abs(u + v - 1.0) * dx * dy / math.hypot(dx, dy)
+    return min(u * dx, (1 - u) * dx, v * dy, (1 - v) * dy, diag)
+
+
+def test_edge_margin_closed_forms(oracle):
+    """The margin of a source to the nearest triangle edge of the unlensed
+    grid (the certificate that excuses a multiplicity difference between two
+    evaluations): with no lens the closed form above, at random points, on
+    vertices, grid lines and anti-diagonals (margin 0), past the last column
+    and row and past the corners; with a uniform deflection c the grid is
+    translated by -f c; with a mass sheet alpha = (k1 x, k2 y) it is rescaled
+    by (1 - f k1, 1 - f k2), which exercises the per-vertex deflection."""
+    grid = (13, 11, -3.0, -2.5, 0.5, 0.4)
+    nx, ny, x0, y0, dx, dy = grid
+    X1, Y1 = x0 + (nx - 1) * dx, y0 + (ny - 1) * dy
+    zero = np.zeros((ny, nx))
+    pts = [(RNG.uniform(x0 - 1, X1 + 1), RNG.uniform(y0 - 1, Y1 + 1)) for _ in range(300)]
+    pts += [(x0 + 3 * dx, y0 + 4 * dy), (x0 + 5.5 * dx, y0 + 2 * dy), (x0 + 7 * dx, y0 + 0.3 * dy),
+            (x0 + 4.25 * dx, y0 + 6.75 * dy),    # on an anti-diagonal
+            (x0 + 2.2 * dx, y0 + 0.75 * dy),     # nearest edge: the anti-diagonal
+            (X1 + 0.3, y0 + 4.5 * dy), (x0 + 6.5 * dx, Y1 + 0.2), (X1 + 0.3, Y1 + 0.4),
+            (x0 - 0.2, y0 - 0.1), (X1 - 0.05, y0 + 5.5 * dy), (x0 + 6.5 * dx, Y1 - 0.03)]
+    for px, py in pts:
+        want = grid_edge_distance(grid, px, py)
+        got = oracle.edge_margin(zero, zero, grid, 0.7, px, py)
+        assert got == pytest.approx(want, abs=1e-12), (px, py, got, want)
+    # a uniform deflection: the unlensed grid is the grid moved by -f c
+    f, cx, cy = 0.6, 1.7, -0.9
+    for px, py in pts[:120]:
+        want = grid_edge_distance(grid, px + f * cx, py + f * cy)
+        got = oracle.edge_margin(zero + cx, zero + cy, grid, f, px, py)
+        assert got == pytest.approx(want, abs=1e-12)
+    # an anisotropic mass sheet: unlensed vertex (1 - f k1) x, (1 - f k2) y
+    k1, k2 = 0.35, -0.2
+    xs, ys = x0 + np.arange(nx) * dx, y0 + np.arange(ny) * dy
+    X, Y = np.meshgrid(xs, ys)
+    sx, sy = 1 - f * k1, 1 - f * k2
+    sheet = (nx, ny, x0 * sx, y0 * sy, dx * sx, dy * sy)
+    for px, py in pts[:120] + pts[300:]:
+        want = grid_edge_distance(sheet, px, py)
+        got = oracle.edge_margin(k1 * X, k2 * Y, grid, f, px, py)
+        assert got == pytest.approx(want, abs=1e-12)
+
+
 def test_assignment_rules(oracle):
     cx, cy, sig = [0.0, 1.0, 5.0], [0.0, 0.0, 0.0], [0.5, 0.5, 1.0]
     # image 0 nearest constraint 0, image 1 nearest constraint 1, none for 2

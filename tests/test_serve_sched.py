@@ -111,3 +111,63 @@ def test_request_stream_generator():
     assert all(r["side"] in (512, 1024, 2048, 4096) for r in rs if r["kind"] == "map")
     assert all(50 <= r["npot"] <= 1000 for r in rs if r["kind"] == "map")
     Req.from_dict(rs[0])
+
+
+def test_merging_stops_at_the_memory_budget():
+    """Six waiting chi^2 requests of 10 B each under a 50 B budget: the merged
+    batch takes the five that fit and the sixth runs after it; no request is
+    refused, the budget is never exceeded."""
+    clock = ScriptedClock()
+    be = make(clock, budget=50)
+    chis = [Req(i, 0.0, "chi2", samples=10) for i in range(6)]
+    st = Scheduler(be, n_slots=2).run(chis, clock=clock, sleep=clock.sleep)
+    assert [ids for _, _, ids in be.launched] == [[0, 1, 2, 3, 4], [5]]
+    assert st["peak_bytes"] <= 50 and all(r.done is not None for r in chis)
+
+
+def test_head_chi2_request_over_the_free_room_waits():
+    """A map holds most of the budget; the chi^2 request behind it is not
+    merged beyond the room left and waits for the map to finish."""
+    clock = ScriptedClock()
+    be = make(clock, budget=120)
+    reqs = [Req(0, 0.0, "map", side=512, model=0, npot=10)] + \
+        [Req(i, 0.0, "chi2", samples=10) for i in range(1, 4)]
+    st = Scheduler(be, n_slots=2).run(reqs, clock=clock, sleep=clock.sleep)
+    groups = [ids for _, _, ids in be.launched]
+    assert groups[0] == [0] and groups[1] == [1, 2]
+    assert st["peak_bytes"] <= 120
+
+
+def test_scratch_accounting_with_the_library_sizes():
+    """The slots' context scratch is sized by the library (host arithmetic,
+    no device) for the largest map and merged chi^2 batch, reserved up front,
+    and the requests' own buffers are charged against what remains: with a
+    device share that holds the reservation plus two maps, a third map
+    waits, and reservation + peak never exceed the share."""
+    from paper_2004_06352_amd import binding as B
+    from paper_2004_06352_amd import inputs
+    from paper_2004_06352_amd.serve import HbmAccount
+    c3 = inputs.config3(n_samples=1)
+    nsys, nimg = len(c3["catalog"]["off"]) - 1, int(c3["catalog"]["off"][-1])
+    acc = HbmAccount(B.map_scratch_bytes, B.chi2_scratch_bytes, 4, 300, nsys, nimg,
+                     inputs.N_FREE, 16384, 1000)
+    # the library's layout: derived constants of 35 doubles + 19 floats per
+    # potential (tables padded to 64 entries), per-image constants
+    assert B.map_scratch_bytes(1000) == 1024 * 356
+    chi2 = B.chi2_scratch_bytes(300, 16384 * 6, 16384, nsys, nimg)
+    assert chi2 >= 320 * 356 + 16384 * 6 * 356 + 3 * nimg * 8
+    assert acc.slot_scratch == max(1024 * 356, chi2) and acc.reserved == 4 * acc.slot_scratch
+    with pytest.raises(MemoryError):
+        acc.budget(acc.reserved)
+    map_b = HbmAccount.map_bytes(1024, 8)
+    share = acc.reserved + 2 * map_b + map_b // 2
+    clock = ScriptedClock()
+    be = FakeBackend(clock, lambda g: 0.01,
+                     lambda g: (HbmAccount.map_bytes(g[0].side, 8) if g[0].kind == "map"
+                                else HbmAccount.chi2_bytes(sum(r.samples for r in g),
+                                                           6 * sum(r.samples for r in g))),
+                     acc.budget(share))
+    reqs = [Req(i, 0.0, "map", side=1024, model=0, npot=100) for i in range(3)] + \
+        [Req(3, 0.0, "chi2", samples=4096)]
+    st = Scheduler(be, n_slots=4).run(reqs, clock=clock, sleep=clock.sleep)
+    assert st["deferred"] >= 1 and acc.reserved + st["peak_bytes"] <= share
