@@ -261,6 +261,29 @@ def chi2_legs(args, ctx, secondary, torch, B, inputs):
     secondary["chi2_image_workload"] = c4["name"]
 
 
+def chi2_source_only(args, ctx, torch, B, inputs):
+    """Profiling aid: the batched source-plane chi^2 call and the sampler step
+    on the workload-3 batch, `args.steps` of each after one warm-up."""
+    c3 = inputs.config3()
+    cat = B.catalog_to_device(B.catalog_with_dlsds(c3["catalog"], c3["zl"]))
+    fixed = B.table_from_physical(B.to_device(c3["fixed"], B.PHYS_KEYS), 0, ctx)
+    free = B.table_from_physical(B.to_device(c3["free"], B.PHYS_KEYS), 0, ctx)
+    off = torch.as_tensor(c3["free_off"], dtype=torch.int32, device="cuda")
+    S = int(off.numel()) - 1
+    w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, ctx=ctx), args.steps, 1,
+                       torch, per_step=False)
+    sm = inputs.sampler_start(n_walkers=4096)
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    um = dev(inputs.sampler_uniforms(np.random.default_rng(9), sm["params"].shape[0], 6))
+    mc = B.Mcmc(fixed, cat, dev(sm["params"]), dev(sm["lo"]), dev(sm["hi"]), dev(sm["step"]),
+                um, ctx=ctx)
+    wm, em = timed_steps(mc.step, args.steps, 1, torch, per_step=False)
+    mc.close()
+    log(json.dumps({"chi2_source_batched_us_per_call": e * 1e6,
+                    "chi2_source_batched_samples_per_s": S / e,
+                    "mcmc_us_per_step": em * 1e6}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +301,9 @@ def main():
     ap.add_argument("--skip-map", action="store_true",
                     help="profiling aid: no map timing; the chi^2 legs only (no JSON line)")
     ap.add_argument("--no-image", action="store_true", help="skip the image-plane chi^2 legs")
+    ap.add_argument("--only-chi2-source", action="store_true",
+                    help="profiling aid: `--steps` batched source-plane chi^2 calls on the "
+                         "4096-sample batch and as many sampler steps, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
@@ -291,6 +317,9 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = B.Context(0, check=False)
+    if args.only_chi2_source:
+        chi2_source_only(args, ctx, torch, B, inputs)
+        return
     c2 = inputs.config2()
     f = B.dlsds(c2["zl"], c2["zs"])
     phys = B.to_device(c2["pots"], B.PHYS_KEYS)
@@ -358,7 +387,8 @@ def main():
     exe = measured_executed_flop()
     if exe is not None:
         # the executed-instruction view of the same launches (counters taken on
-        # the one-pixel-per-thread shape): FP64 vector work actually issued
+        # 64x4 blocks with two pixels per thread, the autotuner's pick here):
+        # FP64 vector work actually issued
         rec["roofline"]["executed_flop_per_launch"] = exe
         rec["roofline"]["executed_frac"] = exe / ev / 1e12 / PEAK_FP64_TFLOPS
     secondary = {}

@@ -32,7 +32,7 @@ PHYS_KEYS = ("x0", "y0", "sigma", "e", "phi", "rcore", "rcut")
 ZL = 0.4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-CATALOG_PATH = os.path.join(os.path.dirname(_HERE), "tests", "golden", "cfg3_catalog.txt")
+CATALOG_PATH = os.path.join(_HERE, "data", "cfg3_catalog.txt")
 
 
 def pixel_centre_grid(n: int, lo: float, hi: float):

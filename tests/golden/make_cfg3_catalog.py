@@ -1,6 +1,6 @@
-"""Write ``cfg3_catalog.txt``: the multiple-image constraint catalogue of the
-config-3 lens model (6 free dPIEs at their prior midpoints + 300 fixed galaxy
-dPIEs, zl = 0.4).
+"""Write ``paper_2004_06352_amd/data/cfg3_catalog.txt``: the multiple-image
+constraint catalogue of the config-3 lens model (6 free dPIEs at their prior
+midpoints + 300 fixed galaxy dPIEs, zl = 0.4).
 
 Uses the oracle only (test infrastructure):
   1. deflection of the true model on a 1500^2 pixel-centre grid over [-75, 75]^2;
@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 from oracle import oracle as O  # noqa: E402
 from paper_2004_06352_amd import inputs  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg3_catalog.txt")
+OUT = os.path.join(ROOT, "paper_2004_06352_amd", "data", "cfg3_catalog.txt")
 N_SYS = 60
 SIGMA = 0.05
 
