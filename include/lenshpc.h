@@ -230,6 +230,27 @@ lens_status_t lens_hessian_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
                                void *hxx, void *hxy, void *hyy, void *ax, void *ay,
                                void *stream);
 
+/* lens_hessian_map without device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Arguments, results and errors are those of
+ * lens_hessian_map; the context's scratch is neither used nor grown.  The
+ * potentials' derived constants go instead to a fixed array of device memory
+ * that the library holds on each device from load to process exit
+ * (LENS_NOALLOC_MAX_POT potentials, 356 bytes each: 2.8 MiB per device).
+ *   - A table of more than LENS_NOALLOC_MAX_POT potentials is LENS_ENOMEM,
+ *     detected before anything is launched.
+ *   - Every call on one device uses that device's one array, whatever the
+ *     context or stream: calls that overlap on a device race and must be
+ *     ordered by the caller (one stream, or events between streams).  The
+ *     array is fully rewritten by each call before it is read.
+ *   - The call itself allocates nothing (checked contexts still synchronise
+ *     `stream` once, as lens_hessian_map does). */
+#define LENS_NOALLOC_MAX_POT 8192
+lens_status_t lens_hessian_map_noalloc(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                                       const lens_grid_t *grid, double dlsds,
+                                       lens_precision_t prec, void *hxx, void *hxy, void *hyy,
+                                       void *ax, void *ay, void *stream);
+
 /* Lensing potential psi = dlsds * sum_k psi_k (alpha = grad psi, Sec. 2.1;
  * one of the lensing maps of Sec. 2.4), FP64 only (psi must be nx*ny
  * doubles; other precisions return LENS_EUNSUPPORTED).  Each cored isothermal

@@ -36,7 +36,7 @@ PHYS_KEYS = ("x0", "y0", "sigma", "e", "phi", "rcore", "rcut")
 EXPORTS = ("lens_ctx_create", "lens_ctx_destroy", "lens_ctx_status", "lens_set_map_tuning",
            "lens_get_map_tuning", "lens_set_chi2_tuning", "lens_get_chi2_tuning",
            "lens_table_from_physical", "lens_grad_map",
-           "lens_hessian_map", "lens_derived_map", "lens_potential_map", "lens_time_delay_map",
+           "lens_hessian_map", "lens_hessian_map_noalloc", "lens_derived_map", "lens_potential_map", "lens_time_delay_map",
            "lens_time_delay_scale", "lens_chi2_batch", "lens_find_images",
            "lens_chi2_plan_create", "lens_chi2_plan_create_ex",
            "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_mcmc_create",
@@ -119,6 +119,8 @@ def lib():
         L.lens_grad_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp, vp]
         L.lens_hessian_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp,
                                        vp, vp, vp, vp]
+        L.lens_hessian_map_noalloc.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32,
+                                               vp, vp, vp, vp, vp, vp]
         L.lens_derived_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp,
                                        vp, vp, vp, vp, vp]
         L.lens_potential_map.argtypes = [vp, C.POINTER(_Pot), C.POINTER(_Grid), dbl, i32, vp, vp]
@@ -292,6 +294,23 @@ def hessian_map(table, grid, dlsds=1.0, prec=FP64, with_alpha=True, ctx=None, ou
     _check(lib().lens_hessian_map(ctx.handle, C.byref(T), C.byref(G), float(dlsds), prec,
                                   _ptr(out["hxx"]), _ptr(out["hxy"]), _ptr(out["hyy"]),
                                   _ptr(out.get("ax")), _ptr(out.get("ay")), _stream(dev)))
+    return out
+
+
+# the allocation-free call's table limit (LENS_NOALLOC_MAX_POT)
+NOALLOC_MAX_POT = 8192
+
+
+def hessian_map_noalloc(table, grid, dlsds=1.0, prec=FP64, ctx=None, out=None):
+    """lens_hessian_map_noalloc into the caller's planes `out` (dict hxx, hxy,
+    hyy and optionally ax, ay); the library allocates nothing for the call."""
+    ctx = _ctx(ctx)
+    dev = table["x0"].device
+    T, G = _pot(table), _grid(grid)
+    _check(lib().lens_hessian_map_noalloc(ctx.handle, C.byref(T), C.byref(G), float(dlsds),
+                                          prec, _ptr(out["hxx"]), _ptr(out["hxy"]),
+                                          _ptr(out["hyy"]), _ptr(out.get("ax")),
+                                          _ptr(out.get("ay")), _stream(dev)))
     return out
 
 

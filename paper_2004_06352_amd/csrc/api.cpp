@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -69,6 +70,21 @@ struct lens_chi2_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+
+// Device memory of the allocation-free map call: the derived constants of at
+// most LENS_NOALLOC_MAX_POT potentials, laid out as a context's derived table
+// of that many entries.  Each device holds its own copy for the life of the
+// process.  Host code never passes `scratch` itself (its host-side name is
+// not a device address): the address of each device's copy is looked up once
+// per device when a context is created there, and only that address is used.
+constexpr size_t kNoallocBytes =
+    (size_t)LENS_NOALLOC_MAX_POT * (lens::NDER * sizeof(double) + lens::NDERF * sizeof(float));
+static_assert(LENS_NOALLOC_MAX_POT % 64 == 0, "a derived table's stride is a multiple of 64");
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[kMaxDevices] = {};
 
 namespace {
 
@@ -210,9 +226,32 @@ lens_status_t status_check(lens_ctx_t *ctx, hipStream_t st) {
     return LENS_OK;
 }
 
+// Address of this device's copy of `scratch`, looked up once per device with
+// the device current (context creation calls this).
+lens_status_t noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices)
+        return fail(LENS_EUNSUPPORTED, "device %d: the allocation-free call supports devices "
+                    "0..%d", device, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return LENS_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+        (void)hipGetLastError();
+        return fail(LENS_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                    hipGetErrorString(e));
+    }
+    g_noalloc_ptr[device] = p;
+    return LENS_OK;
+}
+
+// The map calls.  `fixed_scratch` (the allocation-free call): the derived
+// table goes to that device memory, sized for LENS_NOALLOC_MAX_POT entries,
+// instead of the context's scratch.
 lens_status_t map_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const lens_grid_t *grid,
                          double dlsds, lens_precision_t prec, void *out[5], bool grad, bool hess,
-                         hipStream_t st, void *const *dout = nullptr) {
+                         hipStream_t st, void *const *dout = nullptr,
+                         char *fixed_scratch = nullptr) {
     if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
     TRY(check_prec(prec));
     TRY(check_table(table, "table"));
@@ -229,10 +268,20 @@ lens_status_t map_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const l
             if (dout[c]) TRY(check_range(dout[c], np * esz, dnames[c]));
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
-    Carve cv;
-    const size_t o_tab = cv.take(derived_bytes(table->n));
-    TRY(ensure_scratch(ctx, cv.off));
-    const Derived D = derived_at(ctx, o_tab, table->n);
+    Derived D;
+    if (fixed_scratch) {
+        if (table->n > LENS_NOALLOC_MAX_POT)
+            return fail(LENS_ENOMEM, "table of %d potentials: the allocation-free call holds at "
+                        "most %d", table->n, LENS_NOALLOC_MAX_POT);
+        // the same layout as a context table of n entries (stride from n),
+        // which fits in the space of LENS_NOALLOC_MAX_POT entries
+        D = derived_in(fixed_scratch, 0, table->n);
+    } else {
+        Carve cv;
+        const size_t o_tab = cv.take(derived_bytes(table->n));
+        TRY(ensure_scratch(ctx, cv.off));
+        D = derived_at(ctx, o_tab, table->n);
+    }
     TRY(status_reset(ctx, st));
     TRY(run_prologue(ctx, table, D, st));
     TRY(status_check(ctx, st));
@@ -510,6 +559,7 @@ lens_status_t lens_ctx_create(int32_t device, uint64_t scratch_bytes_max, uint32
     if (flags & ~LENS_CTX_CHECK_TABLES) return fail(LENS_EINVAL, "unknown flags 0x%x", flags);
     DeviceGuard dg(device);
     if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", device);
+    TRY(noalloc_setup(device));
     lens_ctx_t *c = new lens_ctx_t();
     c->device = device;
     c->scratch_max = scratch_bytes_max;
@@ -631,6 +681,26 @@ lens_status_t lens_hessian_map(lens_ctx_t *ctx, const lens_pot_table_t *table,
     void *out[5] = {ax, ay, hxx, hxy, hyy};
     return map_common(ctx, table, grid, dlsds, prec, out, ax != nullptr, true,
                       (hipStream_t)stream);
+}
+
+lens_status_t lens_hessian_map_noalloc(lens_ctx_t *ctx, const lens_pot_table_t *table,
+                                       const lens_grid_t *grid, double dlsds,
+                                       lens_precision_t prec, void *hxx, void *hxy, void *hyy,
+                                       void *ax, void *ay, void *stream) {
+    if (!ctx) return fail(LENS_EINVAL, "ctx is NULL");
+    if (!hxx || !hxy || !hyy) return fail(LENS_EINVAL, "hxx, hxy and hyy are required");
+    if ((ax == nullptr) != (ay == nullptr))
+        return fail(LENS_EINVAL, "ax and ay must both be given or both be NULL");
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (ctx->device >= 0 && ctx->device < kMaxDevices)
+            base = static_cast<char *>(g_noalloc_ptr[ctx->device]);
+    }
+    if (!base) return fail(LENS_EDEVICE, "no fixed scratch on device %d", ctx->device);
+    void *out[5] = {ax, ay, hxx, hxy, hyy};
+    return map_common(ctx, table, grid, dlsds, prec, out, ax != nullptr, true,
+                      (hipStream_t)stream, nullptr, base);
 }
 
 // Potential (td = 0) or time-delay (td = 1) map: validation, prologue, kernel.
