@@ -377,7 +377,7 @@ SrcPlan plan_src(Carve &cv, const lens_model_batch_t *b, const lens_catalog_t *c
     p.nimg_pad = (c->n_img + 63) / 64 * 64;
     p.o_fix = cv.take(derived_bytes(b->fixed.n));
     p.o_free = cv.take(derived_bytes(b->free.n));
-    p.o_rec = cv.take((size_t)3 * p.nimg_pad * sizeof(double));
+    p.o_rec = cv.take((size_t)CHI2_REC_ROWS * p.nimg_pad * sizeof(double));
     p.o_src = sources ? cv.take((size_t)std::max(b->n_samples, 1) * c->n_sys * 2 * sizeof(double))
                       : 0;
     return p;
@@ -1092,7 +1092,7 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
     sp.nimg_pad = (c->n_img + 63) / 64 * 64;
     sp.o_fix = cv.take(derived_bytes(fixed->n));
     sp.o_free = cv.take(derived_bytes(0));
-    sp.o_rec = cv.take((size_t)3 * sp.nimg_pad * sizeof(double));
+    sp.o_rec = cv.take((size_t)CHI2_REC_ROWS * sp.nimg_pad * sizeof(double));
     sp.o_src = 0;
     lens_mcmc_t *m = new lens_mcmc_t();
     m->ctx = ctx;

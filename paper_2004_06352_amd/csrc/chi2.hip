@@ -46,14 +46,41 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Per-image constants that every sample shares, computed once per call:
-// rec[0][t], rec[1][t] = the fixed potentials' deflection at image t and
+// rec[0][t], rec[1][t] = the fixed potentials' deflection at image t,
 // rec[2][t] = the image's Dls/Ds (its system's, found by bisection over the
-// image offsets staged in LDS).  One block per image: thread l evaluates the
-// fixed potentials l, l+256, ... in that order (lanes hold different
-// potentials, so the kind branches diverge), then a shuffle tree per wave
-// and the four wave sums in order.
+// image offsets staged in LDS) and rec[3][t] = 1/sigma_t^2, the weight of its
+// term in Eq. (6).  One block per image, of as many threads as
+// there are fixed potentials (rounded up to whole waves, at most
+// PREP_MAX_BLOCK): thread l evaluates the fixed potentials l, l + blockDim,
+// ... in that order (lanes hold different potentials, so the kind branches
+// may diverge), then a shuffle tree per wave and the wave sums in order.
+// The block size depends only on the number of fixed potentials, so the
+// summation order is that of the table, not of the call.
 constexpr int PREP_OFF_MAX = 4097;
-constexpr int PREP_BLOCK = 256;
+constexpr int PREP_MAX_BLOCK = 1024;
+constexpr int PREP_FREE_BLOCK = 256;  // the free table's prologue blocks
+
+// Threads of a per-image block for nfix fixed potentials.
+__host__ __device__ inline int prep_threads(int nfix) {
+    const int w = ((nfix > 1 ? nfix : 1) + 63) / 64;
+    return 64 * (w < PREP_MAX_BLOCK / 64 ? w : PREP_MAX_BLOCK / 64);
+}
+
+// One fixed potential's deflection at a constraint (each lane its own
+// potential): the usual kind through the full-range form, which these points
+// near the mass need in most waves, the others through the general form.
+__device__ __forceinline__ void prep_eval_f64(const ConstD c, double x, double y, double acc[5],
+                                              const Series &S) {
+    const int kind = kind_bits(c[D_KIND]);
+    if ((kind & (K_CUT | K_ELL | K_SING)) == (K_CUT | K_ELL)) {
+        double pa[1][5] = {{acc[0], acc[1], 0.0, 0.0, 0.0}};
+        grad_cut_ell_full<1>(c, &x, &y, pa, S);
+        acc[0] = pa[0][0];
+        acc[1] = pa[0][1];
+    } else {
+        eval_pot_f64<true, false, false>(c, x, y, acc, S);
+    }
+}
 
 // INLINE: the fixed potentials' derived constants are not read from a table
 // but formed by each thread from the amplitude table (the table prologue's
@@ -61,13 +88,16 @@ constexpr int PREP_BLOCK = 256;
 // precedes this one; blocks beyond the images then run the free table's
 // prologue, which the per-sample kernel reads.  One launch instead of two.
 template <int PREC, bool INLINE = false>
-__global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) {
+__global__ void __launch_bounds__(PREP_MAX_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) {
     __shared__ int s_off[PREP_OFF_MAX];
-    __shared__ double s_red[2][PREP_BLOCK / 64];
+    __shared__ double s_red[2][PREP_MAX_BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nthr = blockDim.x;
     const int t = blockIdx.x;
     if (INLINE && t >= a.nimg) {
-        const int k = (t - a.nimg) * PREP_BLOCK + tid;
+        // PREP_FREE_BLOCK potentials per block (the threads beyond idle)
+        const int k = (t - a.nimg) * PREP_FREE_BLOCK + tid;
+        if (tid >= PREP_FREE_BLOCK) return;
         if (k < a.freet.n) {
             const PotSoA &F = a.free_amp;
             prologue_values(F.x0[k], F.y0[k], F.b0[k], F.eps[k], F.phi[k], F.rcore[k], F.rcut[k],
@@ -78,12 +108,14 @@ __global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) 
     }
     const bool staged = a.nsys + 1 <= PREP_OFF_MAX;
     if (staged)
-        for (int i = tid; i <= a.nsys; i += PREP_BLOCK) s_off[i] = a.img_off[i];
+        for (int i = tid; i <= a.nsys; i += nthr) s_off[i] = a.img_off[i];
     double acc[5] = {0, 0, 0, 0, 0};
     const double x = a.x[t], y = a.y[t];
     const int st = a.fixedt.stride;
     const int nfix = INLINE ? a.nfixed : a.fixedt.n;
-    for (int k = tid; k < nfix; k += PREP_BLOCK) {
+    // the image role's threads (the launch may have more, for the free blocks)
+    const int nimt = prep_threads(nfix);
+    for (int k = tid; k < nfix && tid < nimt; k += nimt) {
         if (INLINE) {
             double v[NDER];
             float vf[NDERF];
@@ -91,7 +123,7 @@ __global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) 
             prologue_values<PREC != 0>(T.x0[k], T.y0[k], T.b0[k], T.eps[k], T.phi[k], T.rcore[k],
                                        T.rcut[k], 0, v, vf, 1, a.status);
             if (PREC == 0) {
-                eval_pot_f64<true, false, false>(ConstD{v, 1}, x, y, acc, a.S);
+                prep_eval_f64(ConstD{v, 1}, x, y, acc, a.S);
             } else {
                 float o[5];
                 eval_pot_f32<true, false, false>(ConstD{v, 1}, ConstF{vf, 1}, x, y, o, a.S);
@@ -99,7 +131,7 @@ __global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) 
                 acc[1] += (double)o[1];
             }
         } else if (PREC == 0) {
-            eval_pot_f64<true, false, false>(ConstD{a.fixedt.d + k, st}, x, y, acc, a.S);
+            prep_eval_f64(ConstD{a.fixedt.d + k, st}, x, y, acc, a.S);
         } else {
             float o[5];
             eval_pot_f32<true, false, false>(ConstD{a.fixedt.d + k, st},
@@ -116,7 +148,7 @@ __global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) 
     __syncthreads();
     if (tid == 0) {
         double sx = s_red[0][0], sy = s_red[1][0];
-        for (int w = 1; w < PREP_BLOCK / 64; ++w) {
+        for (int w = 1; w < nimt / 64; ++w) {
             sx += s_red[0][w];
             sy += s_red[1][w];
         }
@@ -124,6 +156,8 @@ __global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) 
         a.rec[t] = sx;
         a.rec[(size_t)a.nimg_pad + t] = sy;
         a.rec[2 * (size_t)a.nimg_pad + t] = a.f[i];
+        const double sg = a.sig[t];
+        a.rec[3 * (size_t)a.nimg_pad + t] = 1.0 / (sg * sg);
     }
 }
 
@@ -135,6 +169,10 @@ __global__ void __launch_bounds__(PREP_BLOCK) chi2_prep_kernel(Chi2SrcLaunch a) 
 // shuffle reduction in a fixed order, so a sample's chi^2 does not depend on
 // the batch it is evaluated in, on the path or on the launch shape.
 constexpr int SRC_IPL = 4;
+// Potentials staged in LDS at a time (at most), and the loads per lane that
+// stage them.
+constexpr int SRC_CHUNK_MAX = 8;
+constexpr int SRC_STAGE_LOADS = (SRC_CHUNK_MAX * NDER + 63) / 64;
 
 // The sampler's walker: physical parameters of its potential k (the proposal
 // theta + step (2u - 1) when `in`, else the current state; the same rounded
@@ -161,14 +199,21 @@ __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *t
 // takes the Metropolis decision: accept iff the proposal is inside the prior
 // box and (chi2' <= chi2 or -2 ln u_last > chi2' - chi2), copying the
 // proposal into the walker's parameters.
+// At least four waves per SIMD: a 4096-sample batch is one round of waves.
 template <int PREC, bool MCMC = false>
-__global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
-    extern __shared__ double sh[];  // [2][nimg] unlensed x, y; then the staged potentials
-    double *sx = sh, *sy = sh + a.nimg;
-    double *pd = sh + 2 * (size_t)a.nimg;
+__global__ void __launch_bounds__(64, 4) chi2_src_kernel(Chi2SrcLaunch a) {
+    // LDS: [2][nimg] unlensed x, y, [nimg] each image's 1/sigma^2 when the
+    // catalogue is small enough (stage_sig), then the staged potentials
+    extern __shared__ double sh[];
+    double *sx = sh, *sy = sh + a.nimg, *ss = sh + 2 * (size_t)a.nimg;
+    double *pd = sh + (2 + a.stage_sig) * (size_t)a.nimg;
     float *pf = reinterpret_cast<float *>(pd + (size_t)a.chunk * NDER);
     const int lane = threadIdx.x;
     const int pad = a.nimg_pad, st = a.freet.stride, nf = a.freet.n;
+    // the weights do not depend on the sample: staged once per wave (the
+    // first __syncthreads of the sample loop orders them before their use)
+    if (a.stage_sig)
+        for (int t = lane; t < a.nimg; t += 64) ss[t] = a.rec[3 * (size_t)pad + t];
     for (int m = a.sample0 + blockIdx.x; m < a.n_samples; m += gridDim.x) {
         int k0, k1;
         bool in = false;
@@ -209,9 +254,24 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
                 if (MCMC) {
                     if (lane < cnt) mcmc_derive(a.mc, th, uw, in, kc + lane, pd + lane * NDER);
                 } else {
-                    for (int e = lane; e < cnt * NDER; e += 64) {
-                        const int ci = e / cnt, kk = e - ci * cnt;
-                        pd[kk * NDER + ci] = a.freet.d[(size_t)ci * st + kc + kk];
+                    // every lane's loads in flight at once, then the stores
+                    // (LDS entry e = potential e / NDER, constant e % NDER).
+                    // The lane index passes through an empty asm so that the
+                    // index arithmetic is formed here: hoisted out of the
+                    // sample loop it would hold registers for the whole kernel.
+                    int l0 = lane;
+                    asm volatile("" : "+v"(l0));
+                    double v[SRC_STAGE_LOADS];
+#pragma unroll
+                    for (int i = 0; i < SRC_STAGE_LOADS; ++i) {
+                        const int e = l0 + 64 * i;
+                        const int kk = e / NDER, ci = e - kk * NDER;
+                        v[i] = kk < cnt ? a.freet.d[(size_t)ci * st + kc + kk] : 0.0;
+                    }
+#pragma unroll
+                    for (int i = 0; i < SRC_STAGE_LOADS; ++i) {
+                        const int e = l0 + 64 * i;
+                        if (e < cnt * NDER) pd[e] = v[i];
                     }
                 }
                 if (PREC != 0 && !MCMC) {
@@ -223,6 +283,19 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
                 __syncthreads();
                 for (int kk = 0; kk < cnt; ++kk) {
                     const ConstD cd{pd + kk * NDER, 1};
+                    if (PREC == 0) {
+                        // the usual kind (two cores, elliptical, rcore > 0):
+                        // full-range evaluation, slots in interleaved pairs
+                        const int kind = uniform_kind(cd[D_KIND]);
+                        if ((kind & (K_CUT | K_ELL | K_SING)) == (K_CUT | K_ELL)) {
+#pragma unroll
+                            for (int j = 0; j < SRC_IPL; j += 2) {
+                                if (g0 + j * 64 >= a.nimg) break;  // uniform
+                                grad_cut_ell_full<2>(cd, x + j, y + j, acc + j, a.S);
+                            }
+                            continue;
+                        }
+                    }
 #pragma unroll
                     for (int j = 0; j < SRC_IPL; ++j) {
                         if (g0 + j * 64 >= a.nimg) break;  // uniform: no image in this slot
@@ -260,13 +333,15 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
                 my += sy[t];
             }
             if (M > 0) {
-                mx /= M;
-                my /= M;
+                const double im = 1.0 / M;
+                mx *= im;
+                my *= im;
             }
             double s = 0.0;
             for (int t = o0; t < o1; ++t) {
                 const double ex = sx[t] - mx, ey = sy[t] - my;
-                s += (ex * ex + ey * ey) / (a.sig[t] * a.sig[t]);
+                const double w = a.stage_sig ? ss[t] : a.rec[3 * (size_t)pad + t];
+                s = fma(ex * ex + ey * ey, w, s);
             }
             part += s;
             if (a.src_x) {
@@ -304,10 +379,16 @@ __global__ void __launch_bounds__(64) chi2_src_kernel(Chi2SrcLaunch a) {
 
 // LDS: the unlensed positions plus a chunk of staged potentials; the chunk
 // shrinks for large catalogues so that a block stays within 64 KiB.
-static int src_chunk(int nimg, int prec) {
+// Per-image LDS arrays: 3 (sigma staged) when they leave room for a full
+// chunk of potentials, else 2.
+static int src_img_arrays(int nimg, int prec) {
     const size_t per = NDER * sizeof(double) + (prec ? NDERF * sizeof(float) : 0);
-    const size_t avail = 65536 - 2 * (size_t)nimg * sizeof(double);
-    return (int)std::max<size_t>(1, std::min<size_t>(8, avail / per));
+    return 3 * (size_t)nimg * sizeof(double) + SRC_CHUNK_MAX * per <= 65536 ? 3 : 2;
+}
+static int src_chunk(int nimg, int prec, int arrays) {
+    const size_t per = NDER * sizeof(double) + (prec ? NDERF * sizeof(float) : 0);
+    const size_t avail = 65536 - arrays * (size_t)nimg * sizeof(double);
+    return (int)std::max<size_t>(1, std::min<size_t>(SRC_CHUNK_MAX, avail / per));
 }
 
 hipError_t launch_chi2_prep(const Chi2SrcLaunch &c0, hipStream_t st) {
@@ -315,33 +396,38 @@ hipError_t launch_chi2_prep(const Chi2SrcLaunch &c0, hipStream_t st) {
     c.S = make_series();
     if (c.inline_fixed) {
         const long long free_blocks =
-            c.free_prologue ? ((long long)c.freet.n + PREP_BLOCK - 1) / PREP_BLOCK : 0;
+            c.free_prologue ? ((long long)c.freet.n + PREP_FREE_BLOCK - 1) / PREP_FREE_BLOCK : 0;
         const long long blocks = (long long)std::max(c.nimg, 0) + free_blocks;
         if (blocks == 0) return hipSuccess;
         if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
         if (!c.free_prologue) c.freet.n = 0;
+        // at least PREP_FREE_BLOCK threads, for the free table's blocks
+        const int nt = std::max(prep_threads(c.nfixed), free_blocks ? PREP_FREE_BLOCK : 64);
         if (c.prec == 0)
-            hipLaunchKernelGGL((chi2_prep_kernel<0, true>), dim3((unsigned)blocks), dim3(PREP_BLOCK),
-                               0, st, c);
+            hipLaunchKernelGGL((chi2_prep_kernel<0, true>), dim3((unsigned)blocks), dim3(nt), 0, st,
+                               c);
         else
-            hipLaunchKernelGGL((chi2_prep_kernel<1, true>), dim3((unsigned)blocks), dim3(PREP_BLOCK),
-                               0, st, c);
+            hipLaunchKernelGGL((chi2_prep_kernel<1, true>), dim3((unsigned)blocks), dim3(nt), 0, st,
+                               c);
         return hipGetLastError();
     }
     if (c0.nimg <= 0) return hipSuccess;
+    const int nt = prep_threads(c.fixedt.n);
     if (c.prec == 0)
-        hipLaunchKernelGGL(chi2_prep_kernel<0>, dim3(c.nimg), dim3(PREP_BLOCK), 0, st, c);
+        hipLaunchKernelGGL(chi2_prep_kernel<0>, dim3(c.nimg), dim3(nt), 0, st, c);
     else
-        hipLaunchKernelGGL(chi2_prep_kernel<1>, dim3(c.nimg), dim3(PREP_BLOCK), 0, st, c);
+        hipLaunchKernelGGL(chi2_prep_kernel<1>, dim3(c.nimg), dim3(nt), 0, st, c);
     return hipGetLastError();
 }
 
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
     Chi2SrcLaunch c = c0;
     c.S = make_series();
-    c.chunk = src_chunk(c.nimg, c.prec);
+    const int arrays = src_img_arrays(c.nimg, c.prec);
+    c.stage_sig = arrays == 3;
+    c.chunk = src_chunk(c.nimg, c.prec, arrays);
     const size_t shmem =
-        2 * (size_t)c.nimg * sizeof(double) +
+        arrays * (size_t)c.nimg * sizeof(double) +
         (size_t)c.chunk * (NDER * sizeof(double) + (c.prec ? NDERF * sizeof(float) : 0));
     if (shmem > 65536) return hipErrorInvalidValue;
     if (c.prec == 0)
@@ -357,8 +443,11 @@ hipError_t launch_mcmc_chi2(const Chi2SrcLaunch &c0, hipStream_t st) {
     if (c.n_samples <= 0) return hipSuccess;
     c.S = make_series();
     c.prec = 0;
-    c.chunk = src_chunk(c.nimg, 0);
-    const size_t shmem = 2 * (size_t)c.nimg * sizeof(double) + (size_t)c.chunk * NDER * sizeof(double);
+    const int arrays = src_img_arrays(c.nimg, 0);
+    c.stage_sig = arrays == 3;
+    c.chunk = src_chunk(c.nimg, 0, arrays);
+    const size_t shmem =
+        arrays * (size_t)c.nimg * sizeof(double) + (size_t)c.chunk * NDER * sizeof(double);
     if (shmem > 65536) return hipErrorInvalidValue;
     hipLaunchKernelGGL((chi2_src_kernel<0, true>), dim3(c.grid_blocks), dim3(64), shmem, st, c);
     return hipGetLastError();

@@ -23,6 +23,9 @@ struct McmcFused {
     int *status = nullptr;          // status word (invalid parameters)
 };
 
+// Rows of the per-image constants written by the prep kernel.
+constexpr int CHI2_REC_ROWS = 4;
+
 // Source-plane chi^2
 struct Chi2SrcLaunch {
     Derived freet;            // derived free potentials of all samples
@@ -36,11 +39,13 @@ struct Chi2SrcLaunch {
     int nimg_pad;
     double *chi2;             // [S] or NULL
     double *src_x, *src_y;    // [S*nsys] barycentric sources, or NULL
-    double *rec;              // [3][nimg_pad]: fixed deflection x, y and Dls/Ds per image
+    double *rec;              // [CHI2_REC_ROWS][nimg_pad]: fixed deflection x, y, Dls/Ds
+                              // and 1/sigma^2 per image
     int persistent;           // 1: stride over the batch by the grid size
     int grid_blocks;
     int prec;
     int chunk;                // potentials per LDS stage (set by the launch wrapper)
+    int stage_sig = 0;        // 1: each image's 1/sigma^2 staged in LDS (set by the wrapper)
     Series S;                 // filled by the launch wrapper
     McmcFused mc;             // the sampler's step (mode 0: a plain chi^2 batch)
     // prep with inline fixed prologue (inline_fixed = 1): the fixed potentials'

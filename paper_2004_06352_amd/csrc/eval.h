@@ -109,7 +109,7 @@ struct AtanRed {
 __device__ __forceinline__ AtanRed atan_reduce(double N, double D) {
     const double u = fabs(N);
     const bool big = u > D;
-    const double lo = big ? D : u, hi = big ? u : D;
+    const double lo = fmin(u, D), hi = fmax(u, D);  // (finite operands)
     const bool m1 = lo > kTanPi16 * hi, m2 = lo > kTan3Pi16 * hi;
     const double c = m2 ? 1.0 : (m1 ? kC1 : 0.0);
     AtanRed r;
@@ -384,6 +384,53 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
         eval_pot_f64_impl<GRAD, HESS, true, SHORT>(c, kind, x, y, acc, S);
     else
         eval_pot_f64_impl<GRAD, HESS, false, SHORT>(c, kind, x, y, acc, S);
+}
+
+// Deflection of one two-core elliptical potential (kind K_CUT | K_ELL, rcore >
+// 0) at NP points per lane, added to acc[p][0..1], always through the
+// full-range arctangent and hyperbolic arctangent reductions: no polynomial
+// tier is tried first.  This suits points spread over the strong-lensing
+// region, such as the constraint positions of the chi^2, where the ratios of
+// nearly every wave leave the tiers' intervals (the tiers would be evaluated
+// and thrown away, with their own reciprocal).  The NP evaluations are
+// independent straight-line code that the compiler interleaves.  The steps
+// and their rounding are those of the reduction path of eval_pot_f64 (the
+// two cores' differences, one reciprocal for both reduced quotients).
+template <int NP, int W>
+__device__ __forceinline__ void grad_cut_ell_full(const ConstD c, const double *x,
+                                                  const double *y, double (*acc)[W],
+                                                  const Series &S) {
+    const double x0 = c[D_X0], y0 = c[D_Y0], cp = c[D_C], sp = c[D_S];
+    const double eq2 = c[D_EQ2], ek2i = c[D_EK2I], eca = c[D_ECA], dc = c[D_DC];
+    const double esa = c[D_ESA], ess = c[D_ESS], eq2sa = c[D_EQ2SA], eq2ss = c[D_EQ2SS];
+    const double pfc = c[D_PFC], pfs = c[D_PFS];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const double dx = x[p] - x0, dy = y[p] - y0;
+        const double xp = fma(dx, cp, dy * sp);
+        const double yp = fma(dy, cp, -(dx * sp));
+        const double x2 = xp * xp, y2 = yp * yp;
+        const double ta = fma(eq2, x2, fma(ek2i, y2, eca));
+        const double ts = ta + dc;
+        const double ra = rsq64(ta), rs = rsq64(ts);
+        const double A1 = fma(ta, ra, esa), A2 = fma(ts, rs, ess);
+        const double B1 = fma(ta, ra, eq2sa), B2 = fma(ts, rs, eq2ss);
+        const double Dx = fma(A1, A2, x2);
+        const double Dy = fma(B1, B2, -y2);
+        const double Nx = xp * (A2 - A1);
+        const double Ny = yp * (B2 - B1);
+        const AtanRed ra_ = atan_reduce(Nx, Dx);
+        const AtanhRed rh = atanh_reduce(Ny, Dy);
+        const double R3 = rcp64(ra_.den * rh.den);
+        const double b = ra_.num * (R3 * rh.den);
+        const double s = rh.num * (R3 * ra_.den);
+        const double ax = atan_finish(ra_, b, S);
+        const double ay = atanh_finish(rh, s, S);
+        acc[p][0] = fma(pfc, ax, acc[p][0]);
+        acc[p][0] = fma(-pfs, ay, acc[p][0]);
+        acc[p][1] = fma(pfs, ax, acc[p][1]);
+        acc[p][1] = fma(pfc, ay, acc[p][1]);
+    }
 }
 
 // ---------------------------------------------------------------------------
