@@ -341,11 +341,14 @@ lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *
 /* ---- captured batches (batching form) ------------------------------------ */
 /* Record the whole of one lens_chi2_batch call (batched path) into a HIP
  * graph bound to these exact buffers and shapes; replaying it re-evaluates
- * the batch with whatever the buffers then hold.  Source mode only.  The plan
- * owns its scratch (device memory allocated here, freed by
- * lens_chi2_plan_destroy), so other calls on the context do not disturb it;
- * it uses the context's status word and device, so destroy plans before
- * their context.  Creating a plan synchronises `stream`. */
+ * the batch with whatever the buffers then hold.  lens_chi2_plan_create and
+ * _create_ex record source-mode calls (other modes: LENS_EUNSUPPORTED);
+ * lens_chi2_plan_create2 records either mode, with the image mode's optional
+ * outputs.  The plan owns its scratch (device memory allocated here, freed
+ * by lens_chi2_plan_destroy), so other calls on the context do not disturb
+ * it; it uses the context's device and, in checked contexts, validates the
+ * tables once at creation, so destroy plans before their context.  Creating
+ * a plan synchronises `stream`. */
 lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *batch,
                                     const lens_catalog_t *cat, const lens_chi2_opts_t *opts,
                                     double *chi2, void *stream, lens_chi2_plan_t **out);
@@ -364,7 +367,24 @@ lens_status_t lens_chi2_plan_create_ex(lens_ctx_t *ctx, const lens_model_batch_t
                                        const lens_catalog_t *cat, const lens_chi2_opts_t *opts,
                                        double *chi2, uint32_t flags, void *stream,
                                        lens_chi2_plan_t **out);
+/* Either mode (the Sec. 4.2 pipeline of the image mode: sources, deflection
+ * grids, triangle search, assignment).  A launch of an image-mode plan does
+ * not synchronise: what the eager call reports after its search (slot
+ * overflow, Dls/Ds or coordinates outside the search's domain) is kept in
+ * the plan's status word, which each launch clears first and
+ * lens_chi2_plan_status reads.  With LENS_PLAN_FIXED_RESIDENT the image mode
+ * also keeps the fixed potentials' derived table and their deflection at the
+ * grid vertices from creation. */
+lens_status_t lens_chi2_plan_create2(lens_ctx_t *ctx, const lens_model_batch_t *batch,
+                                     const lens_catalog_t *cat, const lens_chi2_opts_t *opts,
+                                     double *chi2, int32_t *nimg, int32_t *nmissing,
+                                     double *img_xy, uint32_t flags, void *stream,
+                                     lens_chi2_plan_t **out);
 lens_status_t lens_chi2_plan_launch(lens_chi2_plan_t *plan, void *stream);
+/* The outcome of the plan's last launch as lens_chi2_batch would report it
+ * (LENS_OK, LENS_EOVERFLOW or LENS_EINVAL); synchronises `stream`, on which
+ * the launch was made.  Source-mode plans: LENS_OK. */
+lens_status_t lens_chi2_plan_status(lens_chi2_plan_t *plan, void *stream);
 lens_status_t lens_chi2_plan_destroy(lens_chi2_plan_t *plan);
 
 /* ---- sampler (the MCMC of Sec. 2.2; Sec. 4's third bottleneck) ----------- */

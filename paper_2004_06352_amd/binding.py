@@ -38,8 +38,8 @@ EXPORTS = ("lens_ctx_create", "lens_ctx_destroy", "lens_ctx_status", "lens_set_m
            "lens_table_from_physical", "lens_grad_map",
            "lens_hessian_map", "lens_hessian_map_noalloc", "lens_derived_map", "lens_potential_map", "lens_time_delay_map",
            "lens_time_delay_scale", "lens_chi2_batch", "lens_find_images",
-           "lens_chi2_plan_create", "lens_chi2_plan_create_ex",
-           "lens_chi2_plan_launch", "lens_chi2_plan_destroy", "lens_mcmc_create",
+           "lens_chi2_plan_create", "lens_chi2_plan_create_ex", "lens_chi2_plan_create2",
+           "lens_chi2_plan_launch", "lens_chi2_plan_status", "lens_chi2_plan_destroy", "lens_mcmc_create",
            "lens_mcmc_step", "lens_mcmc_destroy", "lens_dlsds",
            "lens_b0_from_sigma", "lens_eps_from_e", "lens_map_scratch_bytes",
            "lens_chi2_scratch_bytes", "lens_last_error", "lens_abi_version")
@@ -136,7 +136,11 @@ def lib():
         L.lens_chi2_plan_create_ex.argtypes = [vp, C.POINTER(_Batch), C.POINTER(_Cat),
                                                C.POINTER(_Opts), vp, C.c_uint32, vp,
                                                C.POINTER(vp)]
+        L.lens_chi2_plan_create2.argtypes = [vp, C.POINTER(_Batch), C.POINTER(_Cat),
+                                             C.POINTER(_Opts), vp, vp, vp, vp, C.c_uint32, vp,
+                                             C.POINTER(vp)]
         L.lens_chi2_plan_launch.argtypes = [vp, vp]
+        L.lens_chi2_plan_status.argtypes = [vp, vp]
         L.lens_chi2_plan_destroy.argtypes = [vp]
         L.lens_dlsds.argtypes = [dbl, dbl, dbl, dbl, C.POINTER(dbl)]
         L.lens_b0_from_sigma.argtypes = [dbl, i32, C.POINTER(dbl)]
@@ -463,30 +467,53 @@ PLAN_FIXED_RESIDENT = 1
 
 
 class Chi2Plan:
-    """A source-plane lens_chi2_batch recorded into a HIP graph; launch()
-    replays it on the current stream over the same buffers.  resident=True:
-    the fixed potentials and the catalogue are read once, at creation."""
+    """A lens_chi2_batch call (batched path) recorded into a HIP graph;
+    launch() replays it on the current stream over the same buffers.
+    resident=True: the fixed potentials and the catalogue are read once, at
+    creation.  mode=CHI2_IMAGE records the image-plane pipeline (grid, kmax,
+    penalty, refine as chi2_batch); nimg, nmissing (and img_xy when
+    want_images) are then bound too, and status() reports what the last
+    launch's search found (overflow, domain)."""
 
-    def __init__(self, fixed, free, free_off, cat, prec=FP64, ctx=None, resident=False):
+    def __init__(self, fixed, free, free_off, cat, prec=FP64, ctx=None, resident=False,
+                 mode=CHI2_SOURCE, grid=None, kmax=16, penalty=0.0, want_images=False,
+                 refine=None):
         self.ctx = _ctx(ctx)
         dev = free_off.device
         S = int(free_off.numel()) - 1
+        nsys = int(cat["off"].numel()) - 1
         self.chi2 = torch.empty(S, dtype=torch.float64, device=dev)
+        self.nimg = self.nmissing = self.img_xy = None
+        if mode == CHI2_IMAGE:
+            self.nimg = torch.empty((S, nsys), dtype=torch.int32, device=dev)
+            self.nmissing = torch.empty(S, dtype=torch.int32, device=dev)
+            if want_images:
+                self.img_xy = torch.empty((S, nsys, kmax, 2), dtype=torch.float64, device=dev)
         self._keep = (fixed, free, free_off, cat)
         B, K = _batch(fixed, free, free_off), _catalog(cat)
-        O = _opts(CHI2_SOURCE, prec, PATH_BATCHED, None, 1, 0.0)
+        O = _opts(mode, prec, PATH_BATCHED, grid, kmax, penalty, refine)
         h = C.c_void_p()
         self.stream = torch.cuda.Stream(device=dev)
         self.stream.wait_stream(torch.cuda.current_stream(dev))
-        _check(lib().lens_chi2_plan_create_ex(self.ctx.handle, C.byref(B), C.byref(K),
-                                              C.byref(O), _ptr(self.chi2),
-                                              PLAN_FIXED_RESIDENT if resident else 0,
-                                              C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        _check(lib().lens_chi2_plan_create2(self.ctx.handle, C.byref(B), C.byref(K),
+                                            C.byref(O), _ptr(self.chi2), _ptr(self.nimg),
+                                            _ptr(self.nmissing), _ptr(self.img_xy),
+                                            PLAN_FIXED_RESIDENT if resident else 0,
+                                            C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.handle = h
 
     def launch(self):
         _check(lib().lens_chi2_plan_launch(self.handle, _stream(self.chi2.device)))
         return self.chi2
+
+    def status(self):
+        """Outcome of the last launch: False, or True when image slots
+        overflowed; raises LensError for the search's domain errors."""
+        st = lib().lens_chi2_plan_status(self.handle, _stream(self.chi2.device))
+        if st == -4:
+            return True
+        _check(st)
+        return False
 
     def close(self):
         if getattr(self, "handle", None):

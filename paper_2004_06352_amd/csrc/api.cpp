@@ -69,6 +69,7 @@ struct lens_chi2_plan {
     void *mem = nullptr;  // the plan's own scratch (derived tables, per-image constants)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int *status = nullptr;  // image mode: the search's status word, in mem
 };
 
 // Device memory of the allocation-free map call: the derived constants of at
@@ -200,10 +201,12 @@ Derived derived_in(char *base, size_t off, int n) {
 
 Derived derived_at(lens_ctx_t *ctx, size_t off, int n) { return derived_in(sc(ctx, off), 0, n); }
 
+// The table prologue; parts: PRO_F32 / PRO_LOG, what the consumer reads
+// besides the FP64 block.
 lens_status_t run_prologue(lens_ctx_t *ctx, const lens_pot_table_t *t, const Derived &D,
-                           hipStream_t st) {
+                           int parts, hipStream_t st) {
     HIP_TRY(launch_prologue(soa(t), t->n, const_cast<double *>(D.d), const_cast<float *>(D.f),
-                            D.stride, ctx->small, st));
+                            D.stride, ctx->small, parts, st));
     return LENS_OK;
 }
 
@@ -283,7 +286,7 @@ lens_status_t map_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const l
         D = derived_at(ctx, o_tab, table->n);
     }
     TRY(status_reset(ctx, st));
-    TRY(run_prologue(ctx, table, D, st));
+    TRY(run_prologue(ctx, table, D, prec == LENS_FP64 ? 0 : PRO_F32, st));
     TRY(status_check(ctx, st));
     MapLaunch m;
     m.tab = D;
@@ -396,7 +399,12 @@ int batched_blocks(const lens_ctx_t *ctx, int S) {
 // evaluate the fixed potentials again, the image plane).  Without the last,
 // the fixed potentials' constants are formed inside the per-image launch and
 // no table of them is written.
-enum SrcParts { SRC_ALL, SRC_FIXED_ONLY, SRC_FREE_ONLY, SRC_SAMPLES_ONLY, SRC_ALL_TABLES };
+// SRC_SAMPLES_DERIVE: the per-sample kernel alone, forming the free
+// potentials' derived constants itself from their amplitude table (one
+// launch; the per-image constants being ready).
+enum SrcParts {
+    SRC_ALL, SRC_FIXED_ONLY, SRC_FREE_ONLY, SRC_SAMPLES_ONLY, SRC_ALL_TABLES, SRC_SAMPLES_DERIVE
+};
 
 // Prologues, fixed deflection at the constraints, then the per-sample kernel.
 lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
@@ -406,14 +414,17 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
     char *base = p.base ? p.base : sc(ctx, 0);
     const Derived DF = derived_in(base, p.o_fix, b->fixed.n);
     const Derived DV = derived_in(base, p.o_free, b->free.n);
+    const int f32 = prec == LENS_FP64 ? 0 : PRO_F32;
     if (with_check) TRY(status_reset(ctx, st));
     if (parts == SRC_ALL_TABLES)
         HIP_TRY(launch_prologue2(soa(&b->fixed), b->fixed.n, const_cast<double *>(DF.d),
                                  const_cast<float *>(DF.f), DF.stride, soa(&b->free), b->free.n,
                                  const_cast<double *>(DV.d), const_cast<float *>(DV.f),
-                                 DV.stride, ctx->small, st));
+                                 DV.stride, ctx->small, f32, st));
+    else if (parts == SRC_SAMPLES_DERIVE)
+        ;  // the per-sample kernel derives the free constants itself
     else if (parts == SRC_FREE_ONLY)
-        TRY(run_prologue(ctx, &b->free, DV, st));
+        TRY(run_prologue(ctx, &b->free, DV, f32, st));
     Chi2SrcLaunch L;
     L.freet = DV;
     L.free_off = b->free_offset;
@@ -446,6 +457,11 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
         HIP_TRY(launch_chi2_prep(L, st));
     if (with_check) TRY(status_check(ctx, st));
     if (parts == SRC_FIXED_ONLY || b->n_samples == 0) return LENS_OK;
+    if (parts == SRC_SAMPLES_DERIVE) {
+        L.derive_free = 1;
+        L.free_amp = soa(&b->free);
+        L.status = ctx->small;
+    }
     if (batched) {
         L.persistent = 1;
         L.grid_blocks = batched_blocks(ctx, b->n_samples);
@@ -500,6 +516,151 @@ ImgPlan plan_img(Carve &cv, int nx, int ny, int n_sys, int kmax, int S, bool one
     return p;
 }
 
+// Outputs of the image-plane sequence and the word its search reports to.
+struct ImgOut {
+    double *chi2;
+    int32_t *nimg, *nmissing;
+    double *img_xy;
+    int *status;  // device: ST_OVERFLOW | ST_DOMAIN | ST_BAD_F bits of this call
+};
+
+// Which parts of the image-plane sequence to issue: everything; only what
+// depends on the fixed potentials and the catalogue (their derived table,
+// the per-image constants and the fixed potentials' deflection at the grid
+// vertices); only what depends on the free potentials (their prologue, the
+// sources, then per chunk the search and the assignment), the fixed part
+// being ready.
+enum ImgParts { IMG_ALL, IMG_FIXED_ONLY, IMG_FREE_ONLY };
+
+// The launches of the image-plane chi^2 (Sec. 4.2, Fig. 7), with no
+// synchronisation: sources (the source-plane kernels), the fixed potentials'
+// deflection at the grid vertices, then per chunk of samples the vertex
+// deflections, the triangle search, the slot order, the optional Newton
+// refinement and the assignment.  Offsets of sp and ip refer to sp.base (the
+// context's scratch when NULL).
+lens_status_t img_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
+                           const lens_chi2_opts_t *o, const SrcPlan &sp, const ImgPlan &ip,
+                           const ImgOut &out, hipStream_t st, bool with_check, ImgParts parts) {
+    char *base = sp.base ? sp.base : sc(ctx, 0);
+    const int S = b->n_samples;
+    const int kmax = o->max_img_per_sys;
+    const GridArgs G{o->grid.nx, o->grid.ny, o->grid.x0, o->grid.y0, o->grid.dx, o->grid.dy};
+    const size_t nv = (size_t)G.nx * G.ny;
+    const int chunk = ip.chunk;
+    const Derived DF = derived_in(base, sp.o_fix, b->fixed.n);
+    const Derived DV = derived_in(base, sp.o_free, b->free.n);
+    double *afx = (double *)(base + ip.o_afix), *afy = afx + nv;
+    if (parts != IMG_FIXED_ONLY) HIP_TRY(launch_zero_i32(out.status, 1, st));
+    if (parts == IMG_ALL) {
+        TRY(src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr, true, st,
+                         with_check, SRC_ALL_TABLES));
+    } else if (parts == IMG_FIXED_ONLY) {
+        TRY(run_prologue(ctx, &b->fixed, DF, 0, st));
+        TRY(src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr, true, st,
+                         with_check, SRC_FIXED_ONLY));
+    } else {
+        TRY(run_prologue(ctx, &b->free, DV, o->prec == LENS_FP64 ? 0 : PRO_F32, st));
+        TRY(src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr, true, st,
+                         false, SRC_SAMPLES_ONLY));
+    }
+    if (parts != IMG_FREE_ONLY && b->fixed.n > 0) {
+        MapLaunch m;
+        m.tab = DF;
+        m.grid = G;
+        m.dlsds = 1.0;
+        m.out[0] = afx;
+        m.out[1] = afy;
+        m.out[2] = m.out[3] = m.out[4] = nullptr;
+        m.prec = 0;
+        m.grad = true;
+        m.hess = false;
+        m.tune = ctx->tune[0];
+        HIP_TRY(launch_map(m, st));
+    }
+    if (parts == IMG_FIXED_ONLY) return LENS_OK;
+    const double *srcx = (const double *)(base + sp.o_src);
+    const double *srcy = srcx + (size_t)S * c->n_sys;
+    double *alpha = (double *)(base + ip.o_alpha);
+    int *count = (int *)(base + ip.o_count);
+    long long *tri = (long long *)(base + ip.o_tri);
+    double *ix = (double *)(base + ip.o_ix), *iy = (double *)(base + ip.o_iy);
+    for (int m0 = 0; m0 < S; m0 += chunk) {
+        const int ns = std::min(chunk, S - m0);
+        AlphaGridLaunch A;
+        A.freet = DV;
+        A.free_off = b->free_offset;
+        A.m0 = m0;
+        A.nsamp = ns;
+        A.grid = G;
+        A.afix_x = b->fixed.n > 0 ? afx : nullptr;
+        A.afix_y = b->fixed.n > 0 ? afy : nullptr;
+        A.out = alpha;
+        A.prec = o->prec == LENS_FP64 ? 0 : 1;
+        HIP_TRY(launch_alpha_grid(A, st));
+        HIP_TRY(launch_zero_i32(count, ns * c->n_sys, st));
+        ImgLaunch I;
+        I.alpha = alpha;
+        I.grid = G;
+        I.n_grids = ns;
+        I.nq = c->n_sys;
+        I.sx = srcx + (size_t)m0 * c->n_sys;
+        I.sy = srcy + (size_t)m0 * c->n_sys;
+        I.f = c->dlsds;
+        I.kmax = kmax;
+        I.count = count;
+        I.tri = tri;
+        I.ix = ix;
+        I.iy = iy;
+        I.tb = (double *)(base + ip.o_tb);
+        I.status = out.status;
+        HIP_TRY(launch_find_images(I, st));
+        HIP_TRY(launch_sort_images(ns * c->n_sys, kmax, count, tri, ix, iy, st));
+        if (o->refine_max_iter > 0) {
+            RefineLaunch F;
+            F.fixedt = DF;
+            F.freet = DV;
+            F.free_off = b->free_offset;
+            F.m0 = m0;
+            F.nsamp = ns;
+            F.nsys = c->n_sys;
+            F.kmax = kmax;
+            F.count = count;
+            F.ix = ix;
+            F.iy = iy;
+            F.sx = I.sx;
+            F.sy = I.sy;
+            F.f = c->dlsds;
+            F.max_iter = o->refine_max_iter;
+            F.tol = o->refine_tol;
+            F.max_shift = 2.0 * std::max(G.dx, G.dy);
+            HIP_TRY(launch_refine_images(F, st));
+        }
+        AssignLaunch Q;
+        Q.nsamp = ns;
+        Q.nsys = c->n_sys;
+        Q.kmax = kmax;
+        Q.count = count;
+        Q.ix = ix;
+        Q.iy = iy;
+        Q.img_off = c->img_offset;
+        Q.nimg_total = c->n_img;
+        Q.x = c->x;
+        Q.y = c->y;
+        Q.sig = c->sigma;
+        Q.penalty = o->missing_penalty;
+        Q.m0 = m0;
+        Q.chi2 = out.chi2;
+        Q.nimg = out.nimg;
+        Q.nmissing = out.nmissing;
+        Q.img_xy = out.img_xy;
+        Q.part = (double *)(base + ip.o_part);
+        Q.miss = (int *)(base + ip.o_miss);
+        Q.status = out.status;
+        HIP_TRY(launch_assign(Q, st));
+    }
+    return LENS_OK;
+}
+
 // The image search's device-side findings (read back after the call).
 lens_status_t search_status(int bits) {
     if (bits & ST_BAD_F)
@@ -510,6 +671,15 @@ lens_status_t search_status(int bits) {
                     "(nonzero magnitudes in [2^-400, 2^400], finite)");
     return LENS_OK;
 }
+
+// Outcome of the image search from its status bits (read back after a call).
+lens_status_t search_outcome(int bits) {
+    TRY(search_status(bits));
+    if (bits & ST_OVERFLOW)
+        return fail(LENS_EOVERFLOW, "more images than max_img_per_sys in some (sample, system)");
+    return LENS_OK;
+}
+
 
 lens_status_t check_chi2_args(lens_ctx_t *ctx, const lens_model_batch_t *b,
                               const lens_catalog_t *c, const lens_chi2_opts_t *o) {
@@ -535,6 +705,106 @@ lens_status_t check_chi2_args(lens_ctx_t *ctx, const lens_model_batch_t *b,
         if (o->refine_max_iter > 0 && !(o->refine_tol > 0.0 && is_fin(o->refine_tol)))
             return fail(LENS_EINVAL, "refine_tol = %g (> 0)", o->refine_tol);
     }
+    return LENS_OK;
+}
+
+// A plan: its own scratch, the fixed part computed once when resident, and
+// the rest of one lens_chi2_batch call (batched path) captured into a graph.
+lens_status_t plan_create(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
+                          const lens_chi2_opts_t *o, double *chi2, int32_t *nimg,
+                          int32_t *nmissing, double *img_xy, uint32_t flags, void *stream,
+                          lens_chi2_plan_t **out) {
+    if (!out) return fail(LENS_EINVAL, "out is NULL");
+    *out = nullptr;
+    TRY(check_chi2_args(ctx, b, c, o));
+    if (flags & ~LENS_PLAN_FIXED_RESIDENT)
+        return fail(LENS_EINVAL, "unknown plan flags %u", (unsigned)flags);
+    const bool resident = (flags & LENS_PLAN_FIXED_RESIDENT) != 0;
+    const bool img = o->mode == LENS_CHI2_IMAGE;
+    const int S = b->n_samples;
+    TRY(check_range(chi2, (size_t)S * sizeof(double), "chi2"));
+    if (img) {
+        const int kmax = o->max_img_per_sys;
+        if (nimg) TRY(check_range(nimg, (size_t)S * c->n_sys * sizeof(int32_t), "nimg"));
+        if (nmissing) TRY(check_range(nmissing, (size_t)S * sizeof(int32_t), "nmissing"));
+        if (img_xy)
+            TRY(check_range(img_xy, (size_t)S * c->n_sys * kmax * 2 * sizeof(double), "img_xy"));
+    }
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv;
+    SrcPlan sp = plan_src(cv, b, c, img);
+    ImgPlan ip{};
+    if (img)
+        ip = plan_img(cv, o->grid.nx, o->grid.ny, c->n_sys, o->max_img_per_sys, S, false,
+                      ctx->scratch_max);
+    const size_t o_status = cv.take(sizeof(int));
+    TRY(check_contents(ctx, b, c, st));
+    lens_chi2_plan_t *p = new lens_chi2_plan_t();
+    p->ctx = ctx;
+    hipError_t e = hipMalloc(&p->mem, std::max<size_t>(cv.off, 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return fail(LENS_ENOMEM, "hipMalloc(%zu) for the plan failed", cv.off);
+    }
+    sp.base = (char *)p->mem;
+    p->status = (int *)(sp.base + o_status);
+    auto bail = [&](lens_status_t s) {
+        (void)hipStreamSynchronize(st);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        (void)hipFree(p->mem);
+        delete p;
+        return s;
+    };
+    // validate the tables once, outside the capture (checked contexts), and
+    // with LENS_PLAN_FIXED_RESIDENT compute the fixed part now
+    const ImgOut io{chi2, nimg, nmissing, img_xy, p->status};
+    lens_status_t s = LENS_OK;
+    if (img) {
+        if (resident || checked(ctx))
+            s = img_sequence(ctx, b, c, o, sp, ip, io, st, checked(ctx), IMG_FIXED_ONLY);
+    } else {
+        s = src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr, false, st,
+                         checked(ctx), SRC_FIXED_ONLY);
+    }
+    if (s == LENS_OK && checked(ctx)) {
+        s = status_reset(ctx, st);
+        const Derived DV = derived_in(sp.base, sp.o_free, b->free.n);
+        if (s == LENS_OK)
+            s = run_prologue(ctx, &b->free, DV, o->prec == LENS_FP64 ? 0 : PRO_F32, st);
+        if (s == LENS_OK) s = status_check(ctx, st);
+    }
+    if (s != LENS_OK) return bail(s);
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e)));
+    if (img)
+        s = img_sequence(ctx, b, c, o, sp, ip, io, st, false,
+                         resident ? IMG_FREE_ONLY : IMG_ALL);
+    else
+        s = src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, chi2, false, st, false,
+                         resident ? SRC_SAMPLES_DERIVE : SRC_ALL);
+    e = hipStreamEndCapture(st, &p->graph);
+    if (s != LENS_OK) return bail(s);
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e)));
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+        return bail(fail(LENS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)));
+    // the executable graph's resources go to the device now, not at the
+    // first launch
+    e = hipGraphUpload(p->exec, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(p->exec);
+        return bail(fail(LENS_EDEVICE, "hipGraphUpload: %s", hipGetErrorString(e)));
+    }
+    if (!img) p->status = nullptr;
+    *out = p;
     return LENS_OK;
 }
 
@@ -721,7 +991,7 @@ lens_status_t psi_common(lens_ctx_t *ctx, const lens_pot_table_t *table, const l
     TRY(ensure_scratch(ctx, cv.off));
     const Derived D = derived_at(ctx, o_tab, table->n);
     TRY(status_reset(ctx, st));
-    TRY(run_prologue(ctx, table, D, st));
+    TRY(run_prologue(ctx, table, D, PRO_LOG, st));
     TRY(status_check(ctx, st));
     const GridArgs G{grid->nx, grid->ny, grid->x0, grid->y0, grid->dx, grid->dy};
     HIP_TRY(launch_potential_map(D, G, dlsds, out, td, bx, by, scale, st));
@@ -779,123 +1049,16 @@ lens_status_t lens_chi2_batch(lens_ctx_t *ctx, const lens_model_batch_t *b,
         return src_sequence(ctx, b, c, o->prec, o->path, sp, chi2, false, st, true);
     }
     // ---- image plane ----
-    const GridArgs G{o->grid.nx, o->grid.ny, o->grid.x0, o->grid.y0, o->grid.dx, o->grid.dy};
-    const size_t nv = (size_t)G.nx * G.ny;
-    const ImgPlan ip = plan_img(cv, G.nx, G.ny, c->n_sys, kmax, S,
+    const ImgPlan ip = plan_img(cv, o->grid.nx, o->grid.ny, c->n_sys, kmax, S,
                                 o->path == LENS_CHI2_PATH_PER_SAMPLE, ctx->scratch_max);
-    const int chunk = ip.chunk;
-    const size_t o_afix = ip.o_afix, o_alpha = ip.o_alpha, o_count = ip.o_count;
-    const size_t o_tri = ip.o_tri, o_ix = ip.o_ix, o_iy = ip.o_iy, o_part = ip.o_part;
-    const size_t o_miss = ip.o_miss, o_tb = ip.o_tb;
     TRY(ensure_scratch(ctx, cv.off));
     TRY(check_contents(ctx, b, c, st));
-    HIP_TRY(launch_zero_i32(ctx->small + 2, 1, st));  // overflow word
-    TRY(src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr, true, st, true,
-                     SRC_ALL_TABLES));
-    const double *srcx = (const double *)sc(ctx, sp.o_src);
-    const double *srcy = srcx + (size_t)S * c->n_sys;
-    double *afx = (double *)sc(ctx, o_afix), *afy = afx + nv;
-    const Derived DF = derived_at(ctx, sp.o_fix, b->fixed.n);
-    const Derived DV = derived_at(ctx, sp.o_free, b->free.n);
-    if (b->fixed.n > 0) {
-        MapLaunch m;
-        m.tab = DF;
-        m.grid = G;
-        m.dlsds = 1.0;
-        m.out[0] = afx;
-        m.out[1] = afy;
-        m.out[2] = m.out[3] = m.out[4] = nullptr;
-        m.prec = 0;
-        m.grad = true;
-        m.hess = false;
-        m.tune = ctx->tune[0];
-        HIP_TRY(launch_map(m, st));
-    }
-    double *alpha = (double *)sc(ctx, o_alpha);
-    int *count = (int *)sc(ctx, o_count);
-    long long *tri = (long long *)sc(ctx, o_tri);
-    double *ix = (double *)sc(ctx, o_ix), *iy = (double *)sc(ctx, o_iy);
-    for (int m0 = 0; m0 < S; m0 += chunk) {
-        const int ns = std::min(chunk, S - m0);
-        AlphaGridLaunch A;
-        A.freet = DV;
-        A.free_off = b->free_offset;
-        A.m0 = m0;
-        A.nsamp = ns;
-        A.grid = G;
-        A.afix_x = b->fixed.n > 0 ? afx : nullptr;
-        A.afix_y = b->fixed.n > 0 ? afy : nullptr;
-        A.out = alpha;
-        A.prec = o->prec == LENS_FP64 ? 0 : 1;
-        HIP_TRY(launch_alpha_grid(A, st));
-        HIP_TRY(launch_zero_i32(count, ns * c->n_sys, st));
-        ImgLaunch I;
-        I.alpha = alpha;
-        I.grid = G;
-        I.n_grids = ns;
-        I.nq = c->n_sys;
-        I.sx = srcx + (size_t)m0 * c->n_sys;
-        I.sy = srcy + (size_t)m0 * c->n_sys;
-        I.f = c->dlsds;
-        I.kmax = kmax;
-        I.count = count;
-        I.tri = tri;
-        I.ix = ix;
-        I.iy = iy;
-        I.tb = (double *)sc(ctx, o_tb);
-        I.status = ctx->small + 2;
-        HIP_TRY(launch_find_images(I, st));
-        HIP_TRY(launch_sort_images(ns * c->n_sys, kmax, count, tri, ix, iy, st));
-        if (o->refine_max_iter > 0) {
-            RefineLaunch F;
-            F.fixedt = DF;
-            F.freet = DV;
-            F.free_off = b->free_offset;
-            F.m0 = m0;
-            F.nsamp = ns;
-            F.nsys = c->n_sys;
-            F.kmax = kmax;
-            F.count = count;
-            F.ix = ix;
-            F.iy = iy;
-            F.sx = I.sx;
-            F.sy = I.sy;
-            F.f = c->dlsds;
-            F.max_iter = o->refine_max_iter;
-            F.tol = o->refine_tol;
-            F.max_shift = 2.0 * std::max(G.dx, G.dy);
-            HIP_TRY(launch_refine_images(F, st));
-        }
-        AssignLaunch Q;
-        Q.nsamp = ns;
-        Q.nsys = c->n_sys;
-        Q.kmax = kmax;
-        Q.count = count;
-        Q.ix = ix;
-        Q.iy = iy;
-        Q.img_off = c->img_offset;
-        Q.nimg_total = c->n_img;
-        Q.x = c->x;
-        Q.y = c->y;
-        Q.sig = c->sigma;
-        Q.penalty = o->missing_penalty;
-        Q.m0 = m0;
-        Q.chi2 = chi2;
-        Q.nimg = nimg;
-        Q.nmissing = nmissing;
-        Q.img_xy = img_xy;
-        Q.part = (double *)sc(ctx, o_part);
-        Q.miss = (int *)sc(ctx, o_miss);
-        Q.status = ctx->small + 2;
-        HIP_TRY(launch_assign(Q, st));
-    }
+    const ImgOut out{chi2, nimg, nmissing, img_xy, ctx->small + 2};
+    TRY(img_sequence(ctx, b, c, o, sp, ip, out, st, true, IMG_ALL));
     HIP_TRY(hipMemcpyAsync(ctx->host_small + 2, ctx->small + 2, sizeof(int),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    TRY(search_status(ctx->host_small[2]));
-    if (ctx->host_small[2] & ST_OVERFLOW)
-        return fail(LENS_EOVERFLOW, "more images than max_img_per_sys in some (sample, system)");
-    return LENS_OK;
+    return search_outcome(ctx->host_small[2]);
 }
 
 lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *ay,
@@ -965,64 +1128,32 @@ lens_status_t lens_chi2_plan_create_ex(lens_ctx_t *ctx, const lens_model_batch_t
                                        const lens_catalog_t *c, const lens_chi2_opts_t *o,
                                        double *chi2, uint32_t flags, void *stream,
                                        lens_chi2_plan_t **out) {
-    if (!out) return fail(LENS_EINVAL, "out is NULL");
-    *out = nullptr;
-    TRY(check_chi2_args(ctx, b, c, o));
-    if (o->mode != LENS_CHI2_SOURCE)
-        return fail(LENS_EUNSUPPORTED, "captured plans cover the source-plane mode");
-    if (flags & ~LENS_PLAN_FIXED_RESIDENT)
-        return fail(LENS_EINVAL, "unknown plan flags %u", (unsigned)flags);
-    const bool resident = (flags & LENS_PLAN_FIXED_RESIDENT) != 0;
-    TRY(check_range(chi2, (size_t)b->n_samples * sizeof(double), "chi2"));
-    DeviceGuard dg(ctx->device);
-    if (!dg.ok) return fail(LENS_EDEVICE, "cannot select device %d", ctx->device);
+    if (o && o->mode != LENS_CHI2_SOURCE) {
+        if (out) *out = nullptr;
+        return fail(LENS_EUNSUPPORTED, "image-mode plans are created by lens_chi2_plan_create2");
+    }
+    return plan_create(ctx, b, c, o, chi2, nullptr, nullptr, nullptr, flags, stream, out);
+}
+
+lens_status_t lens_chi2_plan_create2(lens_ctx_t *ctx, const lens_model_batch_t *b,
+                                     const lens_catalog_t *c, const lens_chi2_opts_t *o,
+                                     double *chi2, int32_t *nimg, int32_t *nmissing,
+                                     double *img_xy, uint32_t flags, void *stream,
+                                     lens_chi2_plan_t **out) {
+    return plan_create(ctx, b, c, o, chi2, nimg, nmissing, img_xy, flags, stream, out);
+}
+
+lens_status_t lens_chi2_plan_status(lens_chi2_plan_t *p, void *stream) {
+    if (!p) return fail(LENS_EINVAL, "plan is NULL");
+    if (!p->status) return LENS_OK;
+    DeviceGuard dg(p->ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    Carve cv;
-    SrcPlan sp = plan_src(cv, b, c, false);
-    TRY(check_contents(ctx, b, c, st));
-    lens_chi2_plan_t *p = new lens_chi2_plan_t();
-    p->ctx = ctx;
-    hipError_t e = hipMalloc(&p->mem, std::max<size_t>(cv.off, 256));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        delete p;
-        return fail(LENS_ENOMEM, "hipMalloc(%zu) for the plan failed", cv.off);
-    }
-    sp.base = (char *)p->mem;
-    auto bail = [&](lens_status_t s) {
-        (void)hipStreamSynchronize(st);
-        if (p->graph) (void)hipGraphDestroy(p->graph);
-        (void)hipFree(p->mem);
-        delete p;
-        return s;
-    };
-    // validate the tables once, outside the capture (checked contexts), and
-    // with LENS_PLAN_FIXED_RESIDENT compute the per-image constants now
-    lens_status_t s = src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, nullptr,
-                                   false, st, checked(ctx), SRC_FIXED_ONLY);
-    if (s == LENS_OK && checked(ctx)) {
-        s = status_reset(ctx, st);
-        const Derived DV = derived_in(sp.base, sp.o_free, b->free.n);
-        if (s == LENS_OK) s = run_prologue(ctx, &b->free, DV, st);
-        if (s == LENS_OK) s = status_check(ctx, st);
-    }
-    if (s != LENS_OK) return bail(s);
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
-    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess)
-        return bail(fail(LENS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e)));
-    s = src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, chi2, false, st, false,
-                     resident ? SRC_FREE_ONLY : SRC_ALL);
-    e = hipStreamEndCapture(st, &p->graph);
-    if (s != LENS_OK) return bail(s);
-    if (e != hipSuccess)
-        return bail(fail(LENS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e)));
-    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess)
-        return bail(fail(LENS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)));
-    *out = p;
-    return LENS_OK;
+    int bits = 0;
+    HIP_TRY(hipMemcpyAsync(p->ctx->host_small + 3, p->status, sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    bits = p->ctx->host_small[3];
+    return search_outcome(bits);
 }
 
 lens_status_t lens_chi2_plan_create(lens_ctx_t *ctx, const lens_model_batch_t *b,

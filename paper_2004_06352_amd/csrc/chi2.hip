@@ -100,7 +100,8 @@ __global__ void __launch_bounds__(PREP_MAX_BLOCK) chi2_prep_kernel(Chi2SrcLaunch
         if (tid >= PREP_FREE_BLOCK) return;
         if (k < a.freet.n) {
             const PotSoA &F = a.free_amp;
-            prologue_values(F.x0[k], F.y0[k], F.b0[k], F.eps[k], F.phi[k], F.rcore[k], F.rcut[k],
+            prologue_values<PREC != 0, false>(F.x0[k], F.y0[k], F.b0[k], F.eps[k], F.phi[k],
+                                              F.rcore[k], F.rcut[k],
                             k, const_cast<double *>(a.freet.d), const_cast<float *>(a.freet.f),
                             a.freet.stride, a.status);
         }
@@ -120,7 +121,8 @@ __global__ void __launch_bounds__(PREP_MAX_BLOCK) chi2_prep_kernel(Chi2SrcLaunch
             double v[NDER];
             float vf[NDERF];
             const PotSoA &T = a.fixed_amp;
-            prologue_values<PREC != 0>(T.x0[k], T.y0[k], T.b0[k], T.eps[k], T.phi[k], T.rcore[k],
+            prologue_values<PREC != 0, false>(T.x0[k], T.y0[k], T.b0[k], T.eps[k], T.phi[k],
+                                              T.rcore[k],
                                        T.rcut[k], 0, v, vf, 1, a.status);
             if (PREC == 0) {
                 prep_eval_f64(ConstD{v, 1}, x, y, acc, a.S);
@@ -191,7 +193,8 @@ __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *t
     const double v = q[2] / c_kms;
     const double b0 = mc.bK * M_PI * v * v * arcsec_per_rad;
     const double eps = q[3] / (1.0 + sqrt(1.0 - q[3] * q[3]));
-    prologue_values<false>(q[0], q[1], b0, eps, q[4], q[5], q[6], 0, dst, nullptr, 1, mc.status);
+    prologue_values<false, false>(q[0], q[1], b0, eps, q[4], q[5], q[6], 0, dst, nullptr, 1,
+                                  mc.status);
 }
 
 // MCMC: the sampler form.  Walker m's free potentials are derived by the wave
@@ -199,9 +202,15 @@ __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *t
 // takes the Metropolis decision: accept iff the proposal is inside the prior
 // box and (chi2' <= chi2 or -2 ln u_last > chi2' - chi2), copying the
 // proposal into the walker's parameters.
-// At least four waves per SIMD: a 4096-sample batch is one round of waves.
-template <int PREC, bool MCMC = false>
-__global__ void __launch_bounds__(64, 4) chi2_src_kernel(Chi2SrcLaunch a) {
+// At least four waves per SIMD, so that a 4096-sample batch is one round of
+// waves; the sampler form, which also derives its walker's potentials,
+// keeps three (its registers would spill at four: measured 44.6 -> 39.9 us
+// per 4096-walker step).
+// DERIVE: the sample's free constants formed by the wave from the amplitude
+// table (a.derive_free), a variant of its own so that the usual batch keeps
+// its register allocation.
+template <int PREC, bool MCMC = false, bool DERIVE = false>
+__global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4)) chi2_src_kernel(Chi2SrcLaunch a) {
     // LDS: [2][nimg] unlensed x, y, [nimg] each image's 1/sigma^2 when the
     // catalogue is small enough (stage_sig), then the staged potentials
     extern __shared__ double sh[];
@@ -253,6 +262,17 @@ __global__ void __launch_bounds__(64, 4) chi2_src_kernel(Chi2SrcLaunch a) {
                 __syncthreads();
                 if (MCMC) {
                     if (lane < cnt) mcmc_derive(a.mc, th, uw, in, kc + lane, pd + lane * NDER);
+                } else if (DERIVE) {
+                    // the free potentials' derived constants formed here from
+                    // the amplitude table (lane per potential) instead of read
+                    // from a table a prologue launch wrote
+                    if (lane < cnt) {
+                        const PotSoA &F = a.free_amp;
+                        const int k = kc + lane;
+                        prologue_values<PREC != 0, false>(
+                            F.x0[k], F.y0[k], F.b0[k], F.eps[k], F.phi[k], F.rcore[k], F.rcut[k],
+                            0, pd + lane * NDER, pf + lane * NDERF, 1, a.status);
+                    }
                 } else {
                     // every lane's loads in flight at once, then the stores
                     // (LDS entry e = potential e / NDER, constant e % NDER).
@@ -274,7 +294,7 @@ __global__ void __launch_bounds__(64, 4) chi2_src_kernel(Chi2SrcLaunch a) {
                         if (e < cnt * NDER) pd[e] = v[i];
                     }
                 }
-                if (PREC != 0 && !MCMC) {
+                if (PREC != 0 && !MCMC && !DERIVE) {
                     for (int e = lane; e < cnt * NDERF; e += 64) {
                         const int ci = e / cnt, kk = e - ci * cnt;
                         pf[kk * NDERF + ci] = a.freet.f[(size_t)ci * st + kc + kk];
@@ -430,10 +450,15 @@ hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
         arrays * (size_t)c.nimg * sizeof(double) +
         (size_t)c.chunk * (NDER * sizeof(double) + (c.prec ? NDERF * sizeof(float) : 0));
     if (shmem > 65536) return hipErrorInvalidValue;
-    if (c.prec == 0)
-        hipLaunchKernelGGL(chi2_src_kernel<0>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
+    const dim3 grid(c.grid_blocks), block(64);
+    if (c.prec == 0 && c.derive_free)
+        hipLaunchKernelGGL((chi2_src_kernel<0, false, true>), grid, block, shmem, st, c);
+    else if (c.prec == 0)
+        hipLaunchKernelGGL((chi2_src_kernel<0>), grid, block, shmem, st, c);
+    else if (c.derive_free)
+        hipLaunchKernelGGL((chi2_src_kernel<1, false, true>), grid, block, shmem, st, c);
     else
-        hipLaunchKernelGGL(chi2_src_kernel<1>, dim3(c.grid_blocks), dim3(64), shmem, st, c);
+        hipLaunchKernelGGL((chi2_src_kernel<1>), grid, block, shmem, st, c);
     return hipGetLastError();
 }
 

@@ -55,6 +55,10 @@ struct Chi2SrcLaunch {
     int inline_fixed = 0, free_prologue = 0, nfixed = 0;
     PotSoA fixed_amp = {}, free_amp = {};
     int *status = nullptr;
+    // per-sample kernel with derive_free = 1: each wave forms its sample's
+    // free potentials' derived constants from free_amp itself (no free table
+    // prologue launch; freet is not read)
+    int derive_free = 0;
 };
 hipError_t launch_chi2_prep(const Chi2SrcLaunch &c, hipStream_t st);
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c, hipStream_t st);

@@ -156,10 +156,15 @@ enum StatusBits : int {
 // HIP error of the launch.
 // ---------------------------------------------------------------------------
 hipError_t launch_zero_i32(int *p, int n, hipStream_t st);
+// Parts of a derived table a prologue writes besides the FP64 block: the
+// FP32 copy (PRO_F32, for the FP32-evaluation precisions) and the constant of
+// the logarithmic term (PRO_LOG, for the lensing-potential kernel).
+enum PrologueParts : int { PRO_F32 = 1, PRO_LOG = 2 };
 hipError_t launch_prologue2(PotSoA a, int na, double *dda, float *dfa, int sa, PotSoA b, int nb,
-                            double *ddb, float *dfb, int sb, int *status, hipStream_t st);
+                            double *ddb, float *dfb, int sb, int *status, int parts,
+                            hipStream_t st);
 hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, int *status,
-                           hipStream_t st);
+                           int parts, hipStream_t st);
 hipError_t launch_phys_to_amp(const double *sigma, const double *e, int n, int convention,
                               double *b0, double *eps, int *status, hipStream_t st);
 

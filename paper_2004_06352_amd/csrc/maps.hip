@@ -80,47 +80,75 @@ hipError_t launch_phys_to_amp(const double *sigma, const double *e, int n, int c
 
 // ---------------------------------------------------------------------------
 // Parameter prologue: amplitude-form table -> derived constants (FP64 block
-// and its FP32 copy).
+// and, with F32, its FP32 copy; with LOG, the logarithmic term's constant).
+template <bool F32, bool LOG>
 __device__ __forceinline__ void prologue_one(const PotSoA &in, int k, double *__restrict__ dd,
                                              float *__restrict__ df, int stride, int *status) {
-    prologue_values(in.x0[k], in.y0[k], in.b0[k], in.eps[k], in.phi[k], in.rcore[k], in.rcut[k],
-                    k, dd, df, stride, status);
+    prologue_values<F32, LOG>(in.x0[k], in.y0[k], in.b0[k], in.eps[k], in.phi[k], in.rcore[k],
+                              in.rcut[k], k, dd, df, stride, status);
 }
 
+template <bool F32, bool LOG>
 __global__ void prologue_kernel(PotSoA in, int n, double *__restrict__ dd, float *__restrict__ df,
                                 int stride, int *status) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) prologue_one(in, k, dd, df, stride, status);
+    if (k < n) prologue_one<F32, LOG>(in, k, dd, df, stride, status);
 }
 
 // Two tables in one launch (the fixed and the free potentials of a chi^2
 // batch): threads [0, na) take table a, [na, na + nb) table b.
+template <bool F32, bool LOG>
 __global__ void prologue2_kernel(PotSoA a, int na, double *__restrict__ dda,
                                  float *__restrict__ dfa, int sa, PotSoA b, int nb,
                                  double *__restrict__ ddb, float *__restrict__ dfb, int sb,
                                  int *status) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < na)
-        prologue_one(a, k, dda, dfa, sa, status);
+        prologue_one<F32, LOG>(a, k, dda, dfa, sa, status);
     else if (k - na < nb)
-        prologue_one(b, k - na, ddb, dfb, sb, status);
+        prologue_one<F32, LOG>(b, k - na, ddb, dfb, sb, status);
 }
 
 hipError_t launch_prologue2(PotSoA a, int na, double *dda, float *dfa, int sa, PotSoA b, int nb,
-                            double *ddb, float *dfb, int sb, int *status, hipStream_t st) {
+                            double *ddb, float *dfb, int sb, int *status, int parts,
+                            hipStream_t st) {
     const long long n = (long long)na + nb;
     if (n <= 0) return hipSuccess;
     if (n > 0x7fffff00LL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(prologue2_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a,
-                       na, dda, dfa, sa, b, nb, ddb, dfb, sb, status);
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    const bool f32 = parts & PRO_F32, lg = parts & PRO_LOG;
+    if (f32 && lg)
+        hipLaunchKernelGGL((prologue2_kernel<true, true>), grid, block, 0, st, a, na, dda, dfa,
+                           sa, b, nb, ddb, dfb, sb, status);
+    else if (f32)
+        hipLaunchKernelGGL((prologue2_kernel<true, false>), grid, block, 0, st, a, na, dda, dfa,
+                           sa, b, nb, ddb, dfb, sb, status);
+    else if (lg)
+        hipLaunchKernelGGL((prologue2_kernel<false, true>), grid, block, 0, st, a, na, dda, dfa,
+                           sa, b, nb, ddb, dfb, sb, status);
+    else
+        hipLaunchKernelGGL((prologue2_kernel<false, false>), grid, block, 0, st, a, na, dda, dfa,
+                           sa, b, nb, ddb, dfb, sb, status);
     return hipGetLastError();
 }
 
 hipError_t launch_prologue(PotSoA in, int n, double *dd, float *df, int stride, int *status,
-                           hipStream_t st) {
+                           int parts, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(prologue_kernel, dim3((n + 255) / 256), dim3(256), 0, st, in, n, dd, df,
-                       stride, status);
+    const dim3 grid((n + 255) / 256), block(256);
+    const bool f32 = parts & PRO_F32, lg = parts & PRO_LOG;
+    if (f32 && lg)
+        hipLaunchKernelGGL((prologue_kernel<true, true>), grid, block, 0, st, in, n, dd, df,
+                           stride, status);
+    else if (f32)
+        hipLaunchKernelGGL((prologue_kernel<true, false>), grid, block, 0, st, in, n, dd, df,
+                           stride, status);
+    else if (lg)
+        hipLaunchKernelGGL((prologue_kernel<false, true>), grid, block, 0, st, in, n, dd, df,
+                           stride, status);
+    else
+        hipLaunchKernelGGL((prologue_kernel<false, false>), grid, block, 0, st, in, n, dd, df,
+                           stride, status);
     return hipGetLastError();
 }
 

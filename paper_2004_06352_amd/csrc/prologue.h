@@ -11,8 +11,10 @@ namespace lens {
 // Amplitude-form parameters of potential k -> its derived constants (FP64
 // block and, with F32, its FP32 copy; entry k of tables with the given
 // stride).  Invalid entries get NaN prefactors (their contribution is NaN) and
-// raise ST_INVALID_TABLE.
-template <bool F32 = true>
+// raise ST_INVALID_TABLE.  LOG: the constant of the potential's logarithmic
+// term (D_LC, read only by the lensing-potential kernel) is formed; without
+// it that entry is NaN.
+template <bool F32 = true, bool LOG = true>
 __device__ __forceinline__ void prologue_values(double x0, double y0, double b0, double eps,
                                                 double phi, double a, double s, int k,
                                                 double *__restrict__ dd, float *__restrict__ df,
@@ -77,7 +79,7 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     const double pk = ell ? PF * k1 : 0.0;  // F b0 (1 - eps)
     v[D_LA] = 0.5 * pk * Sa;
     v[D_LS] = 0.5 * pk * Ss;
-    v[D_LC] = ell ? pk * log(k1) * (Sa - Ss) : 0.0;
+    v[D_LC] = !LOG ? NAN : (ell ? pk * log(k1) * (Sa - Ss) : 0.0);
     v[D_PF] = PF;
     v[D_EA] = Sa * (q2 * Sa - Sa);
     v[D_ES] = Ss * (q2 * Ss - Ss);

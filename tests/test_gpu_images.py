@@ -312,3 +312,91 @@ def test_refined_chi2_of_noise_free_constraints_vanishes(B, ctx):
     assert float(r1["chi2"][0]) < 1e-10 < 1e-6 < float(r0["chi2"][0])
     print(f"noise-free constraints: chi2 {float(r0['chi2'][0]):.3g} on the grid, "
           f"{float(r1['chi2'][0]):.3g} refined")
+
+
+def _same(a, b):
+    """Bit-identical tensors (NaN slots compare by bit pattern)."""
+    if a.dtype == torch.float64:
+        return torch.equal(a.view(torch.int64), b.view(torch.int64))
+    return torch.equal(a, b)
+
+
+def _image_eager(B, ctx, fixed, free, off, cat, grid, kmax, penalty, refine=None):
+    r = B.chi2_batch(fixed, free, off, cat, mode=B.CHI2_IMAGE, grid=grid, kmax=kmax,
+                     penalty=penalty, want_images=True, refine=refine, ctx=ctx)
+    return {k: v.clone() for k, v in r.items() if hasattr(v, "clone")}, r["overflow"]
+
+
+@pytest.mark.parametrize("resident", [False, True])
+def test_image_plan_replays_equal_eager(B, ctx, resident):
+    """The image-plane pipeline recorded into a graph (Sec. 4.2: sources,
+    deflection grids, triangle search, assignment), with and without the
+    fixed part kept from creation: every replay is bit-identical to the eager
+    batched call on the same inputs (chi^2, counts, missing constraints, image
+    positions), with the program's own eager work between replays, and a
+    replay follows new free parameters written into the same buffers."""
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=20, uneven=True)
+    fixed, free, off = device_model(B, ctx, c)
+    cat = B.catalog_to_device(B.catalog_with_dlsds(c["catalog"], c["zl"]))
+    grid = inputs.pixel_centre_grid(240, -75.0, 75.0)
+    plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, resident=resident, mode=B.CHI2_IMAGE,
+                      grid=grid, kmax=16, penalty=100.0, want_images=True)
+    outs = ("chi2", "nimg", "nmissing", "img_xy")
+    for r in range(3):
+        for k in outs:
+            getattr(plan, k).fill_(-7)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert plan.status() is False
+        eager, ovf = _image_eager(B, ctx, fixed, free, off, cat, grid, 16, 100.0)
+        torch.cuda.synchronize()
+        assert not ovf
+        for k in outs:
+            assert _same(getattr(plan, k), eager[k]), f"replay {r}: {k}"
+        # eager work of the program between replays
+        x = torch.randn(4096, device="cuda").sum()
+        torch.cuda.synchronize()
+        del x
+        free["x0"].add_(0.05)  # the next replay sees new free parameters
+    if resident:
+        before, _ = _image_eager(B, ctx, fixed, free, off, cat, grid, 16, 100.0)
+        fixed["y0"].add_(0.5)  # not seen: the plan read its fixed part at creation
+        plan.launch()
+        torch.cuda.synchronize()
+        assert _same(plan.chi2, before["chi2"]) and _same(plan.nimg, before["nimg"])
+        fixed["y0"].sub_(0.5)
+    plan.close()
+
+
+def test_image_plan_reports_overflow_and_refines(B, ctx):
+    """An image-mode plan's launch does not synchronise: slot overflow is
+    kept in the plan's status word and reported by status(); counts stay
+    exact as in the eager call (which of the overflowing images keep the slots
+    is not fixed, so positions and chi^2 are not compared then).  A plan with
+    Newton refinement replays the eager refined call bit for bit."""
+    from paper_2004_06352_amd import inputs
+    c = inputs.config3(n_samples=4)
+    fixed, free, off = device_model(B, ctx, c)
+    cat = B.catalog_to_device(B.catalog_with_dlsds(c["catalog"], c["zl"]))
+    grid = inputs.pixel_centre_grid(150, -75.0, 75.0)
+    plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, mode=B.CHI2_IMAGE, grid=grid, kmax=1,
+                      penalty=0.0)
+    plan.launch()
+    assert plan.status() is True
+    eager, ovf = _image_eager(B, ctx, fixed, free, off, cat, grid, 1, 0.0)
+    torch.cuda.synchronize()
+    assert ovf and _same(plan.nimg, eager["nimg"])
+    plan.close()
+    grid = inputs.pixel_centre_grid(200, -75.0, 75.0)
+    plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, mode=B.CHI2_IMAGE, grid=grid, kmax=16,
+                      penalty=100.0, want_images=True, refine=(20, 1e-10), resident=True)
+    for r in range(2):
+        plan.launch()
+        eager, ovf = _image_eager(B, ctx, fixed, free, off, cat, grid, 16, 100.0,
+                                  refine=(20, 1e-10))
+        torch.cuda.synchronize()
+        assert plan.status() is False and not ovf
+        for k in ("chi2", "nimg", "nmissing", "img_xy"):
+            assert _same(getattr(plan, k), eager[k]), f"refined replay {r}: {k}"
+    plan.close()
