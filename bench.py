@@ -487,6 +487,8 @@ def main():
     ap.add_argument("--skip-map", action="store_true",
                     help="profiling aid: no map timing; the chi^2 legs only (no JSON line)")
     ap.add_argument("--no-image", action="store_true", help="skip the image-plane chi^2 legs")
+    ap.add_argument("--no-p", action="store_true",
+                    help="skip the 5000^2 x 217 deflection map (context leg)")
     ap.add_argument("--only-chi2-source", action="store_true",
                     help="profiling aid: `--steps` batched source-plane chi^2 calls on the "
                          "4096-sample batch and as many sampler steps, nothing else")
@@ -611,6 +613,23 @@ def main():
     secondary["derived_map_fp64_evals_per_s"] = evals * nd / wd
     secondary["derived_map_fp64_avg_launch_ms"] = ed * 1e3
     del od
+    # context: a deflection map of the paper's headline shape (5000^2 grid over
+    # 150", 217 potentials), FP64, deflection only as the paper's gradient map
+    # (0.93 s on one P100 for its own lens model, Sec. 5)
+    if not args.no_p:
+        cp = inputs.config_p()
+        tp = B.table_from_physical(B.to_device(cp["pots"], B.PHYS_KEYS), 0, ctx)
+        npx, npy = cp["grid"][0], cp["grid"][1]
+        fp = B.dlsds(cp["zl"], cp["zs"])
+        op = {k: torch.empty((npy, npx), dtype=torch.float64, device="cuda") for k in ("ax", "ay")}
+        gmap = lambda: B.grad_map(tp, cp["grid"], fp, B.FP64, ctx=ctx, out=op)
+        wg, eg = timed_steps(gmap, 5, 2, torch)
+        ev_p = npx * npy * int(cp["pots"]["x0"].size)
+        secondary["map_P_grad_fp64"] = {"workload": cp["name"], "ms_per_map": eg * 1e3,
+                                        "evals_per_s": ev_p / eg,
+                                        "paper_single_gpu_s": 0.93,
+                                        "paper_single_gpu_evals_per_s": ev_p / 0.93}
+        del op, tp
     # lensing potential (FP64), one plane
     op = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
     wp, ep = timed_steps(lambda: B.potential_map(table, grid, f, ctx=ctx, out=op), nd, 1, torch)

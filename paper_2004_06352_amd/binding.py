@@ -273,13 +273,17 @@ def _out_dtype(prec):
     return torch.float64 if prec == FP64 else torch.float32
 
 
-def grad_map(table, grid, dlsds=1.0, prec=FP64, ctx=None):
-    """(ax, ay), each (ny, nx): dlsds times the summed deflection."""
+def grad_map(table, grid, dlsds=1.0, prec=FP64, ctx=None, out=None):
+    """(ax, ay), each (ny, nx): dlsds times the summed deflection (into
+    out["ax"], out["ay"] when given)."""
     ctx = _ctx(ctx)
     nx, ny = int(grid[0]), int(grid[1])
     dev = table["x0"].device
-    ax = torch.empty((ny, nx), dtype=_out_dtype(prec), device=dev)
-    ay = torch.empty_like(ax)
+    if out is not None:
+        ax, ay = out["ax"], out["ay"]
+    else:
+        ax = torch.empty((ny, nx), dtype=_out_dtype(prec), device=dev)
+        ay = torch.empty_like(ax)
     T, G = _pot(table), _grid(grid)
     _check(lib().lens_grad_map(ctx.handle, C.byref(T), C.byref(G), float(dlsds), prec,
                                _ptr(ax), _ptr(ay), _stream(dev)))

@@ -211,18 +211,30 @@ __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *t
 // its register allocation.
 template <int PREC, bool MCMC = false, bool DERIVE = false>
 __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4)) chi2_src_kernel(Chi2SrcLaunch a) {
-    // LDS: [2][nimg] unlensed x, y, [nimg] each image's 1/sigma^2 when the
-    // catalogue is small enough (stage_sig), then the staged potentials
+    // LDS: [2][nimg] unlensed x, y; when the catalogue is small enough
+    // (stage_sig) each image's 1/sigma^2 and Dls/Ds [2][nimg]; the staged
+    // potentials (FP64, then FP32); then, with stage_sig, the nsys + 1 image
+    // offsets
     extern __shared__ double sh[];
-    double *sx = sh, *sy = sh + a.nimg, *ss = sh + 2 * (size_t)a.nimg;
-    double *pd = sh + (2 + a.stage_sig) * (size_t)a.nimg;
+    const int narr = a.stage_sig ? 4 : 2;
+    double *sx = sh, *sy = sh + a.nimg;
+    double *sw = sh + 2 * (size_t)a.nimg, *sf = sh + 3 * (size_t)a.nimg;
+    double *pd = sh + narr * (size_t)a.nimg;
     float *pf = reinterpret_cast<float *>(pd + (size_t)a.chunk * NDER);
+    // (the FP32 block of the staged potentials exists only for PREC != 0)
+    int *soff = reinterpret_cast<int *>(pf + (PREC != 0 ? (size_t)a.chunk * NDERF : 0));
     const int lane = threadIdx.x;
     const int pad = a.nimg_pad, st = a.freet.stride, nf = a.freet.n;
-    // the weights do not depend on the sample: staged once per wave (the
-    // first __syncthreads of the sample loop orders them before their use)
-    if (a.stage_sig)
-        for (int t = lane; t < a.nimg; t += 64) ss[t] = a.rec[3 * (size_t)pad + t];
+    // what does not depend on the sample is staged once per wave (the first
+    // __syncthreads of the sample loop orders it before its use): then the
+    // reduction reads LDS only, with no memory latency in its loops
+    if (a.stage_sig) {
+        for (int t = lane; t < a.nimg; t += 64) {
+            sw[t] = a.rec[3 * (size_t)pad + t];
+            sf[t] = a.rec[2 * (size_t)pad + t];
+        }
+        for (int i = lane; i <= a.nsys; i += 64) soff[i] = min(max(a.img_off[i], 0), a.nimg);
+    }
     for (int m = a.sample0 + blockIdx.x; m < a.n_samples; m += gridDim.x) {
         int k0, k1;
         bool in = false;
@@ -331,21 +343,44 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
                     }
                 }
             }
+            if (a.stage_sig) {
 #pragma unroll
-            for (int j = 0; j < SRC_IPL; ++j) {
-                const int t = g0 + j * 64 + lane;
-                if (t < a.nimg) {
-                    const double f = a.rec[2 * (size_t)pad + t];
-                    sx[t] = x[j] - f * acc[j][0];
-                    sy[t] = y[j] - f * acc[j][1];
+                for (int j = 0; j < SRC_IPL; ++j) {
+                    const int t = g0 + j * 64 + lane;
+                    if (t < a.nimg) {
+                        const double f = sf[t];
+                        sx[t] = x[j] - f * acc[j][0];
+                        sy[t] = y[j] - f * acc[j][1];
+                    }
+                }
+            } else {
+                double f[SRC_IPL];
+#pragma unroll
+                for (int j = 0; j < SRC_IPL; ++j) {
+                    const int t = g0 + j * 64 + lane;
+                    f[j] = t < a.nimg ? a.rec[2 * (size_t)pad + t] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < SRC_IPL; ++j) {
+                    const int t = g0 + j * 64 + lane;
+                    if (t < a.nimg) {
+                        sx[t] = x[j] - f[j] * acc[j][0];
+                        sy[t] = y[j] - f[j] * acc[j][1];
+                    }
                 }
             }
         }
         __syncthreads();
         double part = 0.0;
         for (int i = lane; i < a.nsys; i += 64) {
-            const int o0 = min(max(a.img_off[i], 0), a.nimg);
-            const int o1 = min(max(a.img_off[i + 1], o0), a.nimg);
+            int o0, o1;
+            if (a.stage_sig) {
+                o0 = soff[i];
+                o1 = max(soff[i + 1], o0);
+            } else {
+                o0 = min(max(a.img_off[i], 0), a.nimg);
+                o1 = min(max(a.img_off[i + 1], o0), a.nimg);
+            }
             const int M = o1 - o0;
             double mx = 0.0, my = 0.0;
             for (int t = o0; t < o1; ++t) {
@@ -358,10 +393,16 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
                 my *= im;
             }
             double s = 0.0;
-            for (int t = o0; t < o1; ++t) {
-                const double ex = sx[t] - mx, ey = sy[t] - my;
-                const double w = a.stage_sig ? ss[t] : a.rec[3 * (size_t)pad + t];
-                s = fma(ex * ex + ey * ey, w, s);
+            if (a.stage_sig) {
+                for (int t = o0; t < o1; ++t) {
+                    const double ex = sx[t] - mx, ey = sy[t] - my;
+                    s = fma(ex * ex + ey * ey, sw[t], s);
+                }
+            } else {
+                for (int t = o0; t < o1; ++t) {
+                    const double ex = sx[t] - mx, ey = sy[t] - my;
+                    s = fma(ex * ex + ey * ey, a.rec[3 * (size_t)pad + t], s);
+                }
             }
             part += s;
             if (a.src_x) {
@@ -399,15 +440,22 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
 
 // LDS: the unlensed positions plus a chunk of staged potentials; the chunk
 // shrinks for large catalogues so that a block stays within 64 KiB.
-// Per-image LDS arrays: 3 (sigma staged) when they leave room for a full
-// chunk of potentials, else 2.
-static int src_img_arrays(int nimg, int prec) {
+// LDS of the per-sample kernel: per-image arrays (4 with the sample-independent
+// constants staged, else 2), a chunk of staged potentials, and with the
+// staging the image offsets.  Staged when that fits a budget that keeps 16
+// one-wave blocks on a CU (160 KiB of LDS) with a full chunk.
+constexpr size_t SRC_LDS_BUDGET = 10240;
+static size_t src_lds(int nimg, int nsys, int prec, int chunk, bool staged) {
     const size_t per = NDER * sizeof(double) + (prec ? NDERF * sizeof(float) : 0);
-    return 3 * (size_t)nimg * sizeof(double) + SRC_CHUNK_MAX * per <= 65536 ? 3 : 2;
+    return (staged ? 4 : 2) * (size_t)nimg * sizeof(double) + (size_t)chunk * per +
+           (staged ? ((size_t)nsys + 1) * sizeof(int) : 0);
 }
-static int src_chunk(int nimg, int prec, int arrays) {
+static bool src_staged(int nimg, int nsys, int prec) {
+    return src_lds(nimg, nsys, prec, SRC_CHUNK_MAX, true) <= SRC_LDS_BUDGET;
+}
+static int src_chunk(int nimg, int prec) {
     const size_t per = NDER * sizeof(double) + (prec ? NDERF * sizeof(float) : 0);
-    const size_t avail = 65536 - arrays * (size_t)nimg * sizeof(double);
+    const size_t avail = 65536 - 2 * (size_t)nimg * sizeof(double);
     return (int)std::max<size_t>(1, std::min<size_t>(SRC_CHUNK_MAX, avail / per));
 }
 
@@ -443,12 +491,9 @@ hipError_t launch_chi2_prep(const Chi2SrcLaunch &c0, hipStream_t st) {
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
     Chi2SrcLaunch c = c0;
     c.S = make_series();
-    const int arrays = src_img_arrays(c.nimg, c.prec);
-    c.stage_sig = arrays == 3;
-    c.chunk = src_chunk(c.nimg, c.prec, arrays);
-    const size_t shmem =
-        arrays * (size_t)c.nimg * sizeof(double) +
-        (size_t)c.chunk * (NDER * sizeof(double) + (c.prec ? NDERF * sizeof(float) : 0));
+    c.stage_sig = src_staged(c.nimg, c.nsys, c.prec);
+    c.chunk = c.stage_sig ? SRC_CHUNK_MAX : src_chunk(c.nimg, c.prec);
+    const size_t shmem = src_lds(c.nimg, c.nsys, c.prec, c.chunk, c.stage_sig);
     if (shmem > 65536) return hipErrorInvalidValue;
     const dim3 grid(c.grid_blocks), block(64);
     if (c.prec == 0 && c.derive_free)
@@ -468,11 +513,9 @@ hipError_t launch_mcmc_chi2(const Chi2SrcLaunch &c0, hipStream_t st) {
     if (c.n_samples <= 0) return hipSuccess;
     c.S = make_series();
     c.prec = 0;
-    const int arrays = src_img_arrays(c.nimg, 0);
-    c.stage_sig = arrays == 3;
-    c.chunk = src_chunk(c.nimg, 0, arrays);
-    const size_t shmem =
-        arrays * (size_t)c.nimg * sizeof(double) + (size_t)c.chunk * NDER * sizeof(double);
+    c.stage_sig = src_staged(c.nimg, c.nsys, 0);
+    c.chunk = c.stage_sig ? SRC_CHUNK_MAX : src_chunk(c.nimg, 0);
+    const size_t shmem = src_lds(c.nimg, c.nsys, 0, c.chunk, c.stage_sig);
     if (shmem > 65536) return hipErrorInvalidValue;
     hipLaunchKernelGGL((chi2_src_kernel<0, true>), dim3(c.grid_blocks), dim3(64), shmem, st, c);
     return hipGetLastError();

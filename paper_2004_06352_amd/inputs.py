@@ -111,6 +111,18 @@ def config2(seed=2, n=2048, n_gal=500):
                 grid=pixel_centre_grid(n, -100.0, 100.0), zl=ZL, zs=2.0)
 
 
+def config_p(seed=7, n=5000, n_gal=215):
+    """The shape of the paper's headline map (Sec. 5: a 5000^2 grid over
+    150 arcsec, 217 potentials): 5000^2 pixel centres over [-75, 75]^2, the
+    two cluster dPIEs of workload 2 plus 215 Schechter galaxies over the
+    field.  The paper's lens model itself is not available; this stands in
+    for its sizes only."""
+    rng = np.random.default_rng(seed)
+    pots = concat(_table([CLUSTER1, CLUSTER2]), galaxies(rng, n_gal, -75.0, 75.0))
+    return dict(name=f"cfgP_{n}sq_{2 + n_gal}pot", pots=pots,
+                grid=pixel_centre_grid(n, -75.0, 75.0), zl=ZL, zs=2.0)
+
+
 # --- the config-3 model: 6 free dPIEs with uniform priors + 300 fixed galaxies
 # (lo, hi) per physical parameter in PHYS_KEYS order
 _FREE_PRIORS = [
