@@ -87,6 +87,17 @@ __device__ __forceinline__ double rsq64(double x) {
     return fma(y, fma(-0.5 * x, y * y, 0.5), y);
 }
 
+// 2/sqrt(T) from the estimate w by the same Newton step written as
+// w (3 - T w^2) (three instructions: the halving of the step is left in the
+// result).  The elliptical forms hold T = R/4, a quarter of the squared
+// radius R = psi^2/k^2, so this is 4/sqrt(R), and T times it is sqrt(R).
+// Relative error: about 1.5 times the square of the estimate's plus three
+// roundings (4.5e-15 at most over the measured estimate range).
+__device__ __forceinline__ double rsq2q(double T) {
+    const double w = __builtin_amdgcn_rsq(T);
+    return w * fma(-T, w * w, 3.0);
+}
+
 constexpr double kPi2 = 1.5707963267948966;
 constexpr double kPi4 = 0.7853981633974483;
 constexpr double kSqrt2 = 1.4142135623730951;
@@ -186,27 +197,28 @@ __device__ __forceinline__ double atanh_finish(const AtanhRed &r, double s, cons
 }
 
 // ---------------------------------------------------------------------------
-// SING: the potential has rcore = 0, and its contribution at its own centre
-// is zero (handled by a separate instance so that regular potentials carry no
-// test for it).
-template <bool GRAD, bool HESS, bool SING, bool SHORT>
-__device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, double x, double y,
-                                                  double acc[5], const Series &S) {
-    double dx = x - c[D_X0];
-    double dy = y - c[D_Y0];
-    bool zero = false;
-    if (SING) {
-        zero = (dx == 0.0) & (dy == 0.0);
-        if (zero) dx = 1.0;  // any regular point; the contribution is dropped
-    }
+// A potential with rcore = 0 (K_SING) contributes zero at its own centre
+// (where the closed forms give NaN): one block at the end, guarded by the kind
+// bit, after the body that every kind shares (on a wave-uniform kind a scalar
+// branch that regular potentials skip; the accumulators stay in one set of
+// registers).
+//
+// The point enters as its offsets (dx, dy) from the centre with dy cos(phi) and
+// dy sin(phi) (dyc, dys): a caller whose points share a row forms the last two
+// once per potential.
+template <bool GRAD, bool HESS, bool SHORT>
+__device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, double dx, double dy,
+                                                  double dyc, double dys, double acc[5],
+                                                  const Series &S) {
     const double cp = c[D_C], sp = c[D_S];
-    const double xp = fma(dx, cp, dy * sp);
-    const double yp = fma(dy, cp, -(dx * sp));
+    const double xp = fma(dx, cp, dys);
+    const double yp = fma(-sp, dx, dyc);
     const double x2 = xp * xp, y2 = yp * yp;
     // htr, hdf: psi_xx + psi_yy and psi_xx - psi_yy; hxy holds -psi_xy
     double ax = 0.0, ay = 0.0, htr = 0.0, hdf = 0.0, hxy = 0.0;
-    // Two cores (ra, rs: 1/psi_w; iDa, iDs: 1/D_w): trace r_a - r_s, and the
-    // difference and -psi_xy from h_w = 1/(psi_w D_w).
+    // Two cores (ra, rs: 1/psi_w up to the form's constant factor; iDa, iDs:
+    // 1/D_w): trace r_a - r_s, and the difference and -psi_xy from
+    // h_w = 1/(psi_w D_w).
     const auto hess2 = [&](double ra, double rs, double iDa, double iDs) {
         const double ha = ra * iDa, hs = rs * iDs;
         const double dh = ha - hs;
@@ -225,14 +237,15 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
     // work with every length of the closed form divided by k (psi_w/k, A_w/k,
     // B_w/k): the ratios k x'/A_w and k y'/B_w lose their k and D_w/k^2 =
     // A_w^2/k^2 + x'^2; the Hessian constants carry the factors k and 1/k^3
-    // this leaves on the trace and on the other parts.
+    // this leaves on the trace and on the other parts, and the factor 1/4 of
+    // ra, rs = 4 k/psi_w (from rsq2q of the quarter radii ta, ts).
     switch (kind & (K_CUT | K_ELL)) {
     case K_CUT | K_ELL: {
-        // psi_w^2/k^2, the second as the first plus (C_s - C_a)/k^2; psi_w/k
-        // enters A_w/k and B_w/k through one FMA each
+        // psi_w^2/(4 k^2), the second as the first plus (C_s - C_a)/(4 k^2);
+        // psi_w/k = ta ra enters A_w/k and B_w/k through one FMA each
         const double ta = fma(c[D_EQ2], x2, fma(c[D_EK2I], y2, c[D_ECA]));
         const double ts = ta + c[D_DC];
-        const double ra = rsq64(ta), rs = rsq64(ts);
+        const double ra = rsq2q(ta), rs = rsq2q(ts);
         const double A1 = fma(ta, ra, c[D_ESA]), A2 = fma(ts, rs, c[D_ESS]);
         // one reciprocal (a quarter-rate instruction) of D_a D_s Dx Dy serves
         // the Hessian denominators and the ratios' denominators Dx = A_a A_s +
@@ -314,9 +327,9 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         break;
     }
     case K_ELL: {
-        // lengths divided by k as in the two-core form
+        // lengths divided by k and quarter radius as in the two-core form
         const double ta = fma(c[D_EQ2], x2, fma(c[D_EK2I], y2, c[D_ECA]));
-        const double ra = rsq64(ta);
+        const double ra = rsq2q(ta);
         const double A1 = fma(ta, ra, c[D_ESA]);
         const double B1 = fma(ta, ra, c[D_EQ2SA]);
         const double Da = fma(A1, A1, x2);
@@ -350,7 +363,12 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
         break;
     }
     }
-    if (SING && zero) ax = ay = htr = hdf = hxy = 0.0;
+    if (kind & K_SING) {
+        // (an empty volatile statement keeps this a branch: the compiler may
+        // not turn it into selects executed for every potential)
+        asm volatile("");
+        if ((dx == 0.0) & (dy == 0.0)) ax = ay = htr = hdf = hxy = 0.0;
+    }
     // rotate back and accumulate, the prefactors folded into the rotation
     // constants (ax, ay, htr, hdf, hxy above carry no PF or HF)
     if (GRAD) {
@@ -376,14 +394,20 @@ __device__ __forceinline__ void eval_pot_f64_impl(const ConstD c, int kind, doub
 // may hold a different potential and the branches diverge.
 // SHORT: the two-core elliptical form first tries the shorter polynomials
 // (worth it where most waves are far from every core, as on a map).
+template <bool GRAD, bool HESS, bool SHORT = false>
+__device__ __forceinline__ void eval_pot_f64_rel(const ConstD c, int kind, double dx, double dy,
+                                                 double dyc, double dys, double acc[5],
+                                                 const Series &S) {
+    eval_pot_f64_impl<GRAD, HESS, SHORT>(c, kind, dx, dy, dyc, dys, acc, S);
+}
+
 template <bool GRAD, bool HESS, bool UNIF = true, bool SHORT = false>
 __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y, double acc[5],
                                              const Series &S) {
     const int kind = UNIF ? uniform_kind(c[D_KIND]) : kind_bits(c[D_KIND]);
-    if (kind & K_SING)
-        eval_pot_f64_impl<GRAD, HESS, true, SHORT>(c, kind, x, y, acc, S);
-    else
-        eval_pot_f64_impl<GRAD, HESS, false, SHORT>(c, kind, x, y, acc, S);
+    const double dy = y - c[D_Y0];
+    eval_pot_f64_rel<GRAD, HESS, SHORT>(c, kind, x - c[D_X0], dy, dy * c[D_C], dy * c[D_S], acc,
+                                        S);
 }
 
 // Deflection of one two-core elliptical potential (kind K_CUT | K_ELL, rcore >
@@ -408,11 +432,11 @@ __device__ __forceinline__ void grad_cut_ell_full(const ConstD c, const double *
     for (int p = 0; p < NP; ++p) {
         const double dx = x[p] - x0, dy = y[p] - y0;
         const double xp = fma(dx, cp, dy * sp);
-        const double yp = fma(dy, cp, -(dx * sp));
+        const double yp = fma(-sp, dx, dy * cp);
         const double x2 = xp * xp, y2 = yp * yp;
         const double ta = fma(eq2, x2, fma(ek2i, y2, eca));
         const double ts = ta + dc;
-        const double ra = rsq64(ta), rs = rsq64(ts);
+        const double ra = rsq2q(ta), rs = rsq2q(ts);
         const double A1 = fma(ta, ra, esa), A2 = fma(ts, rs, ess);
         const double B1 = fma(ta, ra, eq2sa), B2 = fma(ts, rs, eq2ss);
         const double Dx = fma(A1, A2, x2);
@@ -641,14 +665,21 @@ __device__ __forceinline__ void eval_pot_f32_impl(const ConstD c, const ConstF f
     }
 }
 
-template <bool GRAD, bool HESS, bool UNIF = true, bool SHORT = false>
-__device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, double x, double y,
-                                             float out[5], const Series &S) {
-    const int kind = UNIF ? uniform_kind(c[D_KIND]) : kind_bits(c[D_KIND]);
+template <bool GRAD, bool HESS, bool SHORT = false>
+__device__ __forceinline__ void eval_pot_f32_kind(const ConstD c, const ConstF f, int kind,
+                                                  double x, double y, float out[5],
+                                                  const Series &S) {
     if (kind & K_SING)
         eval_pot_f32_impl<GRAD, HESS, true, SHORT>(c, f, kind, x, y, out, S);
     else
         eval_pot_f32_impl<GRAD, HESS, false, SHORT>(c, f, kind, x, y, out, S);
+}
+
+template <bool GRAD, bool HESS, bool UNIF = true, bool SHORT = false>
+__device__ __forceinline__ void eval_pot_f32(const ConstD c, const ConstF f, double x, double y,
+                                             float out[5], const Series &S) {
+    const int kind = UNIF ? uniform_kind(c[D_KIND]) : kind_bits(c[D_KIND]);
+    eval_pot_f32_kind<GRAD, HESS, SHORT>(c, f, kind, x, y, out, S);
 }
 
 // Neumaier compensated addition: s + c carries the sum to about twice the

@@ -39,19 +39,21 @@ enum DerivedIndex : int {
     D_X0 = 0, D_Y0, D_C, D_S,          // centre, cos(phi), sin(phi)
     D_PFC, D_PFS,                      // PF c, PF s: deflection rotated back
     D_HT, D_HCMH, D_HCS, D_HCS2, D_HCMS,  // HF/2, HF (c^2 - s^2)/2, HF c s, 2 HF c s, HF (c^2 - s^2);
-                                       // for eps > 0 times 1/k (D_HT) and 1/k^3 (the rest)
+                                       // for eps > 0 times 1/k (D_HT) and 1/k^3 (the rest),
+                                       // and 1/4 (the quarter radii below)
     D_Q2,                              // q^2
     D_CA, D_CS_, D_SA, D_SS,           // C_a = q^2 S_a^2, C_s, S_a, S_s
     D_Q2SA, D_Q2SS,                    // q^2 S_a, q^2 S_s
-    D_DC, D_DS,                        // C_s - C_a (divided by k^2 for eps > 0, as the
-                                       // D_E* entries), S_s - S_a
+    D_DC, D_DS,                        // C_s - C_a (divided by 4 k^2 for eps > 0, as the
+                                       // D_EQ2 .. D_ECS entries), S_s - S_a
     D_LA, D_LS, D_LC,                  // eps > 0, the potential's log terms: PF k S_a/2,
                                        // PF k S_s/2, PF k ln(k) (S_a - S_s)
     D_PF,                              // deflection prefactor (F included)
     D_EA, D_ES,                        // E_a, E_s
-    // eps > 0: the lengths of the closed form divided by k (unscaled for eps = 0)
-    D_EQ2, D_EK2I,                     // q^2/k^2, 1/k^2 (the squared radius R/k^2)
-    D_ECA, D_ECS, D_ESA, D_ESS,        // C_a/k^2, C_s/k^2, S_a/k, S_s/k
+    // eps > 0: the lengths of the closed form divided by k, the squared ones
+    // also by 4 (a quarter of the squared radius R/k^2; unscaled for eps = 0)
+    D_EQ2, D_EK2I,                     // q^2/(4 k^2), 1/(4 k^2)
+    D_ECA, D_ECS, D_ESA, D_ESS,        // C_a/(4 k^2), C_s/(4 k^2), S_a/k, S_s/k
     D_EQ2SA, D_EQ2SS,                  // q^2 S_a/k, q^2 S_s/k
     D_KIND,                            // kind bits: low word of the entry's bit pattern
     NDER
@@ -59,7 +61,8 @@ enum DerivedIndex : int {
 // Float copy of the constants used after the FP64 offset/rotation step.  For
 // eps > 1e-8 (K_ELL32) the FP32 evaluation takes the lengths divided by k as
 // the FP64 one does (F_Q2 .. F_Q2SS, F_K2I and the Hessian constants as the
-// D_E* and D_H* entries); below, it takes the circular forms (they differ from
+// D_E* and D_H* entries without their factor 1/4); below, it takes the
+// circular forms (they differ from
 // the elliptical ones at first order in eps, far below FP32 rounding), with
 // the circular prefactor in F_PFC, F_PFS.
 enum DerivedIndexF : int {

@@ -161,6 +161,16 @@ __device__ __forceinline__ double uniform_f64(double v) {
     return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
                             __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
+// &base[off] for a wave-uniform off, the address held in a vector register:
+// entries addressed from it are read with one vector add for their address
+// (left to itself the compiler keeps a uniform address in a scalar register
+// and copies it to a vector register before each group of reads).
+__device__ __forceinline__ const double *lds_entry(const double *base, int off) {
+    int v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(off * (int)sizeof(double)));
+    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + v);
+}
+
 struct MapArgs {
     Derived tab;
     GridArgs g;
@@ -235,50 +245,80 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
         S.ats[0] = vgpr_f64(a.S.ats[0]);
         S.ahs[0] = vgpr_f64(a.S.ahs[0]);
     }
-    auto body = [&](const ConstD cd, const ConstF cf) {
+    // one potential (kind: its wave-uniform kind bits) at the thread's pixels;
+    // they share the row, so dy and its rotated parts are formed once
+    auto body = [&](const ConstD cd, const ConstF cf, int kind) {
+        if (PREC == 0) {
+            const double dy = y - cd[D_Y0];
+            const double dyc = dy * cd[D_C], dys = dy * cd[D_S], x0 = cd[D_X0];
+#pragma unroll
+            for (int p = 0; p < PPT; ++p)
+                eval_pot_f64_rel<GRAD, HESS, true>(cd, kind, x[p] - x0, dy, dyc, dys, acc[p], S);
+            return;
+        }
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-            if (PREC == 0) {
-                eval_pot_f64<GRAD, HESS, true, true>(cd, x[p], y, acc[p], S);
-            } else {
-                float o[5];
-                eval_pot_f32<GRAD, HESS, true, true>(cd, cf, x[p], y, o, a.S);
+            float o[5];
+            eval_pot_f32_kind<GRAD, HESS, true>(cd, cf, kind, x[p], y, o, a.S);
 #pragma unroll
-                for (int ch = 0; ch < 5; ++ch) {
-                    const bool used = (ch < 2) ? GRAD : HESS;
-                    if (!used) continue;
-                    if (PREC == 1)
-                        acc[p][ch] += (double)o[ch];
-                    else
-                        neumaier_add(fs[p][ch], fc[p][ch], o[ch]);
-                }
+            for (int ch = 0; ch < 5; ++ch) {
+                const bool used = (ch < 2) ? GRAD : HESS;
+                if (!used) continue;
+                if (PREC == 1)
+                    acc[p][ch] += (double)o[ch];
+                else
+                    neumaier_add(fs[p][ch], fc[p][ch], o[ch]);
             }
         }
     };
 
     if (STAGE) {
         const int chunk = a.chunk;
-        const int nt = bx * by, tid = threadIdx.y * bx + threadIdx.x;
+        // waves of the block (block_x is a multiple of 64) and lane in the wave
+        const int tid = threadIdx.y * bx + threadIdx.x;
+        const int wv = tid >> 6, lane = tid & 63, nw = (bx * by) >> 6;
         float *ldsf = reinterpret_cast<float *>(lds + (size_t)chunk * NDER);
         for (int k0 = 0; k0 < n; k0 += chunk) {
             const int cnt = min(chunk, n - k0);
             __syncthreads();
-            for (int e = tid; e < cnt * NDER; e += nt) {
-                const int ci = e / cnt, kk = e - ci * cnt;
-                lds[kk * NDER + ci] = a.tab.d[(size_t)ci * st + k0 + kk];
+            // wave wv copies the constants wv, wv + nw, ... of the chunk's
+            // potentials, its lanes consecutive potentials (coalesced reads)
+            for (int ci = wv; ci < NDER; ci += nw) {
+                const double *src = a.tab.d + (size_t)ci * st + k0;
+                for (int kk = lane; kk < cnt; kk += 64) lds[kk * NDER + ci] = src[kk];
             }
             if (PREC != 0) {
-                for (int e = tid; e < cnt * NDERF; e += nt) {
-                    const int ci = e / cnt, kk = e - ci * cnt;
-                    ldsf[kk * NDERF + ci] = a.tab.f[(size_t)ci * st + k0 + kk];
+                for (int ci = wv; ci < NDERF; ci += nw) {
+                    const float *src = a.tab.f + (size_t)ci * st + k0;
+                    for (int kk = lane; kk < cnt; kk += 64) ldsf[kk * NDERF + ci] = src[kk];
                 }
             }
             __syncthreads();
-            for (int kk = 0; kk < cnt; ++kk)
-                body(ConstD{lds + kk * NDER, 1}, ConstF{ldsf + kk * NDERF, 1});
+            for (int kb = 0; kb < cnt; kb += 64) {
+                // the kinds of the next (up to) 64 potentials as one bit mask
+                // per kind bit (lane l reads potential kb + l), so that the
+                // loop takes each potential's kind in scalar registers
+                const int m = min(64, cnt - kb);
+                const int kl = lane < m ? kind_bits(lds[(kb + lane) * NDER + D_KIND]) : 0;
+                const unsigned long long m_ell = __builtin_amdgcn_ballot_w64(kl & K_ELL);
+                const unsigned long long m_cut = __builtin_amdgcn_ballot_w64(kl & K_CUT);
+                const unsigned long long m_sing = __builtin_amdgcn_ballot_w64(kl & K_SING);
+                const unsigned long long m_e32 = __builtin_amdgcn_ballot_w64(kl & K_ELL32);
+                const double *row = lds_entry(lds, kb * NDER);
+                for (int i = 0; i < m; ++i) {
+                    const int kind = (int)((m_ell >> i) & 1) * K_ELL |
+                                     (int)((m_cut >> i) & 1) * K_CUT |
+                                     (int)((m_sing >> i) & 1) * K_SING |
+                                     (int)((m_e32 >> i) & 1) * K_ELL32;
+                    body(ConstD{row + i * NDER, 1},
+                         ConstF{ldsf + (kb + i) * NDERF, 1}, kind);
+                }
+            }
         }
     } else {
-        for (int k = 0; k < n; ++k) body(ConstD{a.tab.d + k, st}, ConstF{a.tab.f + k, st});
+        for (int k = 0; k < n; ++k)
+            body(ConstD{a.tab.d + k, st}, ConstF{a.tab.f + k, st},
+                 uniform_kind(a.tab.d[(size_t)D_KIND * st + k]));
     }
 
     if (j >= a.g.ny) return;

@@ -66,7 +66,7 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
     }
     const double cp = c[D_C], sp = c[D_S];
     const double xp = fma(dx, cp, dy * sp);
-    const double yp = fma(dy, cp, -(dx * sp));
+    const double yp = fma(-sp, dx, dy * cp);
     const double x2 = xp * xp, y2 = yp * yp;
     double v = 0.0;
     // Elliptical forms in the lengths divided by k, as in the deflection map:
@@ -76,7 +76,7 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
     case K_CUT | K_ELL: {
         const double ta = fma(c[D_EQ2], x2, fma(c[D_EK2I], y2, c[D_ECA]));
         const double ts = ta + c[D_DC];
-        const double ra = rsq64(ta), rs = rsq64(ts);
+        const double ra = rsq2q(ta), rs = rsq2q(ts);  // quarter radii, as in the map
         const double A1 = fma(ta, ra, c[D_ESA]), A2 = fma(ts, rs, c[D_ESS]);
         const double B1 = fma(ta, ra, c[D_EQ2SA]), B2 = fma(ts, rs, c[D_EQ2SS]);
         const double Dx = fma(A1, A2, x2);
@@ -128,7 +128,7 @@ __device__ __forceinline__ double eval_psi_f64(const ConstD c, double x, double 
     }
     case K_ELL: {
         const double ta = fma(c[D_EQ2], x2, fma(c[D_EK2I], y2, c[D_ECA]));
-        const double ra = rsq64(ta);
+        const double ra = rsq2q(ta);
         const double A1 = fma(ta, ra, c[D_ESA]);
         const double B1 = fma(ta, ra, c[D_EQ2SA]);
         const AtanRed ra_ = atan_reduce(xp, A1);

@@ -59,14 +59,16 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_PFC] = PF * c;
     v[D_PFS] = PF * sn;
     // Hessian constants: the FP64 evaluation of an elliptical potential
-    // leaves a factor k on the trace and 1/k^3 on the other parts
+    // leaves a factor k on the trace and 1/k^3 on the other parts, and works
+    // with quarter radii (its 1/psi_w carry a factor 4, taken out here by h4)
     const double kap = ell ? 1.0 / k1 : 1.0, kap2 = kap * kap, kap3 = kap2 * kap;
+    const double h4 = ell ? 0.25 : 1.0;
     const double hcms = HF * (c * c - sn * sn), hcs = HF * (c * sn);
-    v[D_HT] = kap * (0.5 * HF);
-    v[D_HCMS] = kap3 * hcms;
-    v[D_HCMH] = kap3 * (0.5 * hcms);
-    v[D_HCS] = kap3 * hcs;
-    v[D_HCS2] = kap3 * (2.0 * hcs);
+    v[D_HT] = h4 * (kap * (0.5 * HF));
+    v[D_HCMS] = h4 * (kap3 * hcms);
+    v[D_HCMH] = h4 * (kap3 * (0.5 * hcms));
+    v[D_HCS] = h4 * (kap3 * hcs);
+    v[D_HCS2] = h4 * (kap3 * (2.0 * hcs));
     v[D_Q2] = q2;
     v[D_CA] = q2 * Sa * Sa;
     v[D_CS_] = q2 * Ss * Ss;
@@ -74,7 +76,7 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_SS] = Ss;
     v[D_Q2SA] = q2 * Sa;
     v[D_Q2SS] = q2 * Ss;
-    v[D_DC] = kap2 * DC;
+    v[D_DC] = h4 * (kap2 * DC);
     v[D_DS] = DS;
     const double pk = ell ? PF * k1 : 0.0;  // F b0 (1 - eps)
     v[D_LA] = 0.5 * pk * Sa;
@@ -83,10 +85,10 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     v[D_PF] = PF;
     v[D_EA] = Sa * (q2 * Sa - Sa);
     v[D_ES] = Ss * (q2 * Ss - Ss);
-    v[D_EQ2] = kap2 * q2;
-    v[D_EK2I] = kap2;
-    v[D_ECA] = kap2 * v[D_CA];
-    v[D_ECS] = kap2 * v[D_CS_];
+    v[D_EQ2] = h4 * (kap2 * q2);
+    v[D_EK2I] = h4 * kap2;
+    v[D_ECA] = h4 * (kap2 * v[D_CA]);
+    v[D_ECS] = h4 * (kap2 * v[D_CS_]);
     v[D_ESA] = kap * Sa;
     v[D_ESS] = kap * Ss;
     v[D_EQ2SA] = kap * v[D_Q2SA];
