@@ -175,6 +175,9 @@ constexpr int SRC_IPL = 4;
 // stage them.
 constexpr int SRC_CHUNK_MAX = 8;
 constexpr int SRC_STAGE_LOADS = (SRC_CHUNK_MAX * NDER + 63) / 64;
+// Staged per-image constants and image offsets: at most this many per lane
+// (the staging is used only when nimg and nsys + 1 fit).
+constexpr int SRC_SIG_LOADS = 4;
 
 // The sampler's walker: physical parameters of its potential k (the proposal
 // theta + step (2u - 1) when `in`, else the current state; the same rounded
@@ -225,18 +228,54 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
     int *soff = reinterpret_cast<int *>(pf + (PREC != 0 ? (size_t)a.chunk * NDERF : 0));
     const int lane = threadIdx.x;
     const int pad = a.nimg_pad, st = a.freet.stride, nf = a.freet.n;
-    // what does not depend on the sample is staged once per wave (the first
-    // __syncthreads of the sample loop orders it before its use): then the
-    // reduction reads LDS only, with no memory latency in its loops
-    if (a.stage_sig) {
-        for (int t = lane; t < a.nimg; t += 64) {
-            sw[t] = a.rec[3 * (size_t)pad + t];
-            sf[t] = a.rec[2 * (size_t)pad + t];
-        }
-        for (int i = lane; i <= a.nsys; i += 64) soff[i] = min(max(a.img_off[i], 0), a.nimg);
+    // The first sample's range of free potentials (each next one is fetched
+    // during the current sample's reduction; DERIVE, whose registers are
+    // fuller, reads it at the top of the sample).
+    int m = a.sample0 + blockIdx.x;
+    int fo0 = 0, fo1 = 0;
+    if (!MCMC && !DERIVE && m < a.n_samples) {
+        fo0 = a.free_off[m];
+        fo1 = a.free_off[m + 1];
     }
-    for (int m = a.sample0 + blockIdx.x; m < a.n_samples; m += gridDim.x) {
-        int k0, k1;
+    // What does not depend on the sample is staged once per wave (the first
+    // __syncthreads of the sample loop orders it before its use): then the
+    // reduction reads LDS only, with no memory latency in its loops.  Every
+    // load of the lane is issued, unconditionally (indices clamped into the
+    // arrays), before the first LDS write: one memory latency, shared with the
+    // range above, instead of one per element.
+    if (a.stage_sig) {
+        double stw[SRC_SIG_LOADS], stf[SRC_SIG_LOADS];
+        int sto[SRC_SIG_LOADS];
+        const int tmax = max(a.nimg - 1, 0);
+#pragma unroll
+        for (int i = 0; i < SRC_SIG_LOADS; ++i) {
+            const int t = lane + 64 * i;
+            sto[i] = a.img_off[min(t, a.nsys)];
+        }
+        if (a.nimg > 0) {
+#pragma unroll
+            for (int i = 0; i < SRC_SIG_LOADS; ++i) {
+                const int t = min(lane + 64 * i, tmax);
+                stw[i] = a.rec[3 * (size_t)pad + t];
+                stf[i] = a.rec[2 * (size_t)pad + t];
+            }
+#pragma unroll
+            for (int i = 0; i < SRC_SIG_LOADS; ++i) {
+                const int t = lane + 64 * i;
+                if (t < a.nimg) {
+                    sw[t] = stw[i];
+                    sf[t] = stf[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < SRC_SIG_LOADS; ++i) {
+            const int t = lane + 64 * i;
+            if (t <= a.nsys) soff[t] = min(max(sto[i], 0), a.nimg);
+        }
+    }
+    for (; m < a.n_samples; m += gridDim.x) {
+        int k0 = 0, k1 = 0;
         bool in = false;
         const int P = 7 * a.mc.nfree;
         const double *th = nullptr, *uw = nullptr;
@@ -254,21 +293,27 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
                 in = __ballot(out) == 0;
             }
         } else {
-            k0 = __builtin_amdgcn_readfirstlane(min(max(a.free_off[m], 0), nf));
-            k1 = __builtin_amdgcn_readfirstlane(min(max(a.free_off[m + 1], k0), nf));
+            if (DERIVE) {
+                fo0 = a.free_off[m];
+                fo1 = a.free_off[m + 1];
+            }
+            k0 = __builtin_amdgcn_readfirstlane(min(max(fo0, 0), nf));
+            k1 = __builtin_amdgcn_readfirstlane(min(max(fo1, k0), nf));
         }
         for (int g0 = 0; g0 < a.nimg; g0 += 64 * SRC_IPL) {
+            // (lanes past the last image load its data, unconditionally so
+            // that the loads need no wait between them, and store nothing)
             double x[SRC_IPL], y[SRC_IPL], acc[SRC_IPL][5];
 #pragma unroll
             for (int j = 0; j < SRC_IPL; ++j) {
-                const int t = g0 + j * 64 + lane;
-                const bool ok = t < a.nimg;
-                x[j] = ok ? a.x[t] : 0.0;
-                y[j] = ok ? a.y[t] : 0.0;
-                acc[j][0] = ok ? a.rec[t] : 0.0;
-                acc[j][1] = ok ? a.rec[pad + t] : 0.0;
+                const int t = min(g0 + j * 64 + lane, a.nimg - 1);
+                x[j] = a.x[t];
+                y[j] = a.y[t];
+                acc[j][0] = a.rec[t];
+                acc[j][1] = a.rec[pad + t];
                 acc[j][2] = acc[j][3] = acc[j][4] = 0.0;
             }
+
             for (int kc = k0; kc < k1; kc += a.chunk) {
                 const int cnt = min(a.chunk, k1 - kc);
                 __syncthreads();
@@ -370,6 +415,10 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
                 }
             }
         }
+        if (!MCMC && !DERIVE && a.persistent && m + (int)gridDim.x < a.n_samples) {
+            fo0 = a.free_off[m + gridDim.x];
+            fo1 = a.free_off[m + gridDim.x + 1];
+        }
         __syncthreads();
         double part = 0.0;
         for (int i = lane; i < a.nsys; i += 64) {
@@ -451,7 +500,8 @@ static size_t src_lds(int nimg, int nsys, int prec, int chunk, bool staged) {
            (staged ? ((size_t)nsys + 1) * sizeof(int) : 0);
 }
 static bool src_staged(int nimg, int nsys, int prec) {
-    return src_lds(nimg, nsys, prec, SRC_CHUNK_MAX, true) <= SRC_LDS_BUDGET;
+    return nimg <= 64 * SRC_SIG_LOADS && nsys + 1 <= 64 * SRC_SIG_LOADS &&
+           src_lds(nimg, nsys, prec, SRC_CHUNK_MAX, true) <= SRC_LDS_BUDGET;
 }
 static int src_chunk(int nimg, int prec) {
     const size_t per = NDER * sizeof(double) + (prec ? NDERF * sizeof(float) : 0);

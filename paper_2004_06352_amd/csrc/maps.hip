@@ -201,11 +201,11 @@ __device__ __forceinline__ void derived_of(double hxx, double hxy, double hyy, d
 }
 
 // Minimum waves per SIMD the register allocation must allow: the FP64 kernel
-// with one pixel per thread fits five without spilling (the compiler's own
-// choice leaves four); the other variants keep the compiler's choice.
+// with one pixel per thread fits six without spilling (80 registers); the
+// other variants keep the compiler's choice.
 template <int PREC, int PPT>
 constexpr int map_min_waves() {
-    return (PREC == 0 && PPT == 1) ? 5 : 1;
+    return (PREC == 0 && PPT == 1) ? 6 : 1;
 }
 
 template <int PREC, bool GRAD, bool HESS, bool STAGE, int PPT>
@@ -282,15 +282,36 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
             const int cnt = min(chunk, n - k0);
             __syncthreads();
             // wave wv copies the constants wv, wv + nw, ... of the chunk's
-            // potentials, its lanes consecutive potentials (coalesced reads)
-            for (int ci = wv; ci < NDER; ci += nw) {
-                const double *src = a.tab.d + (size_t)ci * st + k0;
-                for (int kk = lane; kk < cnt; kk += 64) lds[kk * NDER + ci] = src[kk];
-            }
-            if (PREC != 0) {
-                for (int ci = wv; ci < NDERF; ci += nw) {
-                    const float *src = a.tab.f + (size_t)ci * st + k0;
-                    for (int kk = lane; kk < cnt; kk += 64) ldsf[kk * NDERF + ci] = src[kk];
+            // potentials, its lanes consecutive potentials (coalesced reads),
+            // four constants' loads in flight before their LDS writes
+            for (int kk = lane; kk < cnt; kk += 64) {
+                for (int c0 = wv; c0 < NDER; c0 += 4 * nw) {
+                    double v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int ci = c0 + u * nw;
+                        v[u] = ci < NDER ? a.tab.d[(size_t)ci * st + k0 + kk] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int ci = c0 + u * nw;
+                        if (ci < NDER) lds[kk * NDER + ci] = v[u];
+                    }
+                }
+                if (PREC != 0) {
+                    for (int c0 = wv; c0 < NDERF; c0 += 4 * nw) {
+                        float v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int ci = c0 + u * nw;
+                            v[u] = ci < NDERF ? a.tab.f[(size_t)ci * st + k0 + kk] : 0.f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int ci = c0 + u * nw;
+                            if (ci < NDERF) ldsf[kk * NDERF + ci] = v[u];
+                        }
+                    }
                 }
             }
             __syncthreads();
