@@ -575,7 +575,7 @@ def main():
     exe = measured_executed_flop()
     if exe is not None:
         # the executed-instruction view of the same launches (counters taken on
-        # 64x4 blocks with two pixels per thread, the autotuner's pick here):
+        # 64x4 blocks with one pixel per thread, the autotuner's pick here):
         # FP64 vector work actually issued
         rec["roofline"]["executed_flop_per_launch"] = exe
         rec["roofline"]["executed_frac"] = exe / ev / 1e12 / PEAK_FP64_TFLOPS
