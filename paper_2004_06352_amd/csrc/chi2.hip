@@ -175,9 +175,68 @@ constexpr int SRC_IPL = 4;
 // stage them.
 constexpr int SRC_CHUNK_MAX = 8;
 constexpr int SRC_STAGE_LOADS = (SRC_CHUNK_MAX * NDER + 63) / 64;
-// Staged per-image constants and image offsets: at most this many per lane
-// (the staging is used only when nimg and nsys + 1 fit).
+// Staged per-image constants and image offsets: at most this many per thread
+// of a one-wave block (the staging is used only when nimg and nsys + 1 fit).
 constexpr int SRC_SIG_LOADS = 4;
+// Waves (samples at a time) per block of the per-sample kernel, at most.
+constexpr int SRC_MAX_WPB = 4;
+// LDS of the block-shared region (six per-image rows and the image offsets,
+// in doubles) and of one wave's region (unlensed x, y and a chunk of staged
+// potentials).
+__host__ __device__ inline size_t src_shared_doubles(int nimg, int nsys) {
+    return 6 * (size_t)nimg + ((size_t)nsys + 2) / 2;
+}
+__host__ __device__ inline size_t src_wave_doubles(int nimg, int chunk, int prec) {
+    return 2 * (size_t)nimg + (size_t)chunk * NDER + (prec ? ((size_t)chunk * NDERF + 1) / 2 : 0);
+}
+// The block-shared region: thread tid stages entries tid, tid + nthr, ...
+// (N of them cover the at most 64 SRC_SIG_LOADS entries staging admits), all
+// its loads issued before its LDS writes.
+template <int N>
+__device__ __forceinline__ void src_stage_images(const Chi2SrcLaunch &a, double *shw, int tid,
+                                                 int nthr) {
+    const size_t pad = a.nimg_pad;
+    int *offw = reinterpret_cast<int *>(shw + 6 * (size_t)a.nimg);
+    const int tmax = max(a.nimg - 1, 0);
+    int sto[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) sto[i] = a.img_off[min(tid + nthr * i, a.nsys)];
+    if (a.nimg > 0) {
+        double v[N][6];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int t = min(tid + nthr * i, tmax);
+            v[i][0] = a.x[t];
+            v[i][1] = a.y[t];
+            v[i][2] = a.rec[t];
+            v[i][3] = a.rec[pad + t];
+            v[i][4] = a.rec[3 * pad + t];
+            v[i][5] = a.rec[2 * pad + t];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int t = tid + nthr * i;
+            if (t < a.nimg) {
+#pragma unroll
+                for (int r = 0; r < 6; ++r) shw[(size_t)r * a.nimg + t] = v[i][r];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int t = tid + nthr * i;
+        if (t <= a.nsys) offw[t] = min(max(sto[i], 0), a.nimg);
+    }
+}
+
+// Orders one wave's LDS writes before its later reads by other lanes (the
+// per-wave regions need no block barrier, and the waves of a block may run
+// different numbers of samples and chunks).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // The sampler's walker: physical parameters of its potential k (the proposal
 // theta + step (2u - 1) when `in`, else the current state; the same rounded
@@ -213,68 +272,54 @@ __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *t
 // table (a.derive_free), a variant of its own so that the usual batch keeps
 // its register allocation.
 template <int PREC, bool MCMC = false, bool DERIVE = false>
-__global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4)) chi2_src_kernel(Chi2SrcLaunch a) {
-    // LDS: [2][nimg] unlensed x, y; when the catalogue is small enough
-    // (stage_sig) each image's 1/sigma^2 and Dls/Ds [2][nimg]; the staged
-    // potentials (FP64, then FP32); then, with stage_sig, the nsys + 1 image
-    // offsets
+__global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4)) chi2_src_kernel(Chi2SrcLaunch a) {
+    // A block holds blockDim.x / 64 waves, each on its own samples.  LDS: when
+    // the catalogue is small enough (stage_sig), a region the block's waves
+    // share, staged once: each image's x, y, fixed deflection x, y, 1/sigma^2
+    // and Dls/Ds [6][nimg] and the nsys + 1 image offsets; then per wave
+    // [2][nimg] unlensed x, y and the staged potentials (FP64, then FP32).
     extern __shared__ double sh[];
-    const int narr = a.stage_sig ? 4 : 2;
-    double *sx = sh, *sy = sh + a.nimg;
-    double *sw = sh + 2 * (size_t)a.nimg, *sf = sh + 3 * (size_t)a.nimg;
-    double *pd = sh + narr * (size_t)a.nimg;
+    // (the wave index is uniform across the wave: in a scalar register, the
+    // per-wave LDS region's base is too)
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const size_t shared_d = a.stage_sig ? src_shared_doubles(a.nimg, a.nsys) : 0;
+    const double *ix = sh, *iy = sh + a.nimg, *ir0 = sh + 2 * (size_t)a.nimg,
+                 *ir1 = sh + 3 * (size_t)a.nimg;
+    const double *sw = sh + 4 * (size_t)a.nimg, *sf = sh + 5 * (size_t)a.nimg;
+    const int *soff = reinterpret_cast<const int *>(sh + 6 * (size_t)a.nimg);
+    double *own = sh + shared_d + (size_t)wv * src_wave_doubles(a.nimg, a.chunk, PREC);
+    double *sx = own, *sy = own + a.nimg;
+    double *pd = own + 2 * (size_t)a.nimg;
     float *pf = reinterpret_cast<float *>(pd + (size_t)a.chunk * NDER);
-    // (the FP32 block of the staged potentials exists only for PREC != 0)
-    int *soff = reinterpret_cast<int *>(pf + (PREC != 0 ? (size_t)a.chunk * NDERF : 0));
-    const int lane = threadIdx.x;
     const int pad = a.nimg_pad, st = a.freet.stride, nf = a.freet.n;
     // The first sample's range of free potentials (each next one is fetched
     // during the current sample's reduction; DERIVE, whose registers are
     // fuller, reads it at the top of the sample).
-    int m = a.sample0 + blockIdx.x;
+    const int mstride = gridDim.x * nw;
+    int m = a.sample0 + blockIdx.x * nw + wv;
     int fo0 = 0, fo1 = 0;
     if (!MCMC && !DERIVE && m < a.n_samples) {
         fo0 = a.free_off[m];
         fo1 = a.free_off[m + 1];
     }
-    // What does not depend on the sample is staged once per wave (the first
-    // __syncthreads of the sample loop orders it before its use): then the
-    // reduction reads LDS only, with no memory latency in its loops.  Every
-    // load of the lane is issued, unconditionally (indices clamped into the
-    // arrays), before the first LDS write: one memory latency, shared with the
-    // range above, instead of one per element.
+    // What does not depend on the sample is staged once per block, by all its
+    // threads, before one block barrier: then the waves read it from LDS, not
+    // each from L2 (the same few cache lines read by every wave at once had
+    // their L2 channels serialise the requests), and the reduction reads LDS
+    // only.  Every load of a thread is issued, unconditionally (indices
+    // clamped into the arrays), before its first LDS write.
     if (a.stage_sig) {
-        double stw[SRC_SIG_LOADS], stf[SRC_SIG_LOADS];
-        int sto[SRC_SIG_LOADS];
-        const int tmax = max(a.nimg - 1, 0);
-#pragma unroll
-        for (int i = 0; i < SRC_SIG_LOADS; ++i) {
-            const int t = lane + 64 * i;
-            sto[i] = a.img_off[min(t, a.nsys)];
-        }
-        if (a.nimg > 0) {
-#pragma unroll
-            for (int i = 0; i < SRC_SIG_LOADS; ++i) {
-                const int t = min(lane + 64 * i, tmax);
-                stw[i] = a.rec[3 * (size_t)pad + t];
-                stf[i] = a.rec[2 * (size_t)pad + t];
-            }
-#pragma unroll
-            for (int i = 0; i < SRC_SIG_LOADS; ++i) {
-                const int t = lane + 64 * i;
-                if (t < a.nimg) {
-                    sw[t] = stw[i];
-                    sf[t] = stf[i];
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < SRC_SIG_LOADS; ++i) {
-            const int t = lane + 64 * i;
-            if (t <= a.nsys) soff[t] = min(max(sto[i], 0), a.nimg);
-        }
+        if (nthr >= 256)
+            src_stage_images<1>(a, sh, tid, nthr);
+        else if (nthr >= 128)
+            src_stage_images<2>(a, sh, tid, nthr);
+        else
+            src_stage_images<4>(a, sh, tid, nthr);
     }
-    for (; m < a.n_samples; m += gridDim.x) {
+    __syncthreads();  // (the only block barrier: below, each wave on its own)
+    for (; m < a.n_samples; m += mstride) {
         int k0 = 0, k1 = 0;
         bool in = false;
         const int P = 7 * a.mc.nfree;
@@ -307,16 +352,23 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
 #pragma unroll
             for (int j = 0; j < SRC_IPL; ++j) {
                 const int t = min(g0 + j * 64 + lane, a.nimg - 1);
-                x[j] = a.x[t];
-                y[j] = a.y[t];
-                acc[j][0] = a.rec[t];
-                acc[j][1] = a.rec[pad + t];
+                if (a.stage_sig) {
+                    x[j] = ix[t];
+                    y[j] = iy[t];
+                    acc[j][0] = ir0[t];
+                    acc[j][1] = ir1[t];
+                } else {
+                    x[j] = a.x[t];
+                    y[j] = a.y[t];
+                    acc[j][0] = a.rec[t];
+                    acc[j][1] = a.rec[pad + t];
+                }
                 acc[j][2] = acc[j][3] = acc[j][4] = 0.0;
             }
 
             for (int kc = k0; kc < k1; kc += a.chunk) {
                 const int cnt = min(a.chunk, k1 - kc);
-                __syncthreads();
+                wave_lds_sync();
                 if (MCMC) {
                     if (lane < cnt) mcmc_derive(a.mc, th, uw, in, kc + lane, pd + lane * NDER);
                 } else if (DERIVE) {
@@ -357,7 +409,7 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
                         pf[kk * NDERF + ci] = a.freet.f[(size_t)ci * st + kc + kk];
                     }
                 }
-                __syncthreads();
+                wave_lds_sync();
                 for (int kk = 0; kk < cnt; ++kk) {
                     const ConstD cd{pd + kk * NDER, 1};
                     if (PREC == 0) {
@@ -415,11 +467,11 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
                 }
             }
         }
-        if (!MCMC && !DERIVE && a.persistent && m + (int)gridDim.x < a.n_samples) {
-            fo0 = a.free_off[m + gridDim.x];
-            fo1 = a.free_off[m + gridDim.x + 1];
+        if (!MCMC && !DERIVE && a.persistent && m + mstride < a.n_samples) {
+            fo0 = a.free_off[m + mstride];
+            fo1 = a.free_off[m + mstride + 1];
         }
-        __syncthreads();
+        wave_lds_sync();
         double part = 0.0;
         for (int i = lane; i < a.nsys; i += 64) {
             int o0, o1;
@@ -482,26 +534,24 @@ __global__ void __launch_bounds__(64, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4))
         } else if (lane == 0 && a.chi2) {
             a.chi2[m] = part;
         }
-        __syncthreads();  // sx, sy are rewritten by the next sample
+        wave_lds_sync();  // sx, sy are rewritten by the next sample
         if (!a.persistent) break;
     }
 }
 
-// LDS: the unlensed positions plus a chunk of staged potentials; the chunk
-// shrinks for large catalogues so that a block stays within 64 KiB.
-// LDS of the per-sample kernel: per-image arrays (4 with the sample-independent
-// constants staged, else 2), a chunk of staged potentials, and with the
-// staging the image offsets.  Staged when that fits a budget that keeps 16
-// one-wave blocks on a CU (160 KiB of LDS) with a full chunk.
-constexpr size_t SRC_LDS_BUDGET = 10240;
-static size_t src_lds(int nimg, int nsys, int prec, int chunk, bool staged) {
-    const size_t per = NDER * sizeof(double) + (prec ? NDERF * sizeof(float) : 0);
-    return (staged ? 4 : 2) * (size_t)nimg * sizeof(double) + (size_t)chunk * per +
-           (staged ? ((size_t)nsys + 1) * sizeof(int) : 0);
+// LDS of a block of nw waves of the per-sample kernel: with the staging, the
+// block-shared region, then per wave the unlensed positions and a chunk of
+// staged potentials.  A batch stages when that fits a budget that keeps 16
+// waves on a CU (160 KiB of LDS) with a full chunk; the per-sample path (one
+// block) when it fits 64 KiB.
+constexpr size_t SRC_LDS_BUDGET = 10240;  // per wave
+static size_t src_lds(int nimg, int nsys, int prec, int chunk, bool staged, int nw) {
+    return sizeof(double) * ((staged ? src_shared_doubles(nimg, nsys) : 0) +
+                             (size_t)nw * src_wave_doubles(nimg, chunk, prec));
 }
-static bool src_staged(int nimg, int nsys, int prec) {
+static bool src_staged(int nimg, int nsys, int prec, int nw, size_t budget) {
     return nimg <= 64 * SRC_SIG_LOADS && nsys + 1 <= 64 * SRC_SIG_LOADS &&
-           src_lds(nimg, nsys, prec, SRC_CHUNK_MAX, true) <= SRC_LDS_BUDGET;
+           src_lds(nimg, nsys, prec, SRC_CHUNK_MAX, true, nw) <= budget;
 }
 static int src_chunk(int nimg, int prec) {
     const size_t per = NDER * sizeof(double) + (prec ? NDERF * sizeof(float) : 0);
@@ -538,14 +588,33 @@ hipError_t launch_chi2_prep(const Chi2SrcLaunch &c0, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Waves per block, staging and chunk of a launch of the per-sample kernel
+// (c.grid_blocks waves): a batch takes blocks of SRC_MAX_WPB waves (else 2,
+// else 1) that share the staged catalogue; the per-sample path one wave.
+static int src_shape(Chi2SrcLaunch &c, int prec) {
+    int nw = 1;
+    bool staged = false;
+    if (c.persistent && c.grid_blocks > 1) {
+        for (int w = SRC_MAX_WPB; w >= 1 && !staged; w /= 2)
+            if (src_staged(c.nimg, c.nsys, prec, w, SRC_LDS_BUDGET * w)) {
+                nw = w;
+                staged = true;
+            }
+    } else {
+        staged = src_staged(c.nimg, c.nsys, prec, 1, 65536);
+    }
+    c.stage_sig = staged ? 1 : 0;
+    c.chunk = staged ? SRC_CHUNK_MAX : src_chunk(c.nimg, prec);
+    return nw;
+}
+
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c0, hipStream_t st) {
     Chi2SrcLaunch c = c0;
     c.S = make_series();
-    c.stage_sig = src_staged(c.nimg, c.nsys, c.prec);
-    c.chunk = c.stage_sig ? SRC_CHUNK_MAX : src_chunk(c.nimg, c.prec);
-    const size_t shmem = src_lds(c.nimg, c.nsys, c.prec, c.chunk, c.stage_sig);
+    const int nw = src_shape(c, c.prec);
+    const size_t shmem = src_lds(c.nimg, c.nsys, c.prec, c.chunk, c.stage_sig, nw);
     if (shmem > 65536) return hipErrorInvalidValue;
-    const dim3 grid(c.grid_blocks), block(64);
+    const dim3 grid((c.grid_blocks + nw - 1) / nw), block(64 * nw);
     if (c.prec == 0 && c.derive_free)
         hipLaunchKernelGGL((chi2_src_kernel<0, false, true>), grid, block, shmem, st, c);
     else if (c.prec == 0)
@@ -563,11 +632,11 @@ hipError_t launch_mcmc_chi2(const Chi2SrcLaunch &c0, hipStream_t st) {
     if (c.n_samples <= 0) return hipSuccess;
     c.S = make_series();
     c.prec = 0;
-    c.stage_sig = src_staged(c.nimg, c.nsys, 0);
-    c.chunk = c.stage_sig ? SRC_CHUNK_MAX : src_chunk(c.nimg, 0);
-    const size_t shmem = src_lds(c.nimg, c.nsys, 0, c.chunk, c.stage_sig);
+    const int nw = src_shape(c, 0);
+    const size_t shmem = src_lds(c.nimg, c.nsys, 0, c.chunk, c.stage_sig, nw);
     if (shmem > 65536) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((chi2_src_kernel<0, true>), dim3(c.grid_blocks), dim3(64), shmem, st, c);
+    hipLaunchKernelGGL((chi2_src_kernel<0, true>), dim3((c.grid_blocks + nw - 1) / nw),
+                       dim3(64 * nw), shmem, st, c);
     return hipGetLastError();
 }
 
