@@ -699,28 +699,35 @@ __global__ void __launch_bounds__(256, 6) alpha_grid_kernel(AlphaGridLaunch a) {
         kb = ke;
         if (s < ns) ke = min(max(off[s + 1], kb), nf);
     };
+    // staging: wave w copies the constants w, w + 4, ... of the chunk's
+    // potentials, its lanes consecutive potentials (AG_CHUNK <= 64)
+    static_assert(AG_CHUNK <= 64, "a chunk's potentials fit one wave's lanes");
+    const int lane = tid & 63, wv = tid >> 6;
     for (int kc = K0; kc < K1; kc += AG_CHUNK) {
         const int cnt = min(AG_CHUNK, K1 - kc);
         __syncthreads();
-        for (int e = tid; e < cnt * NDER; e += 256) {
-            const int ci = e / cnt, kk = e - ci * cnt;
-            pd[kk * NDER + ci] = a.freet.d[(size_t)ci * st + kc + kk];
-        }
-        if (PREC != 0) {
-            for (int e = tid; e < cnt * NDERF; e += 256) {
-                const int ci = e / cnt, kk = e - ci * cnt;
-                pf[kk * NDERF + ci] = a.freet.f[(size_t)ci * st + kc + kk];
-            }
+        if (lane < cnt) {
+            for (int ci = wv; ci < NDER; ci += 4)
+                pd[lane * NDER + ci] = a.freet.d[(size_t)ci * st + kc + lane];
+            if (PREC != 0)
+                for (int ci = wv; ci < NDERF; ci += 4)
+                    pf[lane * NDERF + ci] = a.freet.f[(size_t)ci * st + kc + lane];
         }
         __syncthreads();
+        // the chunk's kinds in scalar registers, and its entries addressed
+        // from one vector register
+        const KindMasks km = kind_masks(lane < cnt ? kind_bits(pd[lane * NDER + D_KIND]) : 0);
+        const double *row = lds_entry(pd, 0);
         for (int kk = 0; kk < cnt; ++kk) {
             while (s < ns && kc + kk >= ke) finish();
             if (PREC == 0) {
-                eval_pot_f64<true, false>(ConstD{pd + kk * NDER, 1}, x, y, acc, S);
+                eval_pot_f64_kind<true, false>(ConstD{row + kk * NDER, 1}, km.kind(kk), x, y, acc,
+                                               S);
             } else {
                 float o[5];
-                eval_pot_f32<true, false>(ConstD{pd + kk * NDER, 1}, ConstF{pf + kk * NDERF, 1},
-                                          x, y, o, a.S);
+                eval_pot_f32_kind<true, false>(ConstD{row + kk * NDER, 1},
+                                               ConstF{pf + kk * NDERF, 1}, km.kind(kk), x, y, o,
+                                               a.S);
                 acc[0] += (double)o[0];
                 acc[1] += (double)o[1];
             }

@@ -65,6 +65,37 @@ __device__ __forceinline__ double vgpr_f64(double x) {
     return r;
 }
 
+// &base[off] for a wave-uniform off, the address held in a vector register:
+// entries addressed from it are read with one vector add for their address
+// (left to itself the compiler keeps a uniform address in a scalar register
+// and copies it to a vector register before each group of reads).
+__device__ __forceinline__ const double *lds_entry(const double *base, int off) {
+    int v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(off * (int)sizeof(double)));
+    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + v);
+}
+
+// The kinds of up to 64 staged potentials as one bit mask per kind bit (lane
+// l of the wave reads entry l; the caller's whole wave is active), and the
+// kind of entry i from the masks with scalar operations: a loop over staged
+// potentials then takes each one's kind without a copy from a vector
+// register.
+struct KindMasks {
+    unsigned long long ell, cut, sing, e32;
+    __device__ __forceinline__ int kind(int i) const {
+        return (int)((ell >> i) & 1) * K_ELL | (int)((cut >> i) & 1) * K_CUT |
+               (int)((sing >> i) & 1) * K_SING | (int)((e32 >> i) & 1) * K_ELL32;
+    }
+};
+__device__ __forceinline__ KindMasks kind_masks(int kl) {
+    KindMasks m;
+    m.ell = __builtin_amdgcn_ballot_w64(kl & K_ELL);
+    m.cut = __builtin_amdgcn_ballot_w64(kl & K_CUT);
+    m.sing = __builtin_amdgcn_ballot_w64(kl & K_SING);
+    m.e32 = __builtin_amdgcn_ballot_w64(kl & K_ELL32);
+    return m;
+}
+
 // True on every active lane when both predicates hold on all of them (scalar
 // operations on the compare masks and the execution mask).
 __device__ __forceinline__ bool wave_all(bool p, bool q) {
@@ -401,13 +432,20 @@ __device__ __forceinline__ void eval_pot_f64_rel(const ConstD c, int kind, doubl
     eval_pot_f64_impl<GRAD, HESS, SHORT>(c, kind, dx, dy, dyc, dys, acc, S);
 }
 
+// One point, the kind given (as on the uniform paths, read once per potential).
+template <bool GRAD, bool HESS, bool SHORT = false>
+__device__ __forceinline__ void eval_pot_f64_kind(const ConstD c, int kind, double x, double y,
+                                                  double acc[5], const Series &S) {
+    const double dy = y - c[D_Y0];
+    eval_pot_f64_rel<GRAD, HESS, SHORT>(c, kind, x - c[D_X0], dy, dy * c[D_C], dy * c[D_S], acc,
+                                        S);
+}
+
 template <bool GRAD, bool HESS, bool UNIF = true, bool SHORT = false>
 __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y, double acc[5],
                                              const Series &S) {
     const int kind = UNIF ? uniform_kind(c[D_KIND]) : kind_bits(c[D_KIND]);
-    const double dy = y - c[D_Y0];
-    eval_pot_f64_rel<GRAD, HESS, SHORT>(c, kind, x - c[D_X0], dy, dy * c[D_C], dy * c[D_S], acc,
-                                        S);
+    eval_pot_f64_kind<GRAD, HESS, SHORT>(c, kind, x, y, acc, S);
 }
 
 // Deflection of one two-core elliptical potential (kind K_CUT | K_ELL, rcore >

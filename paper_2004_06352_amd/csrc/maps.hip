@@ -161,16 +161,6 @@ __device__ __forceinline__ double uniform_f64(double v) {
     return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
                             __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
-// &base[off] for a wave-uniform off, the address held in a vector register:
-// entries addressed from it are read with one vector add for their address
-// (left to itself the compiler keeps a uniform address in a scalar register
-// and copies it to a vector register before each group of reads).
-__device__ __forceinline__ const double *lds_entry(const double *base, int off) {
-    int v;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(off * (int)sizeof(double)));
-    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + v);
-}
-
 struct MapArgs {
     Derived tab;
     GridArgs g;
@@ -320,20 +310,12 @@ __global__ void __launch_bounds__(256, (map_min_waves<PREC, PPT>())) map_kernel(
                 // per kind bit (lane l reads potential kb + l), so that the
                 // loop takes each potential's kind in scalar registers
                 const int m = min(64, cnt - kb);
-                const int kl = lane < m ? kind_bits(lds[(kb + lane) * NDER + D_KIND]) : 0;
-                const unsigned long long m_ell = __builtin_amdgcn_ballot_w64(kl & K_ELL);
-                const unsigned long long m_cut = __builtin_amdgcn_ballot_w64(kl & K_CUT);
-                const unsigned long long m_sing = __builtin_amdgcn_ballot_w64(kl & K_SING);
-                const unsigned long long m_e32 = __builtin_amdgcn_ballot_w64(kl & K_ELL32);
+                const KindMasks km =
+                    kind_masks(lane < m ? kind_bits(lds[(kb + lane) * NDER + D_KIND]) : 0);
                 const double *row = lds_entry(lds, kb * NDER);
-                for (int i = 0; i < m; ++i) {
-                    const int kind = (int)((m_ell >> i) & 1) * K_ELL |
-                                     (int)((m_cut >> i) & 1) * K_CUT |
-                                     (int)((m_sing >> i) & 1) * K_SING |
-                                     (int)((m_e32 >> i) & 1) * K_ELL32;
-                    body(ConstD{row + i * NDER, 1},
-                         ConstF{ldsf + (kb + i) * NDERF, 1}, kind);
-                }
+                for (int i = 0; i < m; ++i)
+                    body(ConstD{row + i * NDER, 1}, ConstF{ldsf + (kb + i) * NDERF, 1},
+                         km.kind(i));
             }
         }
     } else {
