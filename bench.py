@@ -5,8 +5,9 @@ fused map kernel on the 2048^2-grid, 502-potential workload (FP64, five output
 planes), inputs resident in HBM, each step one lens_hessian_map call (the
 parameter prologue and the map kernel).  Secondary metrics in the same JSON
 line: FP32-evaluation maps, batched source-plane chi^2 samples/s (4096
-samples), the per-sample path on the same batch, the captured (HIP graph)
-batches, the sampler, image-plane chi^2 samples/s (eager and captured), the
+samples), the per-sample path on the same batch, the recorded plans
+(replayed launches), the sampler, image-plane chi^2 samples/s (eager and
+captured in a HIP graph), the
 serving streams at 0.7x and 1.5x the plain path's capacity, and, from the
 CPU-baseline leg (the oracle timed on the host with all threads and with
 one), every map and chi^2 precision's error against the oracle on sampled
@@ -358,7 +359,7 @@ def bench_serving(map_rate, chi2_rate, n_requests):
 
 
 def chi2_legs(args, ctx, secondary, torch, B, inputs, keep):
-    """Source-plane chi^2 (batched, per-sample, graph plans), the sampler and
+    """Source-plane chi^2 (batched, per-sample, recorded plans), the sampler and
     the image-plane chi^2 (eager and captured); results into `secondary`, the
     GPU outputs the CPU-baseline leg compares with the oracle into `keep`."""
     c3 = inputs.config3()
@@ -376,7 +377,7 @@ def chi2_legs(args, ctx, secondary, torch, B, inputs, keep):
         w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=path, ctx=ctx),
                            n, 1, torch, per_step=False)
         secondary[f"chi2_source_{name}_samples_per_s"] = S * n / w
-    for name, resident in (("graph", False), ("graph_fixed_resident", True)):
+    for name, resident in (("plan", False), ("plan_fixed_resident", True)):
         plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, resident=resident)
         w, e = timed_steps(plan.launch, 50, 2, torch, per_step=False)
         secondary[f"chi2_source_{name}_samples_per_s"] = S * 50 / w

@@ -339,9 +339,12 @@ lens_status_t lens_find_images(lens_ctx_t *ctx, const double *ax, const double *
                                void *stream);
 
 /* ---- captured batches (batching form) ------------------------------------ */
-/* Record the whole of one lens_chi2_batch call (batched path) into a HIP
- * graph bound to these exact buffers and shapes; replaying it re-evaluates
- * the batch with whatever the buffers then hold.  lens_chi2_plan_create and
+/* Record the whole of one lens_chi2_batch call (batched path), bound to these
+ * exact buffers and shapes; replaying it re-evaluates the batch with whatever
+ * the buffers then hold.  An image-mode plan replays a HIP graph of its
+ * sequence; a source-mode plan, one or two kernels, replays their recorded
+ * launch descriptions as plain launches (no argument checks, no scratch
+ * carving, no graph launch).  lens_chi2_plan_create and
  * _create_ex record source-mode calls (other modes: LENS_EUNSUPPORTED);
  * lens_chi2_plan_create2 records either mode, with the image mode's optional
  * outputs.  The plan owns its scratch (device memory allocated here, freed

@@ -67,9 +67,13 @@ struct lens_mcmc {
 struct lens_chi2_plan {
     lens_ctx_t *ctx = nullptr;
     void *mem = nullptr;  // the plan's own scratch (derived tables, per-image constants)
+    // image mode: the captured sequence; source mode: the recorded launches
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int *status = nullptr;  // image mode: the search's status word, in mem
+    bool direct = false;
+    bool has_prep = false, has_src = false;
+    lens::Chi2SrcLaunch prep, src;
 };
 
 // Device memory of the allocation-free map call: the derived constants of at
@@ -407,10 +411,23 @@ enum SrcParts {
 };
 
 // Prologues, fixed deflection at the constraints, then the per-sample kernel.
+// The launches a source-mode plan replays: the sequence's prep and
+// per-sample kernels, described once (arguments, shapes, buffers) and issued
+// as plain launches on each replay.
+struct SrcRecord {
+    bool has_prep = false, has_src = false;
+    Chi2SrcLaunch prep, src;
+};
+
+// rec: record the prep and per-sample launches there instead of issuing them
+// (batched path, no table prologue of its own, unchecked).
 lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const lens_catalog_t *c,
                            lens_precision_t prec, lens_chi2_path_t path, const SrcPlan &p,
                            double *chi2, bool sources, hipStream_t st, bool with_check,
-                           SrcParts parts = SRC_ALL) {
+                           SrcParts parts = SRC_ALL, SrcRecord *rec = nullptr) {
+    if (rec && (with_check || path != LENS_CHI2_PATH_BATCHED || parts == SRC_ALL_TABLES ||
+                parts == SRC_FREE_ONLY))
+        return fail(LENS_EUNSUPPORTED, "this source-plane sequence cannot be recorded");
     char *base = p.base ? p.base : sc(ctx, 0);
     const Derived DF = derived_in(base, p.o_fix, b->fixed.n);
     const Derived DV = derived_in(base, p.o_free, b->free.n);
@@ -453,8 +470,14 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
         L.free_amp = soa(&b->free);
         L.status = ctx->small;
     }
-    if (parts == SRC_ALL || parts == SRC_FIXED_ONLY || parts == SRC_ALL_TABLES)
-        HIP_TRY(launch_chi2_prep(L, st));
+    if (parts == SRC_ALL || parts == SRC_FIXED_ONLY || parts == SRC_ALL_TABLES) {
+        if (rec) {
+            rec->prep = L;
+            rec->has_prep = true;
+        } else {
+            HIP_TRY(launch_chi2_prep(L, st));
+        }
+    }
     if (with_check) TRY(status_check(ctx, st));
     if (parts == SRC_FIXED_ONLY || b->n_samples == 0) return LENS_OK;
     if (parts == SRC_SAMPLES_DERIVE) {
@@ -465,7 +488,12 @@ lens_status_t src_sequence(lens_ctx_t *ctx, const lens_model_batch_t *b, const l
     if (batched) {
         L.persistent = 1;
         L.grid_blocks = batched_blocks(ctx, b->n_samples);
-        HIP_TRY(launch_chi2_src(L, st));
+        if (rec) {
+            rec->src = L;
+            rec->has_src = true;
+        } else {
+            HIP_TRY(launch_chi2_src(L, st));
+        }
     } else {
         L.persistent = 0;
         L.grid_blocks = 1;
@@ -779,6 +807,23 @@ lens_status_t plan_create(lens_ctx_t *ctx, const lens_model_batch_t *b, const le
     if (s != LENS_OK) return bail(s);
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(fail(LENS_EDEVICE, "%s", hipGetErrorString(e)));
+    if (!img) {
+        // one or two kernels: replayed as plain launches of their recorded
+        // descriptions (a graph launch costs more here than the launches it
+        // would save)
+        SrcRecord r;
+        s = src_sequence(ctx, b, c, o->prec, LENS_CHI2_PATH_BATCHED, sp, chi2, false, st, false,
+                         resident ? SRC_SAMPLES_DERIVE : SRC_ALL, &r);
+        if (s != LENS_OK) return bail(s);
+        p->direct = true;
+        p->has_prep = r.has_prep;
+        p->has_src = r.has_src;
+        p->prep = r.prep;
+        p->src = r.src;
+        p->status = nullptr;
+        *out = p;
+        return LENS_OK;
+    }
     e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
         return bail(fail(LENS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e)));
@@ -1310,7 +1355,13 @@ lens_status_t lens_mcmc_destroy(lens_mcmc_t *m) {
 lens_status_t lens_chi2_plan_launch(lens_chi2_plan_t *p, void *stream) {
     if (!p) return fail(LENS_EINVAL, "plan is NULL");
     DeviceGuard dg(p->ctx->device);
-    HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    const hipStream_t st = (hipStream_t)stream;
+    if (p->direct) {
+        if (p->has_prep) HIP_TRY(launch_chi2_prep(p->prep, st));
+        if (p->has_src) HIP_TRY(launch_chi2_src(p->src, st));
+        return LENS_OK;
+    }
+    HIP_TRY(hipGraphLaunch(p->exec, st));
     return LENS_OK;
 }
 

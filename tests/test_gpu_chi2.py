@@ -1,6 +1,6 @@
 """GPU parity of the source-plane chi^2 batch against the FP64 oracle, through
 the C ABI: batched (persistent, device work queue), per-sample launches and a
-captured HIP graph, on even and uneven sample sizes."""
+recorded plan, on even and uneven sample sizes."""
 import numpy as np
 import pytest
 
@@ -111,7 +111,7 @@ def test_samples_without_free_potentials_and_empty_batch(B, ctx, oracle):
     assert r["chi2"].numel() == 0
 
 
-def test_captured_graph_replays_equal_eager(B, ctx):
+def test_plan_replays_equal_eager(B, ctx):
     from paper_2004_06352_amd import inputs
     c = inputs.config3(n_samples=256, uneven=True)
     fixed, free, off = device_model(B, ctx, c)
