@@ -245,11 +245,17 @@ __device__ __forceinline__ void wave_lds_sync() {
 // table conversion) -> derived constants at dst (stride 1, FP64 only).
 __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *th,
                                             const double *uw, bool in, int k, double *dst) {
-    double q[7];
+    // (all 21 loads issued before the first use: one memory latency, not seven)
+    double t[7], s[7], u[7], q[7];
+#pragma unroll
     for (int j = 0; j < 7; ++j) {
         const int i = 7 * k + j;
-        q[j] = in ? th[i] + mc.step[i] * (2.0 * uw[i] - 1.0) : th[i];
+        t[j] = th[i];
+        s[j] = mc.step[i];
+        u[j] = uw[i];
     }
+#pragma unroll
+    for (int j = 0; j < 7; ++j) q[j] = in ? t[j] + s[j] * (2.0 * u[j] - 1.0) : t[j];
     const double c_kms = 299792.458;
     const double arcsec_per_rad = 648000.0 / M_PI;
     const double v = q[2] / c_kms;
@@ -265,9 +271,11 @@ __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *t
 // box and (chi2' <= chi2 or -2 ln u_last > chi2' - chi2), copying the
 // proposal into the walker's parameters.
 // At least four waves per SIMD, so that a 4096-sample batch is one round of
-// waves; the sampler form, which also derives its walker's potentials,
-// keeps three (its registers would spill at four: measured 44.6 -> 39.9 us
-// per 4096-walker step).
+// waves.  The sampler form takes one walker per wave and has no sample loop
+// (with one, the constants of the walker's logarithm and prologue were held
+// in registers across it: 158 VGPRs, 134 without); it keeps three waves (at
+// four a few registers spill outside the potential loop, and a 4096-walker
+// step measured the same, 36.0-36.6 against 36.2-36.4 us).
 // DERIVE: the sample's free constants formed by the wave from the amplitude
 // table (a.derive_free), a variant of its own so that the usual batch keeps
 // its register allocation.
@@ -535,7 +543,7 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
             a.chi2[m] = part;
         }
         wave_lds_sync();  // sx, sy are rewritten by the next sample
-        if (!a.persistent) break;
+        if (MCMC || !a.persistent) break;
     }
 }
 
@@ -632,6 +640,9 @@ hipError_t launch_mcmc_chi2(const Chi2SrcLaunch &c0, hipStream_t st) {
     if (c.n_samples <= 0) return hipSuccess;
     c.S = make_series();
     c.prec = 0;
+    // one walker per wave (a kernel without a sample loop keeps the constants
+    // of the walker's own arithmetic out of the registers of the potential loop)
+    c.grid_blocks = c.n_samples;
     const int nw = src_shape(c, 0);
     const size_t shmem = src_lds(c.nimg, c.nsys, 0, c.chunk, c.stage_sig, nw);
     if (shmem > 65536) return hipErrorInvalidValue;
