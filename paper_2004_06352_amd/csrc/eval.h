@@ -458,40 +458,59 @@ __device__ __forceinline__ void eval_pot_f64(const ConstD c, double x, double y,
 // independent straight-line code that the compiler interleaves.  The steps
 // and their rounding are those of the reduction path of eval_pot_f64 (the
 // two cores' differences, one reciprocal for both reduced quotients).
+//
+// grad_cut_ell_point: one point's deflection in the potential's frame, before
+// the prefactors and the rotation back (which grad_cut_ell_add applies); the
+// constants may differ from lane to lane.
+struct CutEllConsts {
+    double x0, y0, cp, sp, eq2, ek2i, eca, dc, esa, ess, eq2sa, eq2ss;
+};
+__device__ __forceinline__ CutEllConsts cut_ell_consts(const ConstD c) {
+    return CutEllConsts{c[D_X0],  c[D_Y0],  c[D_C],   c[D_S],   c[D_EQ2],   c[D_EK2I],
+                        c[D_ECA], c[D_DC],  c[D_ESA], c[D_ESS], c[D_EQ2SA], c[D_EQ2SS]};
+}
+__device__ __forceinline__ void grad_cut_ell_point(const CutEllConsts &k, double x, double y,
+                                                   double &ax, double &ay, const Series &S) {
+    const double dx = x - k.x0, dy = y - k.y0;
+    const double xp = fma(dx, k.cp, dy * k.sp);
+    const double yp = fma(-k.sp, dx, dy * k.cp);
+    const double x2 = xp * xp, y2 = yp * yp;
+    const double ta = fma(k.eq2, x2, fma(k.ek2i, y2, k.eca));
+    const double ts = ta + k.dc;
+    const double ra = rsq2q(ta), rs = rsq2q(ts);
+    const double A1 = fma(ta, ra, k.esa), A2 = fma(ts, rs, k.ess);
+    const double B1 = fma(ta, ra, k.eq2sa), B2 = fma(ts, rs, k.eq2ss);
+    const double Dx = fma(A1, A2, x2);
+    const double Dy = fma(B1, B2, -y2);
+    const double Nx = xp * (A2 - A1);
+    const double Ny = yp * (B2 - B1);
+    const AtanRed ra_ = atan_reduce(Nx, Dx);
+    const AtanhRed rh = atanh_reduce(Ny, Dy);
+    const double R3 = rcp64(ra_.den * rh.den);
+    const double b = ra_.num * (R3 * rh.den);
+    const double s = rh.num * (R3 * ra_.den);
+    ax = atan_finish(ra_, b, S);
+    ay = atanh_finish(rh, s, S);
+}
+// acc += the rotated, scaled deflection (pfc, pfs: the potential's D_PFC, D_PFS)
+__device__ __forceinline__ void grad_cut_ell_add(double pfc, double pfs, double ax, double ay,
+                                                 double *acc) {
+    acc[0] = fma(pfc, ax, acc[0]);
+    acc[0] = fma(-pfs, ay, acc[0]);
+    acc[1] = fma(pfs, ax, acc[1]);
+    acc[1] = fma(pfc, ay, acc[1]);
+}
 template <int NP, int W>
 __device__ __forceinline__ void grad_cut_ell_full(const ConstD c, const double *x,
                                                   const double *y, double (*acc)[W],
                                                   const Series &S) {
-    const double x0 = c[D_X0], y0 = c[D_Y0], cp = c[D_C], sp = c[D_S];
-    const double eq2 = c[D_EQ2], ek2i = c[D_EK2I], eca = c[D_ECA], dc = c[D_DC];
-    const double esa = c[D_ESA], ess = c[D_ESS], eq2sa = c[D_EQ2SA], eq2ss = c[D_EQ2SS];
+    const CutEllConsts k = cut_ell_consts(c);
     const double pfc = c[D_PFC], pfs = c[D_PFS];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const double dx = x[p] - x0, dy = y[p] - y0;
-        const double xp = fma(dx, cp, dy * sp);
-        const double yp = fma(-sp, dx, dy * cp);
-        const double x2 = xp * xp, y2 = yp * yp;
-        const double ta = fma(eq2, x2, fma(ek2i, y2, eca));
-        const double ts = ta + dc;
-        const double ra = rsq2q(ta), rs = rsq2q(ts);
-        const double A1 = fma(ta, ra, esa), A2 = fma(ts, rs, ess);
-        const double B1 = fma(ta, ra, eq2sa), B2 = fma(ts, rs, eq2ss);
-        const double Dx = fma(A1, A2, x2);
-        const double Dy = fma(B1, B2, -y2);
-        const double Nx = xp * (A2 - A1);
-        const double Ny = yp * (B2 - B1);
-        const AtanRed ra_ = atan_reduce(Nx, Dx);
-        const AtanhRed rh = atanh_reduce(Ny, Dy);
-        const double R3 = rcp64(ra_.den * rh.den);
-        const double b = ra_.num * (R3 * rh.den);
-        const double s = rh.num * (R3 * ra_.den);
-        const double ax = atan_finish(ra_, b, S);
-        const double ay = atanh_finish(rh, s, S);
-        acc[p][0] = fma(pfc, ax, acc[p][0]);
-        acc[p][0] = fma(-pfs, ay, acc[p][0]);
-        acc[p][1] = fma(pfs, ax, acc[p][1]);
-        acc[p][1] = fma(pfc, ay, acc[p][1]);
+        double ax, ay;
+        grad_cut_ell_point(k, x[p], y[p], ax, ay, S);
+        grad_cut_ell_add(pfc, pfs, ax, ay, acc[p]);
     }
 }
 
