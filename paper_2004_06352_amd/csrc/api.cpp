@@ -1314,8 +1314,10 @@ lens_status_t lens_mcmc_create(lens_ctx_t *ctx, const lens_pot_table_t *fixed,
     L.chi2 = nullptr;
     L.src_x = L.src_y = nullptr;
     L.rec = (double *)(sp.base + sp.o_rec);
+    // (batch-shaped blocks sharing the staged catalogue; the launch takes one
+    // wave per walker)
     L.persistent = 1;
-    L.grid_blocks = batched_blocks(ctx, W);
+    L.grid_blocks = W;
     L.prec = 0;
     L.mc.nfree = nf;
     L.mc.params = d->params;

@@ -62,7 +62,7 @@ struct Chi2SrcLaunch {
 };
 hipError_t launch_chi2_prep(const Chi2SrcLaunch &c, hipStream_t st);
 hipError_t launch_chi2_src(const Chi2SrcLaunch &c, hipStream_t st);
-// The sampler's chi^2 (FP64, persistent): c.mc.mode 1 or 2.
+// The sampler's chi^2 (FP64, one wave per walker, c.n_samples walkers): c.mc.mode 1 or 2.
 hipError_t launch_mcmc_chi2(const Chi2SrcLaunch &c, hipStream_t st);
 
 // Image plane
