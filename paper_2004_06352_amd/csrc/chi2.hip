@@ -192,9 +192,23 @@ __host__ __device__ inline size_t src_wave_doubles(int nimg, int chunk, int prec
 // The block-shared region: thread tid stages entries tid, tid + nthr, ...
 // (N of them cover the at most 64 SRC_SIG_LOADS entries staging admits), all
 // its loads issued before its LDS writes.
+// The launch's arguments read through an opaque pointer into the kernel
+// argument segment (the kernel's one argument sits at its start).  Each section
+// of the per-sample kernel takes a fresh one, so that the fields it needs are
+// reloaded there by scalar loads instead of held from the kernel's entry: held
+// across the potential loop they did not fit the scalar registers beside the
+// loop's own and were parked in vector-register lanes (v_writelane and
+// v_readlane, vector instructions) and spilled.
+typedef const __attribute__((address_space(4))) Chi2SrcLaunch *ArgsPtr;
+__device__ __forceinline__ ArgsPtr launch_args() {
+    ArgsPtr p = (ArgsPtr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 template <int N>
-__device__ __forceinline__ void src_stage_images(const Chi2SrcLaunch &a, double *shw, int tid,
-                                                 int nthr) {
+__device__ __forceinline__ void src_stage_images(ArgsPtr A, double *shw, int tid, int nthr) {
+    const auto &a = *A;
     const size_t pad = a.nimg_pad;
     int *offw = reinterpret_cast<int *>(shw + 6 * (size_t)a.nimg);
     const int tmax = max(a.nimg - 1, 0);
@@ -243,15 +257,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 // operations as the acceptance's copy) -> amplitude form (sigma [km/s] -> b0
 // [arcsec] = K pi (sigma/c)^2 rad, e -> eps = e/(1 + sqrt(1 - e^2)), as the
 // table conversion) -> derived constants at dst (stride 1, FP64 only).
-__device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *th,
-                                            const double *uw, bool in, int k, double *dst) {
+__device__ __forceinline__ void mcmc_derive(const double *step, double bK, int *status,
+                                            const double *th, const double *uw, bool in, int k,
+                                            double *dst) {
     // (all 21 loads issued before the first use: one memory latency, not seven)
     double t[7], s[7], u[7], q[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
         const int i = 7 * k + j;
         t[j] = th[i];
-        s[j] = mc.step[i];
+        s[j] = step[i];
         u[j] = uw[i];
     }
 #pragma unroll
@@ -259,10 +274,10 @@ __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *t
     const double c_kms = 299792.458;
     const double arcsec_per_rad = 648000.0 / M_PI;
     const double v = q[2] / c_kms;
-    const double b0 = mc.bK * M_PI * v * v * arcsec_per_rad;
+    const double b0 = bK * M_PI * v * v * arcsec_per_rad;
     const double eps = q[3] / (1.0 + sqrt(1.0 - q[3] * q[3]));
     prologue_values<false, false>(q[0], q[1], b0, eps, q[4], q[5], q[6], 0, dst, nullptr, 1,
-                                  mc.status);
+                                  status);
 }
 
 // MCMC: the sampler form.  Walker m's free potentials are derived by the wave
@@ -273,44 +288,47 @@ __device__ __forceinline__ void mcmc_derive(const McmcFused &mc, const double *t
 // At least four waves per SIMD, so that a 4096-sample batch is one round of
 // waves.  The sampler form takes one walker per wave and has no sample loop
 // (with one, the constants of the walker's logarithm and prologue were held
-// in registers across it: 158 VGPRs, 134 without); it keeps three waves (at
-// four a few registers spill outside the potential loop, and a 4096-walker
-// step measured the same, 36.0-36.6 against 36.2-36.4 us).
+// in registers across it: 158 VGPRs, 134 without); with the arguments
+// reloaded per section it fits four waves too (twelve bytes of scratch per
+// lane outside the potential loop; 4096-walker step 37.3 -> 35.0 us in a
+// same-box comparison, three waves 36.5).
 // DERIVE: the sample's free constants formed by the wave from the amplitude
 // table (a.derive_free), a variant of its own so that the usual batch keeps
 // its register allocation.
 template <int PREC, bool MCMC = false, bool DERIVE = false>
-__global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC != 0)) ? 3 : 4)) chi2_src_kernel(Chi2SrcLaunch a) {
+__global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((DERIVE && PREC != 0) ? 3 : 4))
+    chi2_src_kernel(Chi2SrcLaunch a) {
     // A block holds blockDim.x / 64 waves, each on its own samples.  LDS: when
     // the catalogue is small enough (stage_sig), a region the block's waves
     // share, staged once: each image's x, y, fixed deflection x, y, 1/sigma^2
     // and Dls/Ds [6][nimg] and the nsys + 1 image offsets; then per wave
     // [2][nimg] unlensed x, y and the staged potentials (FP64, then FP32).
     extern __shared__ double sh[];
+    const ArgsPtr A0 = launch_args();
     // (the wave index is uniform across the wave: in a scalar register, the
     // per-wave LDS region's base is too)
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const size_t shared_d = a.stage_sig ? src_shared_doubles(a.nimg, a.nsys) : 0;
-    const double *ix = sh, *iy = sh + a.nimg, *ir0 = sh + 2 * (size_t)a.nimg,
-                 *ir1 = sh + 3 * (size_t)a.nimg;
-    const double *sw = sh + 4 * (size_t)a.nimg, *sf = sh + 5 * (size_t)a.nimg;
-    const int *soff = reinterpret_cast<const int *>(sh + 6 * (size_t)a.nimg);
-    double *own = sh + shared_d + (size_t)wv * src_wave_doubles(a.nimg, a.chunk, PREC);
-    double *sx = own, *sy = own + a.nimg;
-    double *pd = own + 2 * (size_t)a.nimg;
-    float *pf = reinterpret_cast<float *>(pd + (size_t)a.chunk * NDER);
-    const int pad = a.nimg_pad, st = a.freet.stride, nf = a.freet.n;
+    const size_t shared_d = A0->stage_sig ? src_shared_doubles(A0->nimg, A0->nsys) : 0;
+    const double *ix = sh, *iy = sh + A0->nimg, *ir0 = sh + 2 * (size_t)A0->nimg,
+                 *ir1 = sh + 3 * (size_t)A0->nimg;
+    const double *sw = sh + 4 * (size_t)A0->nimg, *sf = sh + 5 * (size_t)A0->nimg;
+    const int *soff = reinterpret_cast<const int *>(sh + 6 * (size_t)A0->nimg);
+    double *own = sh + shared_d + (size_t)wv * src_wave_doubles(A0->nimg, A0->chunk, PREC);
+    double *sx = own, *sy = own + A0->nimg;
+    double *pd = own + 2 * (size_t)A0->nimg;
+    float *pf = reinterpret_cast<float *>(pd + (size_t)A0->chunk * NDER);
+    const int pad = A0->nimg_pad, st = A0->freet.stride, nf = A0->freet.n;
     // The first sample's range of free potentials (each next one is fetched
     // during the current sample's reduction; DERIVE, whose registers are
     // fuller, reads it at the top of the sample).
     const int mstride = gridDim.x * nw;
-    int m = a.sample0 + blockIdx.x * nw + wv;
+    int m = A0->sample0 + blockIdx.x * nw + wv;
     int fo0 = 0, fo1 = 0;
-    if (!MCMC && !DERIVE && m < a.n_samples) {
-        fo0 = a.free_off[m];
-        fo1 = a.free_off[m + 1];
+    if (!MCMC && !DERIVE && m < A0->n_samples) {
+        fo0 = A0->free_off[m];
+        fo1 = A0->free_off[m + 1];
     }
     // What does not depend on the sample is staged once per block, by all its
     // threads, before one block barrier: then the waves read it from LDS, not
@@ -318,77 +336,82 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
     // their L2 channels serialise the requests), and the reduction reads LDS
     // only.  Every load of a thread is issued, unconditionally (indices
     // clamped into the arrays), before its first LDS write.
-    if (a.stage_sig) {
+    if (A0->stage_sig) {
         if (nthr >= 256)
-            src_stage_images<1>(a, sh, tid, nthr);
+            src_stage_images<1>(A0, sh, tid, nthr);
         else if (nthr >= 128)
-            src_stage_images<2>(a, sh, tid, nthr);
+            src_stage_images<2>(A0, sh, tid, nthr);
         else
-            src_stage_images<4>(a, sh, tid, nthr);
+            src_stage_images<4>(A0, sh, tid, nthr);
     }
     __syncthreads();  // (the only block barrier: below, each wave on its own)
     for (; m < a.n_samples; m += mstride) {
+        const ArgsPtr A1 = launch_args();
         int k0 = 0, k1 = 0;
         bool in = false;
-        const int P = 7 * a.mc.nfree;
+        const int P = 7 * A1->mc.nfree;
         const double *th = nullptr, *uw = nullptr;
         if (MCMC) {
-            th = a.mc.params + (size_t)m * P;
-            uw = a.mc.u + (size_t)m * (P + 1);
+            th = A1->mc.params + (size_t)m * P;
+            uw = A1->mc.u + (size_t)m * (P + 1);
             k0 = 0;
-            k1 = a.mc.nfree;
-            if (a.mc.mode == 2) {
+            k1 = A1->mc.nfree;
+            if (A1->mc.mode == 2) {
                 int out = 0;
                 for (int i = lane; i < P; i += 64) {
-                    const double v = th[i] + a.mc.step[i] * (2.0 * uw[i] - 1.0);
-                    if (!(v >= a.mc.lo[i] && v <= a.mc.hi[i])) out = 1;
+                    const double v = th[i] + A1->mc.step[i] * (2.0 * uw[i] - 1.0);
+                    if (!(v >= A1->mc.lo[i] && v <= A1->mc.hi[i])) out = 1;
                 }
                 in = __ballot(out) == 0;
             }
         } else {
             if (DERIVE) {
-                fo0 = a.free_off[m];
-                fo1 = a.free_off[m + 1];
+                fo0 = A1->free_off[m];
+                fo1 = A1->free_off[m + 1];
             }
             k0 = __builtin_amdgcn_readfirstlane(min(max(fo0, 0), nf));
             k1 = __builtin_amdgcn_readfirstlane(min(max(fo1, k0), nf));
         }
-        for (int g0 = 0; g0 < a.nimg; g0 += 64 * SRC_IPL) {
+        for (int g0 = 0; g0 < A1->nimg; g0 += 64 * SRC_IPL) {
             // (lanes past the last image load its data, unconditionally so
             // that the loads need no wait between them, and store nothing)
             double x[SRC_IPL], y[SRC_IPL], acc[SRC_IPL][5];
 #pragma unroll
             for (int j = 0; j < SRC_IPL; ++j) {
-                const int t = min(g0 + j * 64 + lane, a.nimg - 1);
-                if (a.stage_sig) {
+                const int t = min(g0 + j * 64 + lane, A1->nimg - 1);
+                if (A1->stage_sig) {
                     x[j] = ix[t];
                     y[j] = iy[t];
                     acc[j][0] = ir0[t];
                     acc[j][1] = ir1[t];
                 } else {
-                    x[j] = a.x[t];
-                    y[j] = a.y[t];
-                    acc[j][0] = a.rec[t];
-                    acc[j][1] = a.rec[pad + t];
+                    x[j] = A1->x[t];
+                    y[j] = A1->y[t];
+                    acc[j][0] = A1->rec[t];
+                    acc[j][1] = A1->rec[pad + t];
                 }
                 acc[j][2] = acc[j][3] = acc[j][4] = 0.0;
             }
 
             for (int kc = k0; kc < k1; kc += a.chunk) {
-                const int cnt = min(a.chunk, k1 - kc);
+                const ArgsPtr A2 = launch_args();
+                const int cnt = min(A2->chunk, k1 - kc);
                 wave_lds_sync();
                 if (MCMC) {
-                    if (lane < cnt) mcmc_derive(a.mc, th, uw, in, kc + lane, pd + lane * NDER);
+                    if (lane < cnt)
+                        mcmc_derive(A2->mc.step, A2->mc.bK, A2->mc.status, th, uw, in, kc + lane,
+                                    pd + lane * NDER);
                 } else if (DERIVE) {
                     // the free potentials' derived constants formed here from
                     // the amplitude table (lane per potential) instead of read
                     // from a table a prologue launch wrote
                     if (lane < cnt) {
-                        const PotSoA &F = a.free_amp;
                         const int k = kc + lane;
                         prologue_values<PREC != 0, false>(
-                            F.x0[k], F.y0[k], F.b0[k], F.eps[k], F.phi[k], F.rcore[k], F.rcut[k],
-                            0, pd + lane * NDER, pf + lane * NDERF, 1, a.status);
+                            A2->free_amp.x0[k], A2->free_amp.y0[k], A2->free_amp.b0[k],
+                            A2->free_amp.eps[k], A2->free_amp.phi[k], A2->free_amp.rcore[k],
+                            A2->free_amp.rcut[k], 0, pd + lane * NDER, pf + lane * NDERF, 1,
+                            A2->status);
                     }
                 } else {
                     // every lane's loads in flight at once, then the stores
@@ -403,7 +426,7 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
                     for (int i = 0; i < SRC_STAGE_LOADS; ++i) {
                         const int e = l0 + 64 * i;
                         const int kk = e / NDER, ci = e - kk * NDER;
-                        v[i] = kk < cnt ? a.freet.d[(size_t)ci * st + kc + kk] : 0.0;
+                        v[i] = kk < cnt ? A2->freet.d[(size_t)ci * st + kc + kk] : 0.0;
                     }
 #pragma unroll
                     for (int i = 0; i < SRC_STAGE_LOADS; ++i) {
@@ -414,7 +437,7 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
                 if (PREC != 0 && !MCMC && !DERIVE) {
                     for (int e = lane; e < cnt * NDERF; e += 64) {
                         const int ci = e / cnt, kk = e - ci * cnt;
-                        pf[kk * NDERF + ci] = a.freet.f[(size_t)ci * st + kc + kk];
+                        pf[kk * NDERF + ci] = A2->freet.f[(size_t)ci * st + kc + kk];
                     }
                 }
                 wave_lds_sync();
@@ -427,7 +450,7 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
                         if ((kind & (K_CUT | K_ELL | K_SING)) == (K_CUT | K_ELL)) {
 #pragma unroll
                             for (int j = 0; j < SRC_IPL; j += 2) {
-                                if (g0 + j * 64 >= a.nimg) break;  // uniform
+                                if (g0 + j * 64 >= A2->nimg) break;  // uniform
                                 grad_cut_ell_full<2>(cd, x + j, y + j, acc + j, a.S);
                             }
                             continue;
@@ -435,7 +458,7 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
                     }
 #pragma unroll
                     for (int j = 0; j < SRC_IPL; ++j) {
-                        if (g0 + j * 64 >= a.nimg) break;  // uniform: no image in this slot
+                        if (g0 + j * 64 >= A2->nimg) break;  // uniform: no image in this slot
                         if (PREC == 0) {
                             eval_pot_f64<true, false>(cd, x[j], y[j], acc[j], a.S);
                         } else {
@@ -448,11 +471,12 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
                     }
                 }
             }
-            if (a.stage_sig) {
+            const ArgsPtr A3 = launch_args();
+            if (A3->stage_sig) {
 #pragma unroll
                 for (int j = 0; j < SRC_IPL; ++j) {
                     const int t = g0 + j * 64 + lane;
-                    if (t < a.nimg) {
+                    if (t < A3->nimg) {
                         const double f = sf[t];
                         sx[t] = x[j] - f * acc[j][0];
                         sy[t] = y[j] - f * acc[j][1];
@@ -463,32 +487,33 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
 #pragma unroll
                 for (int j = 0; j < SRC_IPL; ++j) {
                     const int t = g0 + j * 64 + lane;
-                    f[j] = t < a.nimg ? a.rec[2 * (size_t)pad + t] : 0.0;
+                    f[j] = t < A3->nimg ? A3->rec[2 * (size_t)pad + t] : 0.0;
                 }
 #pragma unroll
                 for (int j = 0; j < SRC_IPL; ++j) {
                     const int t = g0 + j * 64 + lane;
-                    if (t < a.nimg) {
+                    if (t < A3->nimg) {
                         sx[t] = x[j] - f[j] * acc[j][0];
                         sy[t] = y[j] - f[j] * acc[j][1];
                     }
                 }
             }
         }
-        if (!MCMC && !DERIVE && a.persistent && m + mstride < a.n_samples) {
-            fo0 = a.free_off[m + mstride];
-            fo1 = a.free_off[m + mstride + 1];
+        const ArgsPtr A4 = launch_args();
+        if (!MCMC && !DERIVE && A4->persistent && m + mstride < A4->n_samples) {
+            fo0 = A4->free_off[m + mstride];
+            fo1 = A4->free_off[m + mstride + 1];
         }
         wave_lds_sync();
         double part = 0.0;
-        for (int i = lane; i < a.nsys; i += 64) {
+        for (int i = lane; i < A4->nsys; i += 64) {
             int o0, o1;
-            if (a.stage_sig) {
+            if (A4->stage_sig) {
                 o0 = soff[i];
                 o1 = max(soff[i + 1], o0);
             } else {
-                o0 = min(max(a.img_off[i], 0), a.nimg);
-                o1 = min(max(a.img_off[i + 1], o0), a.nimg);
+                o0 = min(max(A4->img_off[i], 0), A4->nimg);
+                o1 = min(max(A4->img_off[i + 1], o0), A4->nimg);
             }
             const int M = o1 - o0;
             double mx = 0.0, my = 0.0;
@@ -502,7 +527,7 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
                 my *= im;
             }
             double s = 0.0;
-            if (a.stage_sig) {
+            if (A4->stage_sig) {
                 for (int t = o0; t < o1; ++t) {
                     const double ex = sx[t] - mx, ey = sy[t] - my;
                     s = fma(ex * ex + ey * ey, sw[t], s);
@@ -510,13 +535,13 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
             } else {
                 for (int t = o0; t < o1; ++t) {
                     const double ex = sx[t] - mx, ey = sy[t] - my;
-                    s = fma(ex * ex + ey * ey, a.rec[3 * (size_t)pad + t], s);
+                    s = fma(ex * ex + ey * ey, A4->rec[3 * (size_t)pad + t], s);
                 }
             }
             part += s;
-            if (a.src_x) {
-                a.src_x[(size_t)m * a.nsys + i] = mx;
-                a.src_y[(size_t)m * a.nsys + i] = my;
+            if (A4->src_x) {
+                A4->src_x[(size_t)m * A4->nsys + i] = mx;
+                A4->src_y[(size_t)m * A4->nsys + i] = my;
             }
         }
         part = wave_sum(part);
@@ -525,22 +550,23 @@ __global__ void __launch_bounds__(64 * SRC_MAX_WPB, ((MCMC || (DERIVE && PREC !=
             // the decision on lane 0's value
             part = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(part)),
                                     __builtin_amdgcn_readfirstlane(__double2loint(part)));
-            if (a.mc.mode == 1) {
-                if (lane == 0) a.mc.chi2[m] = part;
+            if (A4->mc.mode == 1) {
+                if (lane == 0) A4->mc.chi2[m] = part;
             } else {
-                const double d = part - a.mc.chi2[m];
+                const double d = part - A4->mc.chi2[m];
                 const double ul = uw[P];
                 if (in && (d <= 0.0 || -2.0 * log(ul) > d)) {
                     for (int i = lane; i < P; i += 64)
-                        a.mc.params[(size_t)m * P + i] = th[i] + a.mc.step[i] * (2.0 * uw[i] - 1.0);
+                        A4->mc.params[(size_t)m * P + i] =
+                            th[i] + A4->mc.step[i] * (2.0 * uw[i] - 1.0);
                     if (lane == 0) {
-                        a.mc.chi2[m] = part;
-                        a.mc.accepted[m] += 1;
+                        A4->mc.chi2[m] = part;
+                        A4->mc.accepted[m] += 1;
                     }
                 }
             }
-        } else if (lane == 0 && a.chi2) {
-            a.chi2[m] = part;
+        } else if (lane == 0 && A4->chi2) {
+            A4->chi2[m] = part;
         }
         wave_lds_sync();  // sx, sy are rewritten by the next sample
         if (MCMC || !a.persistent) break;
