@@ -44,11 +44,22 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     return v;
 }
+// Two sums at once, step by step (the same additions as wave_sum on each, the
+// two shuffles of a step in flight together)
+__device__ __forceinline__ void wave_sum2(double &u, double &v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double su = __shfl_down(u, o, 64), sv = __shfl_down(v, o, 64);
+        u += su;
+        v += sv;
+    }
+}
 
 // Per-image constants that every sample shares, computed once per call:
 // rec[0][t], rec[1][t] = the fixed potentials' deflection at image t,
-// rec[2][t] = the image's Dls/Ds (its system's, found by bisection over the
-// image offsets staged in LDS) and rec[3][t] = 1/sigma_t^2, the weight of its
+// rec[2][t] = the image's Dls/Ds (its system's: with at most 64 systems found
+// by one ballot over their first images, else by bisection over the image
+// offsets staged in LDS) and rec[3][t] = 1/sigma_t^2, the weight of its
 // term in Eq. (6).  One block per image, of as many threads as
 // there are fixed potentials (rounded up to whole waves, at most
 // PREP_MAX_BLOCK): thread l evaluates the fixed potentials l, l + blockDim,
@@ -110,6 +121,21 @@ __global__ void __launch_bounds__(PREP_MAX_BLOCK) chi2_prep_kernel(Chi2SrcLaunch
     const bool staged = a.nsys + 1 <= PREP_OFF_MAX;
     if (staged)
         for (int i = tid; i <= a.nsys; i += nthr) s_off[i] = a.img_off[i];
+    // Wave 0 loads, while the potentials are evaluated, what the block's last
+    // step needs: the image's sigma and, lane l, system l's first image and
+    // Dls/Ds (with at most 64 systems the image's system is then one ballot,
+    // not a bisection and a load after the reduction).
+    const bool wide = a.nsys > 64;
+    int o_lo = 0;
+    double f_l = 0.0, sg = 1.0;
+    if (wave == 0) {
+        const int l = min(lane, max(a.nsys - 1, 0));
+        if (!wide) {
+            o_lo = a.img_off[l];
+            f_l = a.f[l];
+        }
+        sg = a.sig[t];
+    }
     double acc[5] = {0, 0, 0, 0, 0};
     const double x = a.x[t], y = a.y[t];
     const int st = a.fixedt.stride;
@@ -142,7 +168,15 @@ __global__ void __launch_bounds__(PREP_MAX_BLOCK) chi2_prep_kernel(Chi2SrcLaunch
             acc[1] += (double)o[1];
         }
     }
-    const double ax = wave_sum(acc[0]), ay = wave_sum(acc[1]);
+    // the image's system: the last one whose first image is at most t (the
+    // bisection's answer for ordered offsets)
+    double f_t = 0.0;
+    if (wave == 0 && !wide) {
+        const unsigned long long hit = __ballot(lane < a.nsys && o_lo <= t);
+        f_t = __shfl(f_l, hit ? 63 - __clzll(hit) : 0, 64);
+    }
+    double ax = acc[0], ay = acc[1];
+    wave_sum2(ax, ay);
     if (lane == 0) {
         s_red[0][wave] = ax;
         s_red[1][wave] = ay;
@@ -154,11 +188,10 @@ __global__ void __launch_bounds__(PREP_MAX_BLOCK) chi2_prep_kernel(Chi2SrcLaunch
             sx += s_red[0][w];
             sy += s_red[1][w];
         }
-        const int i = system_of(staged ? s_off : a.img_off, a.nsys, t);
+        if (wide) f_t = a.f[system_of(staged ? s_off : a.img_off, a.nsys, t)];
         a.rec[t] = sx;
         a.rec[(size_t)a.nimg_pad + t] = sy;
-        a.rec[2 * (size_t)a.nimg_pad + t] = a.f[i];
-        const double sg = a.sig[t];
+        a.rec[2 * (size_t)a.nimg_pad + t] = f_t;
         a.rec[3 * (size_t)a.nimg_pad + t] = 1.0 / (sg * sg);
     }
 }
@@ -189,9 +222,6 @@ __host__ __device__ inline size_t src_shared_doubles(int nimg, int nsys) {
 __host__ __device__ inline size_t src_wave_doubles(int nimg, int chunk, int prec) {
     return 2 * (size_t)nimg + (size_t)chunk * NDER + (prec ? ((size_t)chunk * NDERF + 1) / 2 : 0);
 }
-// The block-shared region: thread tid stages entries tid, tid + nthr, ...
-// (N of them cover the at most 64 SRC_SIG_LOADS entries staging admits), all
-// its loads issued before its LDS writes.
 // The launch's arguments read through an opaque pointer into the kernel
 // argument segment (the kernel's one argument sits at its start).  Each section
 // of the per-sample kernel takes a fresh one, so that the fields it needs are
@@ -206,6 +236,9 @@ __device__ __forceinline__ ArgsPtr launch_args() {
     return p;
 }
 
+// The block-shared region: thread tid stages entries tid, tid + nthr, ...
+// (N of them cover the at most 64 SRC_SIG_LOADS entries staging admits), all
+// its loads issued before its LDS writes.
 template <int N>
 __device__ __forceinline__ void src_stage_images(ArgsPtr A, double *shw, int tid, int nthr) {
     const auto &a = *A;
