@@ -131,7 +131,6 @@ __device__ __forceinline__ double rsq2q(double T) {
 
 constexpr double kPi2 = 1.5707963267948966;
 constexpr double kPi4 = 0.7853981633974483;
-constexpr double kSqrt2 = 1.4142135623730951;
 constexpr double kLn2 = 0.6931471805599453;
 
 // atan(N/D), D > 0: t = min/max of |N|, D in [0, 1] is shifted to the
@@ -192,10 +191,15 @@ struct AtanhRed {
 };
 __device__ __forceinline__ AtanhRed atanh_reduce(double N, double D) {
     const double P = D + N, Q = D - N;
-    const double mp = __builtin_amdgcn_frexp_mant(P), mq = __builtin_amdgcn_frexp_mant(Q);
-    int k = __builtin_amdgcn_frexp_exp(P) - __builtin_amdgcn_frexp_exp(Q);
-    k += (mp > kSqrt2 * mq) ? 1 : 0;
-    k -= (mq > kSqrt2 * mp) ? 1 : 0;
+    // k ~ log2(P/Q) from the two positive operands' high words (exponent and
+    // the first 20 mantissa bits: log2(1 + m) read as m), rounded: the reduced
+    // ratio P 2^-k / Q is within 2^(1/2 + 0.0861) of 1 and the quotient below
+    // within LENS_ATANH_R_MAX, the interval of the polynomial
+    int k = (__double2hiint(P) - __double2hiint(Q) + (1 << 19)) >> 20;
+    // (an empty statement fixes k here: moved earlier by the scheduler, the
+    // two interleaved points' reductions needed five more registers and the
+    // source-plane kernels spilled)
+    asm volatile("" : "+v"(k));
     // (D+N) 2^-k - (D-N) as (D+N)(2^-k - 1) + 2N: exactly 2N when k = 0, with
     // no select; 2^-k - 1 is exact for the exponents that occur
     const double t = __builtin_amdgcn_ldexp(1.0, -k);
@@ -205,7 +209,8 @@ __device__ __forceinline__ AtanhRed atanh_reduce(double N, double D) {
     r.k = k;
     return r;
 }
-// atanh(s) for |s| <= 3 - 2 sqrt 2: s + s^3 q(s^2).
+// atanh(s) for |s| <= LENS_ATANH_R_MAX (0.2004, what the reduction leaves):
+// s + s^3 q(s^2).  The first polynomial tier takes the narrower 3 - 2 sqrt 2.
 constexpr double kAtanhS = 0.171572875253809;  // 3 - 2 sqrt 2, rounded down
 __device__ __forceinline__ double atanh_poly(double s, const Series &S) {
     const double s2 = s * s;

@@ -44,7 +44,8 @@ def horner(x, coeffs):
 D = defines()
 CASES = [
     ("atan", "LENS_ATAN_COEFFS", "LENS_ATAN_N", math.tan(math.pi / 16), mp.atan),
-    ("atanh", "LENS_ATANH_COEFFS", "LENS_ATANH_N", 3 - 2 * math.sqrt(2), mp.atanh),
+    ("atanh", "LENS_ATANH_COEFFS", "LENS_ATANH_N", float.fromhex(D["LENS_ATANH_R_MAX"]),
+     mp.atanh),
     ("atan short", "LENS_ATAN_S_COEFFS", "LENS_ATAN_S_N", math.tan(math.pi / 16) / 5, mp.atan),
     ("atanh short", "LENS_ATANH_S_COEFFS", "LENS_ATANH_S_N", (3 - 2 * math.sqrt(2)) / 5,
      mp.atanh),
@@ -64,6 +65,50 @@ def test_polynomial_within_few_ulp(name, key, nkey, bound, fn):
             worst = max(worst, float(abs((mp.mpf(got) - ref) / ref)))
     # FP64 evaluation: a few roundings of the last terms on top of the fit
     assert worst < 4 * 2.0 ** -53, f"{name}: {worst:.3g}"
+
+
+def reduction_bound():
+    """|s| after the hyperbolic arctangent's reduction: k read from the high
+    words is within 1/2 + max(log2(1 + m) - m) + 2^-20 of log2(P/Q)."""
+    g = -math.log(math.log(2)) / math.log(2) - 1 / math.log(2) + 1
+    r = 2.0 ** (0.5 + g + 2.0 ** -20)
+    return (r - 1) / (r + 1)
+
+
+def test_reduction_interval_bound():
+    assert float.fromhex(D["LENS_ATANH_R_MAX"]) == pytest.approx(reduction_bound(), rel=1e-12)
+    assert float.fromhex(D["LENS_ATANH_R_MAX"]) > 3 - 2 * math.sqrt(2)
+
+
+def hi_word(v):
+    return int.from_bytes(__import__("struct").pack(">d", v)[:4], "big")
+
+
+def test_reduction_keeps_the_quotient_inside_the_interval():
+    """The kernels' k = (hi(P) - hi(Q) + 2^19) >> 20 for P = D + N, Q = D - N:
+    over random pairs, pairs whose mantissas sit where log2(1 + m) - m peaks,
+    and exponent gaps up to 60, |(P 2^-k - Q)/(P 2^-k + Q)| stays within the
+    bound the polynomial is fitted on, and k is within one of the rounded
+    log2(P/Q)."""
+    import random
+    rng = random.Random(5)
+    bound = float.fromhex(D["LENS_ATANH_R_MAX"])
+    m_star = 1 / math.log(2) - 1
+    cases = []
+    for _ in range(20000):
+        cases.append((2.0 ** rng.uniform(-40, 40), 2.0 ** rng.uniform(-40, 40)))
+    for e in range(-60, 61):
+        for mp_, mq in ((m_star, 0.0), (0.0, m_star), (m_star, 0.999999), (0.999999, m_star)):
+            for h in (0.49, 0.5, 0.51):
+                cases.append(((1 + mp_) * 2.0 ** (e + h), (1 + mq)))
+    worst = 0.0
+    for P, Q in cases:
+        k = (hi_word(P) - hi_word(Q) + (1 << 19)) >> 20
+        r = P * 2.0 ** -k / Q
+        s = (r - 1) / (r + 1)
+        worst = max(worst, abs(s))
+        assert abs(k - math.log2(P / Q)) <= 0.5 + 0.0861 + 1e-6
+    assert worst <= bound, worst
 
 
 def test_short_interval_bounds():
