@@ -4,6 +4,7 @@
 
 #include <math.h>
 
+#include "eval.h"
 #include "lens_internal.h"
 
 namespace lens {
@@ -32,15 +33,22 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
         c = cos(phi);
         sn = sin(phi);
     }
-    const double q = (1.0 - eps) / (1.0 + eps), q2 = q * q;
+    // One reciprocal of 1 + eps, one reciprocal square root of eps and one
+    // reciprocal of s - a (estimates and a Newton step each) serve every
+    // quotient below, instead of correctly rounded divisions (a few units in
+    // the last place on the constants)
+    const double ope = 1.0 + eps;
+    const double r1 = rcp64(ope);
+    const double hr = ell ? 0.5 * rsq64(eps) : 0.0;  // 1/(2 sqrt(eps))
+    const double q = (1.0 - eps) * r1, q2 = q * q;
     const double Sa = (1.0 + eps) * a;
     const double Ss = cut ? (1.0 + eps) * s : 0.0;
-    const double k1 = ell ? 2.0 * sqrt(eps) / (1.0 + eps) : 0.0;
-    const double F = cut ? s / (s - a) : 1.0;
+    const double k1 = ell ? 4.0 * (eps * hr) * r1 : 0.0;  // 2 sqrt(eps)/(1 + eps)
+    const double F = cut ? s * rcp64(s - a) : 1.0;
     const double om = 1.0 - eps;
     const double DC = cut ? om * om * ((s - a) * (s + a)) : 0.0;
     const double DS = cut ? (1.0 + eps) * (s - a) : 0.0;
-    double PF = ell ? F * b0 * (1.0 - eps * eps) / (2.0 * sqrt(eps)) : F * b0;
+    double PF = ell ? F * b0 * (1.0 - eps * eps) * hr : F * b0;
     double HF = F * b0 * om;
     const bool ell32 = eps > 1e-8;
     int kind = (ell ? K_ELL : 0) | (ell32 ? K_ELL32 : 0) | (cut ? K_CUT : 0) |
@@ -61,7 +69,7 @@ __device__ __forceinline__ void prologue_values(double x0, double y0, double b0,
     // Hessian constants: the FP64 evaluation of an elliptical potential
     // leaves a factor k on the trace and 1/k^3 on the other parts, and works
     // with quarter radii (its 1/psi_w carry a factor 4, taken out here by h4)
-    const double kap = ell ? 1.0 / k1 : 1.0, kap2 = kap * kap, kap3 = kap2 * kap;
+    const double kap = ell ? ope * hr : 1.0, kap2 = kap * kap, kap3 = kap2 * kap;  // 1/k
     const double h4 = ell ? 0.25 : 1.0;
     const double hcms = HF * (c * c - sn * sn), hcs = HF * (c * sn);
     v[D_HT] = h4 * (kap * (0.5 * HF));
