@@ -372,17 +372,21 @@ def chi2_legs(args, ctx, secondary, torch, B, inputs, keep):
         from paper_2004_06352_amd import tune
         wpc, _ = tune.tune_chi2(ctx, fixed, free, off, cat)
         secondary["chi2_source_waves_per_cu"] = wpc
-    for name, path in (("batched", B.PATH_BATCHED), ("per_sample", B.PATH_PER_SAMPLE)):
-        # (enough calls that the closing synchronisation is a small share)
-        n = 200 if path == B.PATH_BATCHED else 3
-        w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=path, ctx=ctx),
-                           n, 1, torch, per_step=False)
-        secondary[f"chi2_source_{name}_samples_per_s"] = S * n / w
+    # (enough calls that the closing synchronisation is a small share, after
+    # warm-up calls that bring the clock back up; the per-sample path, a long
+    # run of one-wave launches that leaves the GPU mostly idle and its clock
+    # down, is timed last)
+    w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, ctx=ctx), 200, 20, torch,
+                       per_step=False)
+    secondary["chi2_source_batched_samples_per_s"] = S * 200 / w
     for name, resident in (("plan", False), ("plan_fixed_resident", True)):
         plan = B.Chi2Plan(fixed, free, off, cat, ctx=ctx, resident=resident)
-        w, e = timed_steps(plan.launch, 200, 2, torch, per_step=False)
+        w, e = timed_steps(plan.launch, 200, 20, torch, per_step=False)
         secondary[f"chi2_source_{name}_samples_per_s"] = S * 200 / w
         plan.close()
+    w, e = timed_steps(lambda: B.chi2_batch(fixed, free, off, cat, path=B.PATH_PER_SAMPLE,
+                                            ctx=ctx), 3, 1, torch, per_step=False)
+    secondary["chi2_source_per_sample_samples_per_s"] = S * 3 / w
     secondary["chi2_source_workload"] = c3["name"]
     keep["chi2_source"] = {"fp64": B.chi2_batch(fixed, free, off, cat, ctx=ctx)["chi2"].cpu().numpy(),
                            "fp32_acc64": B.chi2_batch(fixed, free, off, cat, prec=B.FP32_ACC64,
@@ -397,7 +401,7 @@ def chi2_legs(args, ctx, secondary, torch, B, inputs, keep):
     um = dev(inputs.sampler_uniforms(np.random.default_rng(9), Wn, 6))
     mc = B.Mcmc(fixed, cat, dev(sm["params"]), dev(sm["lo"]), dev(sm["hi"]),
                 dev(sm["step"]), um, ctx=ctx)
-    w, e = timed_steps(mc.step, 400, 3, torch, per_step=False)
+    w, e = timed_steps(mc.step, 400, 20, torch, per_step=False)
     secondary["mcmc_walker_steps_per_s"] = Wn * 400 / w
     secondary["mcmc_ms_per_step"] = w / 400 * 1e3
     mc.close()

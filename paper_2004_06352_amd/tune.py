@@ -118,34 +118,45 @@ def tune_map(ctx: B.Context, table, grid, prec=B.FP64, hess=True, reps=3, use_ca
     return best, results
 
 
-def tune_chi2(ctx: B.Context, fixed, free, free_off, cat, prec=B.FP64, reps=3,
+def tune_chi2(ctx: B.Context, fixed, free, free_off, cat, prec=B.FP64, reps=30, rounds=2,
               choices=(4, 8, 12, 16, 24, 32), verbose=False):
     """Pick and install the number of persistent waves per CU of the batched
     source-plane chi^2 for this batch; every choice must give bit-identical
-    chi^2 values.  Returns (best, [(waves_per_cu, seconds), ...])."""
+    chi^2 values.  Each choice is timed over `reps` back-to-back calls after
+    three untimed ones (calls of a few tens of microseconds: with a handful
+    timed right after an idle GPU the ramp decided the pick), in `rounds`
+    passes over the choices, keeping each one's best.  Returns
+    (best, [(waves_per_cu, seconds), ...])."""
     ref = None
-    results = []
-    for bpc in choices:
-        ctx.set_chi2_tuning(bpc)
-        out = B.chi2_batch(fixed, free, free_off, cat, prec=prec, ctx=ctx)["chi2"]
-        torch.cuda.synchronize()
-        if ref is None:
-            ref = out.clone()
-        elif not torch.equal(out, ref):
+    best_sec = {}
+    for _ in range(rounds):
+        for bpc in choices:
+            ctx.set_chi2_tuning(bpc)
+            out = B.chi2_batch(fixed, free, free_off, cat, prec=prec, ctx=ctx)["chi2"]
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = out.clone()
+            elif not torch.equal(out, ref):
+                if verbose:
+                    print("rejected (output differs):", bpc)
+                best_sec[bpc] = None
+                continue
+            if bpc in best_sec and best_sec[bpc] is None:
+                continue
+            for _ in range(3):
+                B.chi2_batch(fixed, free, free_off, cat, prec=prec, ctx=ctx)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(reps):
+                B.chi2_batch(fixed, free, free_off, cat, prec=prec, ctx=ctx)
+            ev1.record()
+            ev1.synchronize()
+            sec = ev0.elapsed_time(ev1) * 1e-3 / reps
+            best_sec[bpc] = min(sec, best_sec.get(bpc) or sec)
             if verbose:
-                print("rejected (output differs):", bpc)
-            continue
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(reps):
-            B.chi2_batch(fixed, free, free_off, cat, prec=prec, ctx=ctx)
-        ev1.record()
-        ev1.synchronize()
-        sec = ev0.elapsed_time(ev1) * 1e-3 / reps
-        results.append((bpc, sec))
-        if verbose:
-            print(f"waves/CU {bpc}: {sec * 1e6:.1f} us")
+                print(f"waves/CU {bpc}: {sec * 1e6:.1f} us")
+    results = [(bpc, sec) for bpc, sec in best_sec.items() if sec is not None]
     results.sort(key=lambda r: r[1])
     best = results[0][0]
     ctx.set_chi2_tuning(best)
